@@ -1,0 +1,193 @@
+/*
+ * cheb.h - C ABI of the MI355X (gfx950) Chebyshev-collocation diffusion solver.
+ *
+ * Problem (Section 2, 3-D extension; Section 3.3 flux form):
+ *     div(K(x) grad u) = f   in the box  prod_a [lo_a, hi_a],
+ *     per face either u = g (Dirichlet) or du/dn = g (Neumann, outward normal),
+ * discretised by collocation at the tensor Chebyshev-Gauss-Lobatto (CGL) nodes:
+ * the PDE holds at interior nodes, one boundary-condition row holds at every
+ * boundary node (Section 2.3.1).  The discrete operator is applied matrix-free
+ * (Algorithm 3): per axis a DCT-I of every pencil (the FFT of its even
+ * extension), the derivative-coefficient recurrence, the back-transform, the
+ * pointwise flux K * du/dx_a, and the same three steps again for the
+ * divergence.  Boundary conditions are eliminated (Section 2.3.1) and the
+ * reduced system is solved by LGMRES (Algorithm 2); hierarchical refinement
+ * prolongs a coarse solution by zero-padding its Chebyshev coefficients
+ * (Section 2.3.3, Algorithm 4).
+ *
+ * Conventions for every call:
+ *   - Field arrays are device pointers to C-contiguous [i][j][k] arrays of
+ *     n[0] x n[1] x n[2] values (i along x, slowest; k along z, fastest), in the
+ *     plan's precision (double for CHEB_F64 and CHEB_MIXED, float for CHEB_F32).
+ *   - Node coordinates along axis a are ascending:
+ *         x_j = (lo+hi)/2 - (hi-lo)/2 * cos(pi j / N_a),  N_a = n[a] - 1.
+ *   - Faces are numbered 0..5 = x_lo, x_hi, y_lo, y_hi, z_lo, z_hi.  Face data
+ *     (g_faces) are packed face after face; the array of face f on axis a has
+ *     shape (n[b], n[c]) with b < c the two other axes.
+ *   - Neumann data are the outward normal derivative du/dn (not the flux).
+ *   - Edge and corner nodes (on several faces) carry exactly one equation: the
+ *     Dirichlet face of lowest axis if one contains the node, otherwise the
+ *     Neumann face of lowest axis.  (The paper is silent on this; the interior
+ *     solution does not depend on the choice.)
+ *   - All calls are asynchronous on the plan's HIP stream unless stated; the
+ *     caller keeps every buffer alive until the stream has finished with it.
+ *   - The caller owns all field buffers and the workspace; the plan owns only a
+ *     few kilobytes of device constants allocated at creation.
+ *   - Errors are return codes, never exceptions.  0 = success; negative = hard
+ *     error, outputs untouched; positive = soft status with valid outputs.
+ *     cheb_last_error() gives a thread-local message for the last failure.
+ *   - A plan is not re-entrant: use it from one host thread at a time.
+ */
+#ifndef CHEB_H_
+#define CHEB_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CHEB_OK 0
+#define CHEB_NOT_CONVERGED 1     /* iterative solve stopped at maxiter; best iterate returned */
+#define CHEB_STAGNATED 2         /* refinement stopped contracting; best iterate returned */
+#define CHEB_ERR_INVALID_ARG (-1)
+#define CHEB_ERR_SINGULAR_BC (-2) /* all six faces Neumann: solution defined up to a constant */
+#define CHEB_ERR_BAD_INPUT (-3)   /* NaN/Inf or non-positive conductivity */
+#define CHEB_ERR_DEVICE (-4)      /* HIP runtime error */
+#define CHEB_ERR_WORKSPACE (-5)   /* workspace missing or too small */
+#define CHEB_ERR_UNSUPPORTED (-6)
+
+/* precision */
+#define CHEB_F64 0   /* everything in FP64 */
+#define CHEB_F32 1   /* everything in FP32 (fields are float) */
+#define CHEB_MIXED 2 /* FP64 fields and outer refinement, FP32 transforms and inner Krylov */
+
+/* face types */
+#define CHEB_DIRICHLET 0
+#define CHEB_NEUMANN 1
+
+/* cheb_apply flags */
+#define CHEB_APPLY_FULL 0u      /* y = A u: interior rows sum_a D_a(K D_a u), boundary rows B u */
+#define CHEB_APPLY_REDUCED 1u   /* y = (A_kk + A_kr G) u_k on interior nodes, 0 on boundary nodes */
+#define CHEB_APPLY_TRANSPOSE 2u /* with REDUCED: y = (A_kk + A_kr G)^T u_k */
+
+typedef struct cheb_grid {
+  int32_t n[3];  /* nodes per axis, 3 <= n <= 513 */
+  double lo[3];  /* box lower corner */
+  double hi[3];  /* box upper corner, hi > lo */
+  int32_t bc[6]; /* CHEB_DIRICHLET or CHEB_NEUMANN per face */
+} cheb_grid;
+
+typedef struct cheb_solve_opts {
+  double rtol;           /* stop when ||r|| <= max(rtol * ||b||, atol) (reduced system) */
+  double atol;
+  int32_t maxiter;       /* maximum operator applications (0 = 10000) */
+  int32_t inner_m;       /* LGMRES Krylov dimension per restart cycle (0 = 30) */
+  int32_t outer_k;       /* LGMRES augmentation vectors (0 = 3, negative = none, max 6) */
+  double ir_inner_rtol;  /* MIXED: relative tolerance of each FP32 inner solve (0 = 1e-4) */
+  int32_t ir_max_outer;  /* MIXED: maximum FP64 refinement steps (0 = 50) */
+  int32_t flags;         /* bit 0: use the initial guess in u_inout (else start from 0) */
+  double* history;       /* optional host array receiving the relative residual per restart / IR step */
+  int32_t history_len;
+  int32_t reserved[3];
+} cheb_solve_opts;
+
+typedef struct cheb_solve_info {
+  int32_t status;        /* CHEB_OK / CHEB_NOT_CONVERGED / CHEB_STAGNATED */
+  int32_t matvecs;       /* operator applications, FP64 + FP32 */
+  int32_t matvecs_f32;   /* of which in FP32 */
+  int32_t restarts;      /* LGMRES restart cycles */
+  int32_t ir_steps;      /* refinement steps (MIXED) */
+  int32_t history_used;
+  double relres_final;   /* ||b - A x|| / ||b||, recomputed in FP64 at the end */
+  double seconds;        /* host wall time of the call */
+} cheb_solve_info;
+
+typedef struct cheb_plan cheb_plan;
+
+/* Create a plan for one grid.  Validates n (3..513), lo < hi, bc values, and
+ * rejects all-Neumann problems with CHEB_ERR_SINGULAR_BC.  `stream` is a
+ * hipStream_t (NULL = default stream).  Allocates a few KB of device constants
+ * (boundary rows of the differentiation matrix). */
+int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, cheb_plan** out);
+
+/* Bytes of device workspace needed by cheb_solve / cheb_adjoint / cheb_picard
+ * with these options (opts may be NULL for defaults). */
+int cheb_plan_workspace_bytes(const cheb_plan* plan, const cheb_solve_opts* opts, size_t* bytes);
+
+/* Give the plan a caller-owned device workspace (256-byte aligned).  The plan
+ * never allocates device memory on the solve path. */
+int cheb_plan_set_workspace(cheb_plan* plan, void* dev_ptr, size_t bytes);
+
+/* Change the stream subsequent calls enqueue on. */
+int cheb_plan_set_stream(cheb_plan* plan, void* stream);
+
+int cheb_plan_destroy(cheb_plan* plan);
+
+/* Operator application (Algorithm 3 with the rows of Section 2.3.1).
+ *   K : conductivity at every node (> 0), u : input field, y : output field
+ *   (y must not alias u or K).  flags: CHEB_APPLY_FULL, CHEB_APPLY_REDUCED or
+ *   CHEB_APPLY_REDUCED|CHEB_APPLY_TRANSPOSE.  In REDUCED modes boundary entries
+ *   of u are ignored and boundary entries of y are set to 0.  Asynchronous.
+ *   Needs no workspace. */
+int cheb_apply(cheb_plan* plan, const void* K, const void* u, void* y, uint32_t flags);
+
+/* Solve div(K grad u) = f with face data g (Algorithm 2): build the reduced
+ * right-hand side f_k - A_kr H g, run LGMRES on the reduced operator (MIXED:
+ * FP32 LGMRES inside FP64 iterative refinement), reconstruct the boundary
+ * values x_r = G x_k + H g.  u_inout: on entry the initial guess if opts->flags
+ * bit 0 is set (its boundary values are ignored), on exit the full nodal
+ * solution.  g_faces: device array of packed face data (double; float for
+ * CHEB_F32).  f: source at every node (boundary entries ignored).  Requires the
+ * workspace.  Synchronises the plan's stream before returning. */
+int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_faces, void* u_inout,
+               const cheb_solve_opts* opts, cheb_solve_info* info);
+
+/* Modal prolongation (Section 2.3.3): u_f = the coarse interpolant evaluated at
+ * the fine CGL nodes, i.e. DCT-I of u_c along each axis, zero-padding of the
+ * coefficients to the fine size, back-transform.  Fine sizes must be >= coarse
+ * sizes and both plans must describe the same box and precision.  If
+ * u_f_solved is not NULL, also returns e_ref = ||u_f_solved - u_f|| / ||u_f_solved||
+ * (Section 2.3.3 refinement indicator) in *e_ref (synchronises the stream).
+ * Uses the fine plan's stream and workspace. */
+int cheb_prolong(const cheb_plan* coarse, const cheb_plan* fine, const void* u_c, void* u_f,
+                 const void* u_f_solved, double* e_ref);
+
+/* Adjoint sensitivity: given the converged state u of cheb_solve for K and
+ * dL/du at every node, solves A^T lambda = dL/du through the reduced transpose
+ * (interior rows: (A_kk + A_kr G)^T lambda_k = r_k + G^T r_r) and writes
+ *   dLdlogK_j = -K_j sum_a (D_a u)_j (D_a^T lambda~)_j,
+ * lambda~ = lambda on interior rows and 0 on boundary rows.  lambda receives
+ * lambda~.  FP64 or MIXED plans only.  Requires the workspace; synchronises. */
+int cheb_adjoint(cheb_plan* plan, const void* K, const void* u, const void* dLdu, void* lambda,
+                 void* dLdlogK, const cheb_solve_opts* opts, cheb_solve_info* info);
+
+/* Lagged-coefficient (Picard) iteration for K(x,u) = K0(x) (1 + u^2/2)
+ * (Section 2.3, Picard form): K_m = K0 (1 + u_m^2/2), solve, until
+ * ||u_{m+1} - u_m|| / ||u_{m+1}|| <= picard_tol or max_steps.  u_inout as in
+ * cheb_solve (bit 0 of opts->flags selects the warm start).  Kwork: caller
+ * device array of one field for the current coefficient.  *steps receives the
+ * number of Picard steps.  Synchronises. */
+int cheb_picard(cheb_plan* plan, const void* K0, const void* f, const void* g_faces, void* u_inout,
+                void* Kwork, double picard_tol, int32_t max_steps, const cheb_solve_opts* opts,
+                cheb_solve_info* info, int32_t* steps);
+
+/* Derivative along one axis, D_a u at every node (first half of an axis pass).
+ * Asynchronous. */
+int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis);
+
+/* Clenshaw-Curtis volume averages <K du/dx_b>, b = 0,1,2, written to host
+ * out[3] (Section 3.3 effective conductivity: K_num = <K du/dx_a> / G).
+ * Uses 4 fields of workspace.  Synchronises. */
+int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[3]);
+
+const char* cheb_status_string(int status);
+const char* cheb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEB_H_ */

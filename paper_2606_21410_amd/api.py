@@ -1,0 +1,238 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only).
+
+PyTorch provides device memory and the stream; every step of the solver runs in
+the HIP kernels of libchebfft.so.  Names follow the C calls: ``Plan.apply`` is
+``cheb_apply``, ``Plan.solve`` is ``cheb_solve`` and so on.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_PREC = {"f64": L.CHEB_F64, "f32": L.CHEB_F32, "mixed": L.CHEB_MIXED}
+_MODE = {"full": L.CHEB_APPLY_FULL, "reduced": L.CHEB_APPLY_REDUCED,
+         "transpose": L.CHEB_APPLY_REDUCED | L.CHEB_APPLY_TRANSPOSE}
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+@dataclass
+class SolveOptions:
+    rtol: float = 1e-10
+    atol: float = 0.0
+    maxiter: int = 10000
+    inner_m: int = 30
+    outer_k: int = 3
+    ir_inner_rtol: float = 1e-4
+    ir_max_outer: int = 50
+    history_len: int = 0
+
+    def to_c(self, warm: bool):
+        o = L.cheb_solve_opts()
+        o.rtol, o.atol, o.maxiter = self.rtol, self.atol, self.maxiter
+        o.inner_m, o.outer_k = self.inner_m, (self.outer_k if self.outer_k > 0 else -1)
+        o.ir_inner_rtol, o.ir_max_outer = self.ir_inner_rtol, self.ir_max_outer
+        o.flags = 1 if warm else 0
+        hist = None
+        if self.history_len > 0:
+            hist = (ctypes.c_double * self.history_len)()
+            o.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+            o.history_len = self.history_len
+        return o, hist
+
+
+class Plan:
+    """One grid: sizes, box, face types, precision ('f64', 'f32', 'mixed')."""
+
+    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0,) * 6, precision="f64",
+                 device="cuda"):
+        self.lib = L.load()
+        self.n = tuple(int(v) for v in n)
+        self.lo = tuple(float(v) for v in lo)
+        self.hi = tuple(float(v) for v in hi)
+        self.bc = tuple(int(v) for v in bc)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if precision == "f32" else torch.float64
+        g = L.cheb_grid()
+        for a in range(3):
+            g.n[a], g.lo[a], g.hi[a] = self.n[a], self.lo[a], self.hi[a]
+        for f in range(6):
+            g.bc[f] = self.bc[f]
+        self._h = ctypes.c_void_p()
+        stream = _stream_handle(self.device) if self.device.type == "cuda" else 0
+        L.check(self.lib.cheb_plan_create(ctypes.byref(g), _PREC[precision], ctypes.c_void_p(stream),
+                                          ctypes.byref(self._h)))
+        self._ws = None
+        self._ws_bytes = 0
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.cheb_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _sync_stream(self):
+        self.lib.cheb_plan_set_stream(self._h, ctypes.c_void_p(_stream_handle(self.device)))
+
+    def _field(self, t: torch.Tensor, name: str, dtype=None):
+        dtype = dtype or self.dtype
+        if t.device != self.device and not (t.device.type == self.device.type):
+            raise ValueError(f"{name}: expected a tensor on {self.device}")
+        if t.dtype != dtype or tuple(t.shape) != self.n or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous {dtype} tensor of shape {self.n}, got "
+                             f"{t.dtype} {tuple(t.shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def face_count(self):
+        n = self.n
+        return 2 * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1])
+
+    def workspace_bytes(self, opts: SolveOptions | None = None) -> int:
+        o, _ = (opts or SolveOptions()).to_c(False)
+        b = ctypes.c_size_t()
+        L.check(self.lib.cheb_plan_workspace_bytes(self._h, ctypes.byref(o), ctypes.byref(b)))
+        return int(b.value)
+
+    def ensure_workspace(self, opts: SolveOptions | None = None):
+        need = self.workspace_bytes(opts)
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws_bytes = need
+            L.check(self.lib.cheb_plan_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()),
+                                                     ctypes.c_size_t(need)))
+        return self._ws
+
+    # --- calls -------------------------------------------------------------
+    def apply(self, K, u, y=None, mode: str = "full"):
+        self._sync_stream()
+        if y is None:
+            y = torch.empty_like(u)
+        L.check(self.lib.cheb_apply(self._h, self._field(K, "K"), self._field(u, "u"), self._field(y, "y"),
+                                    _MODE[mode]))
+        return y
+
+    def derivative(self, u, axis: int, out=None):
+        self._sync_stream()
+        if out is None:
+            out = torch.empty_like(u)
+        L.check(self.lib.cheb_derivative(self._h, self._field(u, "u"), self._field(out, "du"), int(axis)))
+        return out
+
+    def solve(self, K, f, g, u0=None, opts: SolveOptions | None = None, out=None):
+        opts = opts or SolveOptions()
+        self._sync_stream()
+        self.ensure_workspace(opts)
+        if out is None:
+            out = torch.zeros(self.n, dtype=self.dtype, device=self.device)
+        if u0 is not None:
+            out.copy_(u0)
+        gdt = self.dtype
+        if g.dtype != gdt or g.numel() != self.face_count() or not g.is_contiguous():
+            raise ValueError("g: packed face data of the plan's dtype expected")
+        o, hist = opts.to_c(u0 is not None)
+        info = L.cheb_solve_info()
+        rc = L.check(self.lib.cheb_solve(self._h, self._field(K, "K"), self._field(f, "f"),
+                                         ctypes.c_void_p(g.data_ptr()), self._field(out, "u"),
+                                         ctypes.byref(o), ctypes.byref(info)))
+        d = info.as_dict()
+        d["rc"] = rc
+        if hist is not None:
+            d["history"] = [hist[i] for i in range(info.history_used)]
+        return out, d
+
+    def adjoint(self, K, u, dLdu, opts: SolveOptions | None = None):
+        opts = opts or SolveOptions()
+        self._sync_stream()
+        self.ensure_workspace(opts)
+        lam = torch.empty_like(u)
+        grad = torch.empty_like(u)
+        o, _ = opts.to_c(False)
+        info = L.cheb_solve_info()
+        rc = L.check(self.lib.cheb_adjoint(self._h, self._field(K, "K"), self._field(u, "u"),
+                                           self._field(dLdu, "dLdu"), self._field(lam, "lambda"),
+                                           self._field(grad, "dLdlogK"), ctypes.byref(o),
+                                           ctypes.byref(info)))
+        d = info.as_dict()
+        d["rc"] = rc
+        return lam, grad, d
+
+    def picard(self, K0, f, g, u0=None, tol=1e-10, max_steps=50, opts: SolveOptions | None = None):
+        opts = opts or SolveOptions()
+        self._sync_stream()
+        self.ensure_workspace(opts)
+        u = torch.zeros(self.n, dtype=self.dtype, device=self.device)
+        if u0 is not None:
+            u.copy_(u0)
+        Kw = torch.empty_like(u)
+        o, hist = opts.to_c(u0 is not None)
+        info = L.cheb_solve_info()
+        steps = ctypes.c_int32()
+        rc = L.check(self.lib.cheb_picard(self._h, self._field(K0, "K0"), self._field(f, "f"),
+                                          ctypes.c_void_p(g.data_ptr()), self._field(u, "u"),
+                                          self._field(Kw, "Kwork"), float(tol), int(max_steps),
+                                          ctypes.byref(o), ctypes.byref(info), ctypes.byref(steps)))
+        d = info.as_dict()
+        d["rc"] = rc
+        d["picard_steps"] = steps.value
+        if hist is not None:
+            d["history"] = [hist[i] for i in range(min(steps.value, opts.history_len))]
+        return u, d
+
+    def flux_average(self, K, u):
+        self._sync_stream()
+        self.ensure_workspace()
+        out = (ctypes.c_double * 3)()
+        L.check(self.lib.cheb_flux_average(self._h, self._field(K, "K"), self._field(u, "u"), out))
+        return [out[0], out[1], out[2]]
+
+
+def prolong(coarse: Plan, fine: Plan, uc, uf=None, uf_solved=None):
+    """Zero-padding prolongation of uc (coarse grid) onto the fine grid; with
+    uf_solved also returns e_ref."""
+    fine._sync_stream()
+    fine.ensure_workspace()
+    if uf is None:
+        uf = torch.empty(fine.n, dtype=fine.dtype, device=fine.device)
+    e = ctypes.c_double(float("nan"))
+    L.check(fine.lib.cheb_prolong(coarse.handle, fine.handle, coarse._field(uc, "u_c"), fine._field(uf, "u_f"),
+                                  fine._field(uf_solved, "u_f_solved") if uf_solved is not None else None,
+                                  ctypes.byref(e) if uf_solved is not None else None))
+    return uf, (e.value if uf_solved is not None else None)
+
+
+class ChebSolveFn(torch.autograd.Function):
+    """u = solve(K = exp(logK)); backward: dL/dlogK through cheb_adjoint."""
+
+    @staticmethod
+    def forward(ctx, logK, plan: Plan, f, g, opts):
+        K = torch.exp(logK).contiguous()
+        u, _ = plan.solve(K, f, g, opts=opts)
+        ctx.plan, ctx.opts = plan, opts
+        ctx.save_for_backward(K, u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        K, u = ctx.saved_tensors
+        _, grad, _ = ctx.plan.adjoint(K, u, grad_u.contiguous(), ctx.opts)
+        return grad, None, None, None, None
+
+
+def solve_logk(plan: Plan, logK, f, g, opts: SolveOptions | None = None):
+    return ChebSolveFn.apply(logK, plan, f, g, opts or SolveOptions())

@@ -1,0 +1,286 @@
+// C ABI: plans, operator application, derivatives, volume averages, status.
+// The solver entry points live in solver.hip, prolongation in prolong.hip.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "pencil.h"
+
+namespace cheb {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return CHEB_OK;
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return CHEB_ERR_DEVICE;
+}
+
+namespace {
+
+// Boundary rows of the ascending, scaled differentiation matrix, from the
+// closed forms of the endpoint rows of the CGL differentiation matrix
+// (descending nodes: D_00 = (2N^2+1)/6, D_0j = (-1)^j / sin^2(pi j / 2N),
+// D_0N = (-1)^N / 2; ascending order negates, and row N follows from the
+// centro-antisymmetry).
+void boundary_rows(int N, double L, std::vector<double>& r0, std::vector<double>& rN) {
+  r0.assign(N + 1, 0.0);
+  rN.assign(N + 1, 0.0);
+  const double s = 2.0 / L;
+  const double corner = (2.0 * N * N + 1.0) / 6.0;
+  const double half = (N % 2 == 0) ? 0.5 : -0.5;  // (-1)^N / 2
+  for (int j = 1; j < N; ++j) {
+    const double sj = std::sin(M_PI * j / (2.0 * N));
+    const double dj = ((j % 2 == 0) ? 1.0 : -1.0) / (sj * sj);  // descending D_0j
+    const int k = N - j;
+    const double sk = std::sin(M_PI * k / (2.0 * N));
+    const double dk = ((k % 2 == 0) ? 1.0 : -1.0) / (sk * sk);  // descending D_0k
+    r0[j] = -dj * s;
+    rN[j] = dk * s;
+  }
+  r0[0] = -corner * s;
+  r0[N] = -half * s;
+  rN[0] = half * s;
+  rN[N] = corner * s;
+}
+
+// Clenshaw-Curtis weights on [0, L] (closed form, Waldvogel / Trefethen).
+void cc_weights(int N, double L, std::vector<double>& w) {
+  w.assign(N + 1, 0.0);
+  std::vector<double> v(N + 1, 1.0);
+  const bool even = (N % 2 == 0);
+  const double wend = even ? 1.0 / (double(N) * N - 1.0) : 1.0 / (double(N) * N);
+  for (int j = 1; j < N; ++j) {
+    const double th = M_PI * j / N;
+    double t = 1.0;
+    const int kmax = even ? N / 2 - 1 : (N - 1) / 2;
+    for (int k = 1; k <= kmax; ++k) t -= 2.0 * std::cos(2.0 * k * th) / (4.0 * k * k - 1.0);
+    if (even) t -= std::cos(N * th) / (double(N) * N - 1.0);
+    w[j] = 2.0 * t / N;
+  }
+  w[0] = w[N] = wend;
+  for (double& x : w) x *= L / 2.0;
+}
+
+}  // namespace
+}  // namespace cheb
+
+using namespace cheb;
+
+extern "C" {
+
+const char* cheb_last_error(void) { return g_last_error.c_str(); }
+
+const char* cheb_status_string(int status) {
+  switch (status) {
+    case CHEB_OK: return "ok";
+    case CHEB_NOT_CONVERGED: return "not converged";
+    case CHEB_STAGNATED: return "stagnated";
+    case CHEB_ERR_INVALID_ARG: return "invalid argument";
+    case CHEB_ERR_SINGULAR_BC: return "singular boundary conditions (all faces Neumann)";
+    case CHEB_ERR_BAD_INPUT: return "bad input (NaN/Inf or non-positive conductivity)";
+    case CHEB_ERR_DEVICE: return "device error";
+    case CHEB_ERR_WORKSPACE: return "workspace missing or too small";
+    case CHEB_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, cheb_plan** out) {
+  if (!grid || !out) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  for (int a = 0; a < 3; ++a) {
+    if (grid->n[a] < 3 || grid->n[a] > 513) {
+      set_error("grid size must be in [3, 513] on every axis");
+      return CHEB_ERR_INVALID_ARG;
+    }
+    if (!(grid->hi[a] > grid->lo[a]) || !std::isfinite(grid->lo[a]) || !std::isfinite(grid->hi[a])) {
+      set_error("need finite lo < hi on every axis");
+      return CHEB_ERR_INVALID_ARG;
+    }
+  }
+  bool allN = true;
+  for (int f = 0; f < 6; ++f) {
+    if (grid->bc[f] != CHEB_DIRICHLET && grid->bc[f] != CHEB_NEUMANN) {
+      set_error("face type must be CHEB_DIRICHLET or CHEB_NEUMANN");
+      return CHEB_ERR_INVALID_ARG;
+    }
+    allN = allN && grid->bc[f] == CHEB_NEUMANN;
+  }
+  if (allN) {
+    set_error("all six faces Neumann: the problem is singular");
+    return CHEB_ERR_SINGULAR_BC;
+  }
+  if (precision != CHEB_F64 && precision != CHEB_F32 && precision != CHEB_MIXED) {
+    set_error("precision must be CHEB_F64, CHEB_F32 or CHEB_MIXED");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  cheb_plan* p = new (std::nothrow) cheb_plan();
+  if (!p) {
+    set_error("out of host memory");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  std::memset((void*)p, 0, sizeof(cheb_plan));
+  p->g = *grid;
+  p->prec = precision;
+  p->stream = (hipStream_t)stream;
+  p->npts = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+  size_t nmax = 0;
+  for (int a = 0; a < 3; ++a) {
+    AxisConst& c = p->ax[a];
+    c.N = grid->n[a] - 1;
+    c.L = grid->hi[a] - grid->lo[a];
+    c.cscale = -1.0 / (double(c.N) * c.L);
+    if ((size_t)grid->n[a] > nmax) nmax = grid->n[a];
+  }
+  p->dconst_stride = round_up(nmax, 64);
+  const size_t cnt = 9 * p->dconst_stride;
+  std::vector<double> h64(cnt, 0.0);
+  std::vector<float> h32(cnt, 0.0f);
+  for (int a = 0; a < 3; ++a) {
+    AxisConst& c = p->ax[a];
+    std::vector<double> r0, rN, w;
+    boundary_rows(c.N, c.L, r0, rN);
+    cc_weights(c.N, c.L, w);
+    c.m00 = r0[0];
+    c.m0N = r0[c.N];
+    c.mN0 = rN[0];
+    c.mNN = rN[c.N];
+    for (int j = 0; j <= c.N; ++j) {
+      h64[(3 * a + 0) * p->dconst_stride + j] = r0[j];
+      h64[(3 * a + 1) * p->dconst_stride + j] = rN[j];
+      h64[(3 * a + 2) * p->dconst_stride + j] = w[j];
+    }
+  }
+  for (size_t i = 0; i < cnt; ++i) h32[i] = float(h64[i]);
+  int rc = hip_check(hipMalloc((void**)&p->dconst64, cnt * sizeof(double)), "hipMalloc(plan constants)");
+  if (!rc) rc = hip_check(hipMalloc((void**)&p->dconst32, cnt * sizeof(float)), "hipMalloc(plan constants)");
+  if (!rc)
+    rc = hip_check(hipMemcpy(p->dconst64, h64.data(), cnt * sizeof(double), hipMemcpyHostToDevice),
+                   "hipMemcpy(plan constants)");
+  if (!rc)
+    rc = hip_check(hipMemcpy(p->dconst32, h32.data(), cnt * sizeof(float), hipMemcpyHostToDevice),
+                   "hipMemcpy(plan constants)");
+  p->hpinned_len = 4096;
+  if (!rc)
+    rc = hip_check(hipHostMalloc((void**)&p->hpinned, p->hpinned_len * sizeof(double), hipHostMallocDefault),
+                   "hipHostMalloc");
+  if (rc) {
+    if (p->dconst64) (void)hipFree(p->dconst64);
+    if (p->dconst32) (void)hipFree(p->dconst32);
+    if (p->hpinned) (void)hipHostFree(p->hpinned);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return CHEB_OK;
+}
+
+int cheb_plan_set_workspace(cheb_plan* plan, void* dev_ptr, size_t bytes) {
+  if (!plan) {
+    set_error("null plan");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (dev_ptr && ((uintptr_t)dev_ptr % 256) != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return CHEB_ERR_WORKSPACE;
+  }
+  plan->ws = dev_ptr;
+  plan->ws_bytes = dev_ptr ? bytes : 0;
+  return CHEB_OK;
+}
+
+int cheb_plan_set_stream(cheb_plan* plan, void* stream) {
+  if (!plan) {
+    set_error("null plan");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  plan->stream = (hipStream_t)stream;
+  return CHEB_OK;
+}
+
+int cheb_plan_destroy(cheb_plan* plan) {
+  if (!plan) return CHEB_OK;
+  if (plan->dconst64) (void)hipFree(plan->dconst64);
+  if (plan->dconst32) (void)hipFree(plan->dconst32);
+  if (plan->hpinned) (void)hipHostFree(plan->hpinned);
+  delete plan;
+  return CHEB_OK;
+}
+
+int cheb_apply(cheb_plan* plan, const void* K, const void* u, void* y, uint32_t flags) {
+  if (!plan || !K || !u || !y) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (y == u || y == K) {
+    set_error("output must not alias the input");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  int mode;
+  if (flags == CHEB_APPLY_FULL) mode = 0;
+  else if (flags == CHEB_APPLY_REDUCED) mode = 1;
+  else if (flags == (CHEB_APPLY_REDUCED | CHEB_APPLY_TRANSPOSE)) mode = 2;
+  else {
+    set_error("flags must be FULL, REDUCED or REDUCED|TRANSPOSE");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (plan->prec == CHEB_F32)
+    return apply_t<float>(plan, (const float*)K, (const float*)u, (float*)y, mode, plan->stream);
+  return apply_t<double>(plan, (const double*)K, (const double*)u, (double*)y, mode, plan->stream);
+}
+
+int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis) {
+  if (!plan || !u || !du || axis < 0 || axis > 2 || u == du) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (plan->prec == CHEB_F32)
+    return launch_axis_pass<float>(plan, axis, 3, 1, nullptr, (const float*)u, (float*)du, plan->stream);
+  return launch_axis_pass<double>(plan, axis, 3, 1, nullptr, (const double*)u, (double*)du, plan->stream);
+}
+
+int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[3]) {
+  if (!plan || !K || !u || !out) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (plan->prec == CHEB_F32) {
+    set_error("flux average needs an FP64 or MIXED plan");
+    return CHEB_ERR_UNSUPPORTED;
+  }
+  const size_t fb = round_up(plan->npts * sizeof(double), 256);
+  const size_t pb = round_up(8192 * sizeof(double), 256);
+  if (!plan->ws || plan->ws_bytes < fb + pb) {
+    set_error("flux average needs the workspace");
+    return CHEB_ERR_WORKSPACE;
+  }
+  double* du = (double*)plan->ws;
+  double* part = (double*)((char*)plan->ws + fb);
+  double* res = part + 4096;
+  const double vol = (plan->g.hi[0] - plan->g.lo[0]) * (plan->g.hi[1] - plan->g.lo[1]) *
+                     (plan->g.hi[2] - plan->g.lo[2]);
+  for (int b = 0; b < 3; ++b) {
+    int rc = launch_axis_pass<double>(plan, b, 3, 1, nullptr, (const double*)u, du, plan->stream);
+    if (rc) return rc;
+    rc = cc_dot((const double*)K, du, dconst64(plan, 0, 2), dconst64(plan, 1, 2), dconst64(plan, 2, 2),
+                plan->g.n, part, res + b, plan->stream);
+    if (rc) return rc;
+  }
+  int rc = hip_check(hipMemcpyAsync(plan->hpinned, res, 3 * sizeof(double), hipMemcpyDeviceToHost, plan->stream),
+                     "hipMemcpyAsync");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  for (int b = 0; b < 3; ++b) out[b] = plan->hpinned[b] / vol;
+  return CHEB_OK;
+}
+
+}  // extern "C"

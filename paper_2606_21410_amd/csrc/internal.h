@@ -1,0 +1,118 @@
+// Host-side internals of the C ABI: the plan object and the kernel launchers
+// shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/cheb.h"
+
+namespace cheb {
+
+// Per-axis constants of the ascending, affinely scaled differentiation matrix.
+struct AxisConst {
+  int N;
+  double L;
+  double cscale;                 // -1 / (N L)
+  double m00, m0N, mN0, mNN;     // corner entries
+};
+
+void set_error(const std::string& msg);
+int hip_check(hipError_t e, const char* what);
+
+// Workspace carving: fields padded to 256 bytes.
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace cheb
+
+struct cheb_plan {
+  cheb_grid g;
+  int prec;
+  hipStream_t stream;
+  size_t npts;
+  cheb::AxisConst ax[3];
+  // device constants: per axis [row0 | rowN | cc weights], n[a] entries each, f64 then f32
+  double* dconst64;
+  float* dconst32;
+  size_t dconst_stride;  // entries per (axis, row) slot
+  // host-pinned scratch for reductions and small coefficient vectors
+  double* hpinned;
+  size_t hpinned_len;
+  void* ws;
+  size_t ws_bytes;
+  hipEvent_t ev;
+};
+
+namespace cheb {
+
+// device constant pointers (axis a, slot s: 0 = row 0, 1 = row N, 2 = CC weights)
+inline const double* dconst64(const cheb_plan* p, int a, int s) {
+  return p->dconst64 + (size_t)(3 * a + s) * p->dconst_stride;
+}
+inline const float* dconst32(const cheb_plan* p, int a, int s) {
+  return p->dconst32 + (size_t)(3 * a + s) * p->dconst_stride;
+}
+
+// ---- operator passes (pass_f64.hip / pass_f32.hip) ----
+// mode: 0 FULL, 1 REDUCED, 2 TRANSPOSE (reduced), 3 DERIV, 4 DERIV_T
+template <typename T>
+int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T* K, const T* u, T* y,
+                     hipStream_t s);
+
+// full apply (z, y, x passes) in precision T
+template <typename T>
+int apply_t(const cheb_plan* p, const T* K, const T* u, T* y, int mode, hipStream_t s);
+
+// ---- vector kernels (blas.hip) ----
+size_t multidot_partials_len(size_t npts, int nv);
+// out[i] = <V_i, w> for i < nv, out[nv] = <w, w>  (double accumulation)
+template <typename T>
+int multidot(const T* V, size_t ld, int nv, const T* w, size_t npts, double* partials, double* out,
+             hipStream_t s);
+// out = (w - sum_i h_i V_i) * scale   (h on device, nv entries; out may alias w)
+template <typename T>
+int update_scale(const T* V, size_t ld, int nv, const double* h, const T* w, T* out, double scale,
+                 size_t npts, hipStream_t s);
+// out (+)= sum_i c_i V_i  (c on device)
+template <typename T>
+int lincomb(const T* V, size_t ld, int nv, const double* c, T* out, int accumulate, size_t npts,
+            hipStream_t s);
+template <typename T>
+int axpby(T* y, const T* x, double alpha, double beta, size_t npts, hipStream_t s);  // y = alpha x + beta y
+template <typename T>
+int copy_scale(T* y, const T* x, double alpha, size_t npts, hipStream_t s);  // y = alpha x
+int cast_f64_f32(float* y, const double* x, double alpha, size_t npts, hipStream_t s);
+int add_f32_to_f64(double* y, const float* x, double alpha, size_t npts, hipStream_t s);  // y += alpha x
+template <typename T>
+int fill(T* y, double v, size_t npts, hipStream_t s);
+// y = (f - y) on interior nodes, 0 on boundary nodes
+template <typename T>
+int rhs_reduced(T* y, const T* f, const int* n, hipStream_t s);
+template <typename T>
+int mask_interior(T* y, const int* n, hipStream_t s);
+// K-dependent pointwise kernels
+int picard_coeff(double* K, const double* K0, const double* u, size_t npts, hipStream_t s);
+int grad_accumulate(double* g, const double* du, const double* dl, int first, size_t npts,
+                    hipStream_t s);
+int grad_finish(double* g, const double* K, size_t npts, hipStream_t s);
+int check_positive_finite(const double* K, size_t npts, int* dflag, hipStream_t s);
+int check_positive_finite_f32(const float* K, size_t npts, int* dflag, hipStream_t s);
+// weighted sum  sum_ijk wx_i wy_j wz_k a_ijk b_ijk  -> partial sums, reduced into out[0]
+int cc_dot(const double* a, const double* b, const double* wx, const double* wy, const double* wz,
+           const int* n, double* partials, double* out, hipStream_t s);
+
+// ---- lift kernels (lift.hip) ----
+template <typename T>
+int lift_full(const cheb_plan* p, T* U, const T* g_faces, hipStream_t s);     // x_r = G x_k + H g
+template <typename T>
+int lift_transpose(const cheb_plan* p, T* W, hipStream_t s);                  // W <- lift^T W (interior)
+
+// ---- prolongation (prolong.hip) ----
+template <typename T>
+int prolong_t(const cheb_plan* pc, const cheb_plan* pf, const T* uc, T* uf, T* tmp1, T* tmp2,
+              hipStream_t s);
+
+}  // namespace cheb

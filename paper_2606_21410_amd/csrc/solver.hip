@@ -1,0 +1,704 @@
+// Solvers behind the C ABI: LGMRES on the reduced system (Algorithm 2), FP32
+// LGMRES inside FP64 iterative refinement, the adjoint solve and gradient, and
+// the Picard loop.  All arithmetic on fields runs in device kernels; the host
+// keeps the (m+k+1) x (m+k) Hessenberg matrix and its Givens rotations in FP64.
+//
+// LGMRES (Baker, Jessup & Manteuffel, SIAM J. Matrix Anal. Appl. 26(4), 2005):
+// each restart cycle builds an Arnoldi basis from the residual and then
+// continues the Arnoldi process with the k most recent corrections
+// z_i = x_i - x_{i-1} as extra search directions; the update is the
+// least-squares minimiser over that augmented space.  Orthogonalisation is
+// classical Gram-Schmidt in one pass: the multi-dot returns <v_i, w> and <w, w>
+// together; ||w - V h||^2 = ||w||^2 - ||h||^2, and a second pass runs when
+// that difference signals cancellation (||w_new|| < ||w|| / sqrt(2)).
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace cheb {
+
+namespace {
+
+struct Carver {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += round_up(count * sizeof(T), 256);
+    return p;
+  }
+};
+
+struct SolveParams {
+  double rtol, atol;
+  int maxiter, m, k;
+  double ir_rtol;
+  int ir_max;
+  bool warm;
+  double* hist;
+  int hist_len;
+};
+
+SolveParams params_from(const cheb_solve_opts* o) {
+  SolveParams s;
+  s.rtol = (o && o->rtol > 0) ? o->rtol : 1e-10;
+  s.atol = (o && o->atol > 0) ? o->atol : 0.0;
+  s.maxiter = (o && o->maxiter > 0) ? o->maxiter : 10000;
+  s.m = (o && o->inner_m > 0) ? o->inner_m : 30;
+  s.k = !o || o->outer_k == 0 ? 3 : (o->outer_k < 0 ? 0 : o->outer_k);
+  s.ir_rtol = (o && o->ir_inner_rtol > 0) ? o->ir_inner_rtol : 1e-4;
+  s.ir_max = (o && o->ir_max_outer > 0) ? o->ir_max_outer : 50;
+  s.warm = o && (o->flags & 1);
+  s.hist = o ? o->history : nullptr;
+  s.hist_len = o ? o->history_len : 0;
+  return s;
+}
+
+template <typename T>
+struct KrylovWS {
+  T* V = nullptr;  // m + k + 1 basis vectors
+  T* Z = nullptr;  // k augmentation vectors
+  T* w = nullptr;  // work vector
+  size_t ld = 0;   // elements between vectors
+  int m = 0, k = 0;
+};
+
+struct Scratch {
+  double* partials = nullptr;
+  double* dots = nullptr;   // device, 2 x 80
+  double* coef = nullptr;   // device, 80
+  int* flag = nullptr;
+};
+
+template <typename T>
+void carve_krylov(Carver& c, size_t npts, int m, int k, KrylovWS<T>& kw) {
+  kw.ld = round_up(npts * sizeof(T), 256) / sizeof(T);
+  kw.m = m;
+  kw.k = k;
+  kw.V = c.take<T>(kw.ld * (m + k + 1));
+  kw.Z = c.take<T>(kw.ld * (k > 0 ? k : 1));
+  kw.w = c.take<T>(kw.ld);
+}
+
+void carve_scratch(Carver& c, size_t npts, int maxv, Scratch& s) {
+  s.partials = c.take<double>(multidot_partials_len(npts, maxv));
+  s.dots = c.take<double>(160);
+  s.coef = c.take<double>(80);
+  s.flag = c.take<int>(64);
+}
+
+struct Stats {
+  int matvecs = 0;
+  int restarts = 0;
+  int hist_used = 0;
+};
+
+// read back `cnt` doubles from device `src` into the plan's pinned buffer
+int readback(cheb_plan* p, const double* src, int cnt, double* dst, int slot = 0) {
+  double* hp = p->hpinned + slot * 256;
+  int rc = hip_check(hipMemcpyAsync(hp, src, cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream),
+                     "hipMemcpyAsync(D2H)");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  for (int i = 0; i < cnt; ++i) dst[i] = hp[i];
+  return CHEB_OK;
+}
+
+template <typename T>
+int vnorm(cheb_plan* p, const T* v, Scratch& s, double* out) {
+  int rc = multidot<T>(nullptr, 0, 0, v, p->npts, s.partials, s.dots, p->stream);
+  if (rc) return rc;
+  double ww;
+  rc = readback(p, s.dots, 1, &ww);
+  if (rc) return rc;
+  *out = std::sqrt(ww > 0 ? ww : 0.0);
+  return CHEB_OK;
+}
+
+// LGMRES on  A x = b  with absolute tolerance tol_abs on ||b - A x||.
+// Returns CHEB_OK when converged, CHEB_NOT_CONVERGED when maxmv was reached.
+template <typename T, typename ApplyFn>
+int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_abs, int maxmv,
+           KrylovWS<T>& kw, Scratch& sc, Stats& st, double* resid_out, double bnorm, double* hist,
+           int hist_len) {
+  const size_t npts = p->npts;
+  hipStream_t s = p->stream;
+  const int m = kw.m, kmax = kw.k;
+  const int cols = m + kmax;
+  std::vector<double> H((cols + 1) * cols), cs(cols), sn(cols), g(cols + 1), y(cols), dots(cols + 2);
+  auto Hm = [&](int i, int j) -> double& { return H[(size_t)i * cols + j]; };
+  std::vector<int> zslot;  // augmentation vectors, most recent first
+  int zhead = 0;
+  T* w = kw.w;
+  int rc;
+  bool first = true;
+  double beta = 0.0;
+  for (;;) {
+    // true residual r = b - A x  into V_0 (unnormalised)
+    T* v0 = kw.V;
+    if (first && x_zero) {
+      rc = copy_scale<T>(v0, b, 1.0, npts, s);
+    } else {
+      rc = A(x, v0);
+      if (!rc) rc = axpby<T>(v0, b, 1.0, -1.0, npts, s);
+      st.matvecs++;
+    }
+    if (rc) return rc;
+    first = false;
+    rc = vnorm<T>(p, v0, sc, &beta);
+    if (rc) return rc;
+    if (hist && st.hist_used < hist_len) hist[st.hist_used++] = bnorm > 0 ? beta / bnorm : beta;
+    *resid_out = beta;
+    if (!(beta > tol_abs)) return std::isfinite(beta) ? CHEB_OK : CHEB_NOT_CONVERGED;
+    if (st.matvecs >= maxmv) return CHEB_NOT_CONVERGED;
+    rc = copy_scale<T>(v0, v0, 1.0 / beta, npts, s);
+    if (rc) return rc;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    const int jmax = m + (int)zslot.size();
+    int jend = 0;
+    for (int j = 0; j < jmax; ++j) {
+      const T* u = j < m ? kw.V + (size_t)j * kw.ld : kw.Z + (size_t)zslot[j - m] * kw.ld;
+      rc = A(u, w);
+      if (rc) return rc;
+      st.matvecs++;
+      // one-pass classical Gram-Schmidt against v_0..v_j
+      rc = multidot<T>(kw.V, kw.ld, j + 1, w, npts, sc.partials, sc.dots, s);
+      if (rc) return rc;
+      rc = readback(p, sc.dots, j + 2, dots.data());
+      if (rc) return rc;
+      double hh2 = dots[j + 1];
+      for (int i = 0; i <= j; ++i) {
+        Hm(i, j) = dots[i];
+        hh2 -= dots[i] * dots[i];
+      }
+      T* vnext = kw.V + (size_t)(j + 1) * kw.ld;
+      if (!(hh2 > 0.5 * dots[j + 1])) {
+        // cancellation: orthogonalise again
+        rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots, w, w, 1.0, npts, s);
+        if (rc) return rc;
+        rc = multidot<T>(kw.V, kw.ld, j + 1, w, npts, sc.partials, sc.dots + 80, s);
+        if (rc) return rc;
+        rc = readback(p, sc.dots + 80, j + 2, dots.data(), 1);
+        if (rc) return rc;
+        hh2 = dots[j + 1];
+        for (int i = 0; i <= j; ++i) {
+          Hm(i, j) += dots[i];
+          hh2 -= dots[i] * dots[i];
+        }
+        const double hn = hh2 > 0 ? std::sqrt(hh2) : 0.0;
+        if (hn > 0) {
+          rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots + 80, w, vnext, 1.0 / hn, npts, s);
+          if (rc) return rc;
+        }
+        Hm(j + 1, j) = hn;
+      } else {
+        const double hn = std::sqrt(hh2);
+        rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots, w, vnext, 1.0 / hn, npts, s);
+        if (rc) return rc;
+        Hm(j + 1, j) = hn;
+      }
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        const double a = Hm(i, j), bb = Hm(i + 1, j);
+        Hm(i, j) = cs[i] * a + sn[i] * bb;
+        Hm(i + 1, j) = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = Hm(j, j), bb = Hm(j + 1, j);
+      const double r = std::hypot(a, bb);
+      if (r == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = a / r;
+        sn[j] = bb / r;
+      }
+      Hm(j, j) = r;
+      Hm(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      jend = j + 1;
+      const double est = std::fabs(g[j + 1]);
+      const bool breakdown = !(bb > 1e-300) || !(r > 0);
+      if (est <= tol_abs || st.matvecs >= maxmv || breakdown) break;
+    }
+    // y = R^{-1} g
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int l = i + 1; l < jend; ++l) t -= Hm(i, l) * y[l];
+      y[i] = Hm(i, i) != 0.0 ? t / Hm(i, i) : 0.0;
+    }
+    // dx = sum_{i<m} y_i v_i + sum_{i>=m} y_i z_{i-m}  (into w)
+    double* hc = p->hpinned + 2 * 256;
+    for (int i = 0; i < jend; ++i) hc[i] = y[i];
+    rc = hip_check(hipMemcpyAsync(sc.coef, hc, jend * sizeof(double), hipMemcpyHostToDevice, s),
+                   "hipMemcpyAsync(H2D)");
+    if (rc) return rc;
+    const int nv = jend < m ? jend : m;
+    rc = lincomb<T>(kw.V, kw.ld, nv, sc.coef, w, 0, npts, s);
+    if (rc) return rc;
+    for (int i = m; i < jend; ++i) {
+      rc = lincomb<T>(kw.Z + (size_t)zslot[i - m] * kw.ld, kw.ld, 1, sc.coef + i, w, 1, npts, s);
+      if (rc) return rc;
+    }
+    rc = axpby<T>(x, w, 1.0, 1.0, npts, s);
+    if (rc) return rc;
+    if (kmax > 0) {
+      // store the correction as the newest augmentation vector
+      int slot;
+      if ((int)zslot.size() < kmax) {
+        slot = (int)zslot.size();
+      } else {
+        slot = zslot.back();
+        zslot.pop_back();
+      }
+      rc = copy_scale<T>(kw.Z + (size_t)slot * kw.ld, w, 1.0, npts, s);
+      if (rc) return rc;
+      zslot.insert(zslot.begin(), slot);
+      (void)zhead;
+    }
+    // the host coefficient buffer must not be rewritten before the copy ran
+    rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc) return rc;
+    st.restarts++;
+  }
+}
+
+size_t field_bytes(size_t npts, size_t elem) { return round_up(npts * elem, 256); }
+
+// workspace carving for each entry point; base == nullptr gives the size
+struct SolveWS64 {
+  double *bt, *x, *r, *t1, *t2, *t3;
+  KrylovWS<double> kw;
+  Scratch sc;
+};
+struct SolveWS32 {
+  float *bt, *x, *K, *f, *g;
+  KrylovWS<float> kw;
+  Scratch sc;
+};
+struct MixedWS {
+  double *bt, *x, *r, *t1;
+  float *K32, *b32, *d32;
+  KrylovWS<float> kw;
+  Scratch sc;
+};
+
+size_t carve64(cheb_plan* p, const SolveParams& sp, char* base, SolveWS64& w) {
+  Carver c{base, 0};
+  w.bt = c.take<double>(p->npts);
+  w.x = c.take<double>(p->npts);
+  w.r = c.take<double>(p->npts);
+  w.t1 = c.take<double>(p->npts);
+  w.t2 = c.take<double>(p->npts);
+  w.t3 = c.take<double>(p->npts);
+  carve_krylov<double>(c, p->npts, sp.m, sp.k, w.kw);
+  carve_scratch(c, p->npts, sp.m + sp.k + 2, w.sc);
+  return c.off;
+}
+
+size_t carve32(cheb_plan* p, const SolveParams& sp, char* base, SolveWS32& w) {
+  Carver c{base, 0};
+  w.bt = c.take<float>(p->npts);
+  w.x = c.take<float>(p->npts);
+  w.K = nullptr;
+  w.f = nullptr;
+  w.g = nullptr;
+  carve_krylov<float>(c, p->npts, sp.m, sp.k, w.kw);
+  carve_scratch(c, p->npts, sp.m + sp.k + 2, w.sc);
+  return c.off;
+}
+
+size_t carve_mixed(cheb_plan* p, const SolveParams& sp, char* base, MixedWS& w) {
+  Carver c{base, 0};
+  w.bt = c.take<double>(p->npts);
+  w.x = c.take<double>(p->npts);
+  w.r = c.take<double>(p->npts);
+  w.t1 = c.take<double>(p->npts);
+  w.K32 = c.take<float>(p->npts);
+  w.b32 = c.take<float>(p->npts);
+  w.d32 = c.take<float>(p->npts);
+  carve_krylov<float>(c, p->npts, sp.m, sp.k, w.kw);
+  carve_scratch(c, p->npts, sp.m + sp.k + 2, w.sc);
+  return c.off;
+}
+
+size_t solve_need(cheb_plan* p, const SolveParams& sp) {
+  SolveWS64 w64;
+  SolveWS32 w32;
+  MixedWS wm;
+  if (p->prec == CHEB_F32) return carve32(p, sp, nullptr, w32);
+  size_t need = carve64(p, sp, nullptr, w64);
+  if (p->prec == CHEB_MIXED) {
+    const size_t mb = carve_mixed(p, sp, nullptr, wm);
+    if (mb > need) need = mb;
+  }
+  return need;
+}
+
+int check_K(cheb_plan* p, const void* K, Scratch& sc) {
+  int rc = hip_check(hipMemsetAsync(sc.flag, 0, sizeof(int), p->stream), "hipMemsetAsync");
+  if (rc) return rc;
+  if (p->prec == CHEB_F32) rc = check_positive_finite_f32((const float*)K, p->npts, sc.flag, p->stream);
+  else rc = check_positive_finite((const double*)K, p->npts, sc.flag, p->stream);
+  if (rc) return rc;
+  int* hf = (int*)(p->hpinned + 3 * 256);
+  rc = hip_check(hipMemcpyAsync(hf, sc.flag, sizeof(int), hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (*hf) {
+    set_error("conductivity must be finite and positive at every node");
+    return CHEB_ERR_BAD_INPUT;
+  }
+  return CHEB_OK;
+}
+
+// reduced right-hand side bt = f_k - A_kr H g (interior), 0 on the boundary
+template <typename T>
+int reduced_rhs(cheb_plan* p, const T* K, const T* f, const T* g, T* bt, T* tmp) {
+  int rc = fill<T>(tmp, 0.0, p->npts, p->stream);
+  if (!rc) rc = lift_full<T>(p, tmp, g, p->stream);
+  if (!rc) rc = apply_t<T>(p, K, tmp, bt, 0, p->stream);
+  if (!rc) rc = rhs_reduced<T>(bt, f, p->g.n, p->stream);
+  return rc;
+}
+
+// FP64 (or FP32) plain LGMRES solve of the reduced system; x holds interior values.
+template <typename T>
+int solve_plain(cheb_plan* p, const T* K, const T* bt, T* x, T* r, KrylovWS<T>& kw, Scratch& sc,
+                const SolveParams& sp, int mode, Stats& st, double* relres, int* status) {
+  double bnorm;
+  int rc = vnorm<T>(p, bt, sc, &bnorm);
+  if (rc) return rc;
+  const double tol = std::fmax(sp.rtol * bnorm, sp.atol);
+  auto A = [&](const T* in, T* out) { return apply_t<T>(p, K, in, out, mode, p->stream); };
+  double res = 0;
+  if (bnorm == 0.0) {
+    rc = fill<T>(x, 0.0, p->npts, p->stream);
+    *relres = 0.0;
+    *status = CHEB_OK;
+    return rc;
+  }
+  const int r2 = lgmres<T>(p, A, bt, x, !sp.warm, tol, sp.maxiter, kw, sc, st, &res, bnorm, sp.hist,
+                           sp.hist_len);
+  if (r2 < 0) return r2;
+  *status = r2;
+  // final true residual
+  rc = A(x, r);
+  if (!rc) rc = axpby<T>(r, bt, 1.0, -1.0, p->npts, p->stream);
+  if (rc) return rc;
+  double rn;
+  rc = vnorm<T>(p, r, sc, &rn);
+  if (rc) return rc;
+  *relres = rn / bnorm;
+  return CHEB_OK;
+}
+
+}  // namespace
+}  // namespace cheb
+
+using namespace cheb;
+
+extern "C" {
+
+int cheb_plan_workspace_bytes(const cheb_plan* plan, const cheb_solve_opts* opts, size_t* bytes) {
+  if (!plan || !bytes) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  // solver layout, then two FP64 fields used by the Picard loop, the
+  // prolongation and the flux averages
+  *bytes = solve_need(const_cast<cheb_plan*>(plan), params_from(opts)) +
+           2 * field_bytes(plan->npts, sizeof(double));
+  return CHEB_OK;
+}
+
+int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_faces, void* u_inout,
+               const cheb_solve_opts* opts, cheb_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!plan || !K || !f || !g_faces || !u_inout) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  cheb_plan* p = plan;
+  const SolveParams sp = params_from(opts);
+  if (sp.m < 1 || sp.m > 64 || sp.k < 0 || sp.k > 6) {
+    set_error("inner_m must be in [1, 64] and outer_k in [0, 6]");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  size_t need = 0;
+  if (cheb_plan_workspace_bytes(plan, opts, &need)) return CHEB_ERR_INVALID_ARG;
+  if (!p->ws || p->ws_bytes < need) {
+    set_error("workspace missing or too small (see cheb_plan_workspace_bytes)");
+    return CHEB_ERR_WORKSPACE;
+  }
+  cheb_solve_info inf{};
+  Stats st;
+  int rc = 0;
+  int status = CHEB_OK;
+  double relres = 0;
+  if (p->prec == CHEB_F64) {
+    SolveWS64 w;
+    carve64(p, sp, (char*)p->ws, w);
+    rc = check_K(p, K, w.sc);
+    if (rc) return rc;
+    const double* Kd = (const double*)K;
+    rc = reduced_rhs<double>(p, Kd, (const double*)f, (const double*)g_faces, w.bt, w.t1);
+    if (!rc) {
+      if (sp.warm) {
+        rc = copy_scale<double>(w.x, (const double*)u_inout, 1.0, p->npts, p->stream);
+        if (!rc) rc = mask_interior<double>(w.x, p->g.n, p->stream);
+      } else {
+        rc = fill<double>(w.x, 0.0, p->npts, p->stream);
+      }
+    }
+    if (!rc) rc = solve_plain<double>(p, Kd, w.bt, w.x, w.r, w.kw, w.sc, sp, 1, st, &relres, &status);
+    if (!rc) rc = copy_scale<double>((double*)u_inout, w.x, 1.0, p->npts, p->stream);
+    if (!rc) rc = lift_full<double>(p, (double*)u_inout, (const double*)g_faces, p->stream);
+  } else if (p->prec == CHEB_F32) {
+    SolveWS32 w;
+    carve32(p, sp, (char*)p->ws, w);
+    rc = check_K(p, K, w.sc);
+    if (rc) return rc;
+    const float* Kf = (const float*)K;
+    // the first Krylov vector doubles as scratch for the lift of the face data
+    rc = reduced_rhs<float>(p, Kf, (const float*)f, (const float*)g_faces, w.bt, w.kw.w);
+    if (!rc) {
+      if (sp.warm) {
+        rc = copy_scale<float>(w.x, (const float*)u_inout, 1.0, p->npts, p->stream);
+        if (!rc) rc = mask_interior<float>(w.x, p->g.n, p->stream);
+      } else {
+        rc = fill<float>(w.x, 0.0, p->npts, p->stream);
+      }
+    }
+    if (!rc) rc = solve_plain<float>(p, Kf, w.bt, w.x, w.kw.Z, w.kw, w.sc, sp, 1, st, &relres, &status);
+    if (!rc) rc = copy_scale<float>((float*)u_inout, w.x, 1.0, p->npts, p->stream);
+    if (!rc) rc = lift_full<float>(p, (float*)u_inout, (const float*)g_faces, p->stream);
+  } else {
+    // MIXED: FP64 iterative refinement around FP32 LGMRES
+    MixedWS w;
+    carve_mixed(p, sp, (char*)p->ws, w);
+    rc = check_K(p, K, w.sc);
+    if (rc) return rc;
+    const double* Kd = (const double*)K;
+    rc = reduced_rhs<double>(p, Kd, (const double*)f, (const double*)g_faces, w.bt, w.t1);
+    if (!rc) rc = cast_f64_f32(w.K32, Kd, 1.0, p->npts, p->stream);
+    if (!rc) {
+      if (sp.warm) {
+        rc = copy_scale<double>(w.x, (const double*)u_inout, 1.0, p->npts, p->stream);
+        if (!rc) rc = mask_interior<double>(w.x, p->g.n, p->stream);
+      } else {
+        rc = fill<double>(w.x, 0.0, p->npts, p->stream);
+      }
+    }
+    double bnorm = 0;
+    if (!rc) rc = vnorm<double>(p, w.bt, w.sc, &bnorm);
+    const double tol = std::fmax(sp.rtol * bnorm, sp.atol);
+    auto A64 = [&](const double* in, double* out) { return apply_t<double>(p, Kd, in, out, 1, p->stream); };
+    auto A32 = [&](const float* in, float* out) { return apply_t<float>(p, w.K32, in, out, 1, p->stream); };
+    double prev = HUGE_VAL;
+    int slow = 0;
+    status = CHEB_NOT_CONVERGED;
+    int f32mv = 0;
+    for (int it = 0; !rc; ++it) {
+      rc = A64(w.x, w.r);
+      if (!rc) rc = axpby<double>(w.r, w.bt, 1.0, -1.0, p->npts, p->stream);
+      if (rc) break;
+      st.matvecs++;
+      double rho;
+      rc = vnorm<double>(p, w.r, w.sc, &rho);
+      if (rc) break;
+      relres = bnorm > 0 ? rho / bnorm : 0.0;
+      if (sp.hist && st.hist_used < sp.hist_len) sp.hist[st.hist_used++] = relres;
+      if (!(rho > tol)) {
+        status = CHEB_OK;
+        break;
+      }
+      if (it >= sp.ir_max || st.matvecs >= sp.maxiter) break;
+      if (rho > 0.5 * prev) {
+        if (++slow >= 3) {
+          status = CHEB_STAGNATED;
+          break;
+        }
+      } else {
+        slow = 0;
+      }
+      prev = rho;
+      inf.ir_steps++;
+      rc = cast_f64_f32(w.b32, w.r, 1.0 / rho, p->npts, p->stream);
+      if (!rc) rc = fill<float>(w.d32, 0.0, p->npts, p->stream);
+      if (rc) break;
+      Stats si;
+      double res32 = 0;
+      const int budget = sp.maxiter - st.matvecs;
+      const int r2 = lgmres<float>(p, A32, w.b32, w.d32, true, sp.ir_rtol, budget > 1 ? budget : 1, w.kw,
+                                   w.sc, si, &res32, 1.0, nullptr, 0);
+      if (r2 < 0) {
+        rc = r2;
+        break;
+      }
+      st.matvecs += si.matvecs;
+      f32mv += si.matvecs;
+      st.restarts += si.restarts;
+      rc = add_f32_to_f64(w.x, w.d32, rho, p->npts, p->stream);
+    }
+    inf.matvecs_f32 = f32mv;
+    if (!rc) rc = copy_scale<double>((double*)u_inout, w.x, 1.0, p->npts, p->stream);
+    if (!rc) rc = lift_full<double>(p, (double*)u_inout, (const double*)g_faces, p->stream);
+  }
+  if (!rc) rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  inf.status = status;
+  inf.matvecs = st.matvecs;
+  inf.restarts = st.restarts;
+  inf.history_used = st.hist_used;
+  inf.relres_final = relres;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+int cheb_adjoint(cheb_plan* plan, const void* K, const void* u, const void* dLdu, void* lambda, void* dLdlogK,
+                 const cheb_solve_opts* opts, cheb_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!plan || !K || !u || !dLdu || !lambda || !dLdlogK) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (plan->prec == CHEB_F32) {
+    set_error("the adjoint needs an FP64 or MIXED plan");
+    return CHEB_ERR_UNSUPPORTED;
+  }
+  cheb_plan* p = plan;
+  SolveParams sp = params_from(opts);
+  sp.warm = false;
+  SolveWS64 w;
+  const size_t need = carve64(p, sp, nullptr, w);
+  if (!p->ws || p->ws_bytes < need) {
+    set_error("workspace missing or too small (see cheb_plan_workspace_bytes)");
+    return CHEB_ERR_WORKSPACE;
+  }
+  carve64(p, sp, (char*)p->ws, w);
+  int rc = check_K(p, K, w.sc);
+  if (rc) return rc;
+  const double* Kd = (const double*)K;
+  // right-hand side r_k + G^T r_r
+  rc = copy_scale<double>(w.bt, (const double*)dLdu, 1.0, p->npts, p->stream);
+  if (!rc) rc = lift_transpose<double>(p, w.bt, p->stream);
+  if (!rc) rc = fill<double>(w.x, 0.0, p->npts, p->stream);
+  Stats st;
+  double relres = 0;
+  int status = CHEB_OK;
+  if (!rc) rc = solve_plain<double>(p, Kd, w.bt, w.x, w.r, w.kw, w.sc, sp, 2, st, &relres, &status);
+  if (!rc) rc = copy_scale<double>((double*)lambda, w.x, 1.0, p->npts, p->stream);
+  // gradient  -K sum_a (D_a u)(D_a^T lambda~)
+  for (int a = 0; a < 3 && !rc; ++a) {
+    rc = launch_axis_pass<double>(p, a, 3, 1, nullptr, (const double*)u, w.t1, p->stream);
+    if (!rc) rc = launch_axis_pass<double>(p, a, 4, 1, nullptr, w.x, w.t2, p->stream);
+    if (!rc) rc = grad_accumulate((double*)dLdlogK, w.t1, w.t2, a == 0, p->npts, p->stream);
+  }
+  if (!rc) rc = grad_finish((double*)dLdlogK, Kd, p->npts, p->stream);
+  if (!rc) rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (info) {
+    cheb_solve_info inf{};
+    inf.status = status;
+    inf.matvecs = st.matvecs;
+    inf.restarts = st.restarts;
+    inf.history_used = st.hist_used;
+    inf.relres_final = relres;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *info = inf;
+  }
+  return status;
+}
+
+int cheb_picard(cheb_plan* plan, const void* K0, const void* f, const void* g_faces, void* u_inout, void* Kwork,
+                double picard_tol, int32_t max_steps, const cheb_solve_opts* opts, cheb_solve_info* info,
+                int32_t* steps) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!plan || !K0 || !f || !g_faces || !u_inout || !Kwork || max_steps < 1) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (plan->prec == CHEB_F32) {
+    set_error("Picard needs an FP64 or MIXED plan");
+    return CHEB_ERR_UNSUPPORTED;
+  }
+  cheb_plan* p = plan;
+  SolveParams sp = params_from(opts);
+  // the previous iterate and the update live after the solver's own workspace
+  const size_t base = solve_need(p, sp);
+  const size_t fb = field_bytes(p->npts, sizeof(double));
+  if (!p->ws || p->ws_bytes < base + 2 * fb) {
+    set_error("workspace missing or too small (see cheb_plan_workspace_bytes)");
+    return CHEB_ERR_WORKSPACE;
+  }
+  Scratch scr;
+  if (p->prec == CHEB_MIXED) {
+    MixedWS wm;
+    carve_mixed(p, sp, (char*)p->ws, wm);
+    scr = wm.sc;
+  } else {
+    SolveWS64 w64;
+    carve64(p, sp, (char*)p->ws, w64);
+    scr = w64.sc;
+  }
+  double* uold = (double*)((char*)p->ws + base);
+  double* diff = (double*)((char*)p->ws + base + fb);
+  int rc = CHEB_OK;
+  if (!sp.warm) rc = fill<double>((double*)u_inout, 0.0, p->npts, p->stream);
+  cheb_solve_opts o = opts ? *opts : cheb_solve_opts{};
+  o.flags |= 1;
+  cheb_solve_info tot{};
+  int status = CHEB_NOT_CONVERGED;
+  int nsteps = 0;
+  for (int s = 0; s < max_steps && !rc; ++s) {
+    rc = picard_coeff((double*)Kwork, (const double*)K0, (const double*)u_inout, p->npts, p->stream);
+    if (!rc) rc = copy_scale<double>(uold, (const double*)u_inout, 1.0, p->npts, p->stream);
+    if (rc) break;
+    cheb_solve_info si{};
+    const int r2 = cheb_solve(p, Kwork, f, g_faces, u_inout, &o, &si);
+    if (r2 < 0) {
+      rc = r2;
+      break;
+    }
+    nsteps++;
+    tot.matvecs += si.matvecs;
+    tot.matvecs_f32 += si.matvecs_f32;
+    tot.restarts += si.restarts;
+    tot.ir_steps += si.ir_steps;
+    tot.relres_final = si.relres_final;
+    // relative update
+    rc = copy_scale<double>(diff, (const double*)u_inout, 1.0, p->npts, p->stream);
+    if (!rc) rc = axpby<double>(diff, uold, -1.0, 1.0, p->npts, p->stream);
+    double dn = 0, un = 0;
+    if (!rc) rc = vnorm<double>(p, diff, scr, &dn);
+    if (!rc) rc = vnorm<double>(p, (const double*)u_inout, scr, &un);
+    if (rc) break;
+    if (sp.hist && s < sp.hist_len) sp.hist[s] = un > 0 ? dn / un : dn;
+    if (r2 != CHEB_OK) {
+      status = r2;
+      break;
+    }
+    if (!(dn > picard_tol * un)) {
+      status = CHEB_OK;
+      break;
+    }
+  }
+  if (rc) return rc;
+  if (steps) *steps = nsteps;
+  tot.status = status;
+  tot.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  tot.history_used = nsteps < sp.hist_len ? nsteps : sp.hist_len;
+  if (info) *info = tot;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/cheb.h declares, and rejects invalid plans before any
+device call."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2606_21410_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libchebfft.so is not built (run __graft_entry__.build())")
+    return L.load()
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    names = L.declared_functions(os.path.join(ROOT, "include", "cheb.h"))
+    assert len(names) >= 14
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_status_strings():
+    lib = _lib()
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+        s = lib.cheb_status_string(code).decode()
+        assert s and s != "unknown status"
+
+
+def _grid(n=(9, 9, 9), lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 1, 1, 1, 1)):
+    g = L.cheb_grid()
+    for a in range(3):
+        g.n[a], g.lo[a], g.hi[a] = n[a], lo[a], hi[a]
+    for f in range(6):
+        g.bc[f] = bc[f]
+    return g
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=(2, 9, 9)), L.CHEB_ERR_INVALID_ARG),
+    (dict(n=(9, 514, 9)), L.CHEB_ERR_INVALID_ARG),
+    (dict(lo=(0, 1, 0), hi=(1, 1, 1)), L.CHEB_ERR_INVALID_ARG),
+    (dict(bc=(0, 0, 2, 1, 1, 1)), L.CHEB_ERR_INVALID_ARG),
+    (dict(bc=(1, 1, 1, 1, 1, 1)), L.CHEB_ERR_SINGULAR_BC),
+])
+def test_plan_validation(kw, code):
+    lib = _lib()
+    g = _grid(**kw)
+    h = ctypes.c_void_p()
+    rc = lib.cheb_plan_create(ctypes.byref(g), 0, None, ctypes.byref(h))
+    assert rc == code
+    assert not h.value
+    assert lib.cheb_last_error().decode()
+
+
+def test_plan_validation_precision_and_nulls():
+    lib = _lib()
+    g = _grid()
+    h = ctypes.c_void_p()
+    assert lib.cheb_plan_create(ctypes.byref(g), 7, None, ctypes.byref(h)) == L.CHEB_ERR_INVALID_ARG
+    assert lib.cheb_plan_create(None, 0, None, ctypes.byref(h)) == L.CHEB_ERR_INVALID_ARG
+    assert lib.cheb_apply(None, None, None, None, 0) == L.CHEB_ERR_INVALID_ARG
+    assert lib.cheb_solve(None, None, None, None, None, None, None) == L.CHEB_ERR_INVALID_ARG
+    assert lib.cheb_prolong(None, None, None, None, None, None) == L.CHEB_ERR_INVALID_ARG
+    assert lib.cheb_plan_destroy(None) == L.CHEB_OK

@@ -1,0 +1,187 @@
+"""GPU parity of cheb_apply / cheb_derivative against the CPU oracle.
+
+Inputs: u ~ N(0,1) at every node, K log-normal (sigma 0.5) -- the random inputs
+on which the relative L2 metric is meaningful (on smooth u, ||L u|| << ||L|| ||u||).
+Bars: relative L2 error <= 1e-12 in FP64 and <= 1e-5 in FP32.
+"""
+import numpy as np
+import pytest
+
+from oracle import cheb_oracle as O
+from paper_2606_21410_amd import workloads as W
+from tests.gpu_util import BC_SETS, log, rel_l2, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+SIZES = [(5, 5, 5), (9, 9, 9), (17, 17, 17), (24, 24, 24), (33, 33, 33), (49, 49, 49),
+         (65, 65, 65), (97, 97, 97), (17, 33, 9), (13, 6, 65)]
+
+
+def _case(n, bc, seed, lo=(0.0, -1.0, 0.5), hi=(1.0, 1.0, 2.0)):
+    G = O.Grid3(n, lo, hi, bc)
+    u = W.random_field(n, seed)
+    K = W.random_conductivity(n, seed + 1, 0.5)
+    return G, u, K
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("bcname", ["DDNNNN", "NDNNDN", "NNNDNN"])
+def test_apply_full_reduced_f64(n, bcname):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    bc = BC_SETS[bcname]
+    log(f"apply f64 n={n} bc={bcname}")
+    G, u, K = _case(n, bc, 100)
+    plan = Plan(n, G.lo, G.hi, bc, "f64")
+    Kd, ud = to_dev(K, torch.float64), to_dev(u, torch.float64)
+    yf = to_host(plan.apply(Kd, ud, mode="full"))
+    ref = O.apply_full(G, K, u)
+    assert rel_l2(yf, ref) <= F64_TOL
+    yr = to_host(plan.apply(Kd, ud, mode="reduced"))
+    refr = O.apply_reduced(G, K, u)
+    assert rel_l2(yr, refr) <= F64_TOL
+    assert np.all(yr[~G.interior] == 0.0)
+
+
+@pytest.mark.parametrize("n", [(9, 9, 9), (17, 17, 17), (33, 33, 33), (17, 33, 9)])
+@pytest.mark.parametrize("bcname", ["DDNNNN", "NDNNDN", "NNNNND"])
+def test_apply_f32(n, bcname):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    bc = BC_SETS[bcname]
+    log(f"apply f32 n={n} bc={bcname}")
+    G, u, K = _case(n, bc, 200)
+    plan = Plan(n, G.lo, G.hi, bc, "f32")
+    u32 = u.astype(np.float32).astype(np.float64)
+    K32 = K.astype(np.float32).astype(np.float64)
+    Kd, ud = to_dev(K32, torch.float32), to_dev(u32, torch.float32)
+    for mode, fn in (("full", O.apply_full), ("reduced", O.apply_reduced)):
+        y = to_host(plan.apply(Kd, ud, mode=mode))
+        assert rel_l2(y, fn(G, K32, u32)) <= F32_TOL, mode
+
+
+@pytest.mark.parametrize("n", [(5, 5, 5), (9, 7, 6), (13, 13, 13)])
+@pytest.mark.parametrize("bcname", ["DDNNNN", "NDNNDN", "NNNDNN", "DDDDDD"])
+def test_apply_transpose_vs_oracle(n, bcname):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    bc = BC_SETS[bcname]
+    log(f"transpose n={n} bc={bcname}")
+    G, v, K = _case(n, bc, 300)
+    plan = Plan(n, G.lo, G.hi, bc, "f64")
+    y = to_host(plan.apply(to_dev(K, torch.float64), to_dev(v, torch.float64), mode="transpose"))
+    ref = O.apply_reduced_transpose(G, K, v)
+    assert rel_l2(y, ref) <= F64_TOL
+
+
+@pytest.mark.parametrize("n", [(33, 33, 33), (65, 65, 65), (24, 17, 49)])
+def test_apply_transpose_dot_identity(n):
+    """<v, A u> = <A^T v, u> with both sides from the GPU (A checked above)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    bc = BC_SETS["NDNNDN"]
+    G, u, K = _case(n, bc, 400)
+    v = W.random_field(n, 401) * G.interior
+    u = u * G.interior
+    plan = Plan(n, G.lo, G.hi, bc, "f64")
+    Kd = to_dev(K, torch.float64)
+    Au = to_host(plan.apply(Kd, to_dev(u, torch.float64), mode="reduced"))
+    Atv = to_host(plan.apply(Kd, to_dev(v, torch.float64), mode="transpose"))
+    lhs, rhs = float(np.sum(v * Au)), float(np.sum(Atv * u))
+    scale = np.linalg.norm(v) * np.linalg.norm(Au)
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n", [(129, 129, 129)])
+def test_apply_129_full(n):
+    """The metric grid: full parity at 129^3 (FP64 and FP32)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    bc = W.MIXED_X_BC
+    log(f"apply 129^3")
+    G, u, K = _case(n, bc, 500, (0, 0, 0), (1, 1, 1))
+    ref = O.apply_reduced(G, K, u)
+    plan = Plan(n, G.lo, G.hi, bc, "f64")
+    y = to_host(plan.apply(to_dev(K, torch.float64), to_dev(u, torch.float64), mode="reduced"))
+    assert rel_l2(y, ref) <= F64_TOL
+    p32 = Plan(n, G.lo, G.hi, bc, "f32")
+    y32 = to_host(p32.apply(to_dev(K, torch.float32), to_dev(u, torch.float32), mode="reduced"))
+    assert rel_l2(y32, ref) <= F32_TOL
+
+
+def test_apply_257_sampled():
+    """257^3 (fast transform of length 512): pencils sampled against the oracle's
+    per-pencil definition; every x pencil is checked through the derivative."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    n = (257, 257, 257)
+    bc = W.MIXED_X_BC
+    G = O.Grid3((257, 9, 9), (0, 0, 0), (1, 1, 1), bc)   # oracle D for the 257 axis only
+    u = W.random_field(n, 600)
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
+    ud = to_dev(u, torch.float64)
+    for axis in range(3):
+        log(f"derivative 257 axis {axis}")
+        du = to_host(plan.derivative(ud, axis))
+        D = G.D[0]
+        idx = np.random.default_rng(axis).integers(0, 257, size=(24, 2))
+        for a_, b_ in idx:
+            if axis == 0:
+                ref, got = D @ u[:, a_, b_], du[:, a_, b_]
+            elif axis == 1:
+                ref, got = D @ u[a_, :, b_], du[a_, :, b_]
+            else:
+                ref, got = D @ u[a_, b_, :], du[a_, b_, :]
+            assert rel_l2(got, ref) <= F64_TOL
+
+
+@pytest.mark.parametrize("n", [(17, 17, 17), (24, 33, 9)])
+def test_derivative_f64(n):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    G, u, _ = _case(n, BC_SETS["DDNNNN"], 700)
+    plan = Plan(n, G.lo, G.hi, G.bc, "f64")
+    ud = to_dev(u, torch.float64)
+    for a in range(3):
+        d = to_host(plan.derivative(ud, a))
+        assert rel_l2(d, O.deriv(G.D[a], u, a)) <= F64_TOL
+
+
+def test_apply_deterministic():
+    """Same inputs twice -> identical bits (catches missing LDS barriers)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    n = (65, 65, 65)
+    G, u, K = _case(n, BC_SETS["NDNNDN"], 800)
+    plan = Plan(n, G.lo, G.hi, G.bc, "f64")
+    Kd, ud = to_dev(K, torch.float64), to_dev(u, torch.float64)
+    for mode in ("full", "reduced", "transpose"):
+        y1 = plan.apply(Kd, ud, mode=mode).clone()
+        y2 = plan.apply(Kd, ud, mode=mode).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2), mode
+
+
+def test_apply_polynomial_exact():
+    """Polynomial u (deg 3), linear K: the operator reproduces div(K grad u) and
+    the boundary rows reproduce the data (FULL mode) up to rounding."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    P = W.manufactured_polynomial(17, BC_SETS["NDNNDN"], seed=5)
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+    plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64")
+    y = to_host(plan.apply(to_dev(P.K, torch.float64), to_dev(P.u_exact, torch.float64), mode="full"))
+    F = O.full_rhs(G, P.f, P.g)
+    assert np.max(np.abs(y - F)) <= 1e-9 * np.max(np.abs(F))

@@ -1,0 +1,179 @@
+"""GPU parity of prolongation, e_ref, the adjoint gradient, Picard and the
+Clenshaw-Curtis flux averages."""
+import numpy as np
+import pytest
+
+from oracle import cheb_oracle as O
+from paper_2606_21410_amd import workloads as W
+from tests.gpu_util import log, rel_l2, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+
+
+@pytest.mark.parametrize("nc,nf", [((9, 9, 9), (17, 17, 17)), ((17, 17, 17), (33, 33, 33)),
+                                   ((9, 7, 5), (13, 12, 5)), ((33, 33, 33), (65, 65, 65))])
+def test_prolong_vs_barycentric(nc, nf):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, prolong
+    uc = W.random_field(nc, 11)
+    pc = Plan(nc, LO, HI, W.MIXED_X_BC, "f64")
+    pf = Plan(nf, LO, HI, W.MIXED_X_BC, "f64")
+    uf, _ = prolong(pc, pf, to_dev(uc, torch.float64))
+    ref = O.prolong(uc, LO, HI, nf)
+    assert rel_l2(to_host(uf), ref) <= 1e-13
+    if all(2 * (a - 1) == b - 1 for a, b in zip(nc, nf)):
+        # coarse nodes are fine nodes: injection up to rounding
+        assert np.max(np.abs(to_host(uf)[::2, ::2, ::2] - uc)) <= 1e-13 * np.max(np.abs(uc))
+
+
+def test_prolong_f32_and_eref():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, prolong
+    nc, nf = (17, 17, 17), (33, 33, 33)
+    uc = W.random_field(nc, 12)
+    us = W.random_field(nf, 13)
+    pc = Plan(nc, LO, HI, W.MIXED_X_BC, "f32")
+    pf = Plan(nf, LO, HI, W.MIXED_X_BC, "f32")
+    uf, e = prolong(pc, pf, to_dev(uc, torch.float32), uf_solved=to_dev(us, torch.float32))
+    ref = O.prolong(uc.astype(np.float32).astype(np.float64), LO, HI, nf)
+    assert rel_l2(to_host(uf), ref) <= 1e-5
+    assert abs(e - O.e_ref(us.astype(np.float32), ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("bc", [W.MIXED_X_BC, (0, 1, 1, 0, 1, 1)])
+def test_adjoint_vs_dense_oracle(bc):
+    """Adjoint at a small grid against the assembled-matrix adjoint."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    n = (9, 9, 9)
+    G = O.Grid3(n, LO, HI, bc)
+    grid = W.Grid(n, LO, HI, bc)
+    K = W.random_conductivity(n, 21, 0.5)
+    f = W.random_field(n, 22)
+    g = W.random_faces(grid, 23)
+    t = W.random_field(n, 24)
+    U = O.solve_dense(G, K, f, g)
+    lam_ref, g_ref = O.adjoint_dense(G, K, U, U - t)
+    plan = Plan(n, LO, HI, bc, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    lam, grad, info = plan.adjoint(d(K), d(U), d(U - t), SolveOptions(rtol=1e-13))
+    assert info["status"] == 0
+    assert rel_l2(to_host(grad), g_ref) <= 1e-9
+    assert rel_l2(to_host(lam)[G.interior], lam_ref[G.interior]) <= 1e-9
+
+
+def test_adjoint_finite_differences_33():
+    """dL/dlogK against central differences of the GPU forward solve on random
+    node directions (h = 1e-6, FP64)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    n = (33, 33, 33)
+    bc = W.MIXED_X_BC
+    grid = W.Grid(n, (0, 0, 0), (1, 1, 1), bc)
+    logK = np.log(W.lognormal_conductivity(grid, 1005, 1.0, 0.2))
+    t = np.exp(0.5 * W.gaussian_field_rff(grid, 1006, 0.3))
+    g = W.dirichlet_x_faces(grid, -1.0, 1.0)
+    f = np.zeros(n)
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    opts = SolveOptions(rtol=1e-14, maxiter=20000)
+
+    def loss(lk):
+        u, info = plan.solve(d(np.exp(lk)), d(f), d(g), opts=opts)
+        uh = to_host(u)
+        return 0.5 * np.sum((uh - t) ** 2), uh
+
+    L0, U = loss(logK)
+    _, grad, _ = plan.adjoint(d(np.exp(logK)), d(U), d(U - t), opts)
+    gh = to_host(grad)
+    r = np.random.default_rng(1007)
+    h = 1e-6
+    for s in range(3):
+        v = r.standard_normal(n)
+        Lp, _ = loss(logK + h * v)
+        Lm, _ = loss(logK - h * v)
+        fd = (Lp - Lm) / (2 * h)
+        ad = float(np.sum(gh * v))
+        log(f"  FD {fd:.10e} adjoint {ad:.10e}")
+        assert abs(fd - ad) <= 1e-5 * abs(ad)
+
+
+def test_autograd_function():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions, solve_logk
+    n = (9, 9, 9)
+    bc = W.MIXED_X_BC
+    grid = W.Grid(n, (0, 0, 0), (1, 1, 1), bc)
+    G = O.Grid3(n, (0, 0, 0), (1, 1, 1), bc)
+    K = W.random_conductivity(n, 31, 0.5)
+    g = W.dirichlet_x_faces(grid, -1.0, 1.0)
+    f = np.zeros(n)
+    t = W.random_field(n, 32)
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
+    logK = torch.tensor(np.log(K), device="cuda", requires_grad=True)
+    u = solve_logk(plan, logK, to_dev(f, torch.float64), to_dev(g, torch.float64), SolveOptions(rtol=1e-13))
+    L = 0.5 * ((u - to_dev(t, torch.float64)) ** 2).sum()
+    L.backward()
+    U = O.solve_dense(G, K, f, g)
+    _, g_ref = O.adjoint_dense(G, K, U, U - t)
+    assert rel_l2(logK.grad.detach().cpu().numpy(), g_ref) <= 1e-9
+
+
+def test_picard_vs_oracle_and_closed_form():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    n = (17, 17, 17)
+    bc = W.MIXED_X_BC
+    G = O.Grid3(n, (0, 0, 0), (1, 1, 1), bc)
+    grid = W.Grid(n, (0, 0, 0), (1, 1, 1), bc)
+    g = W.dirichlet_x_faces(grid, -1.0, 1.0)
+    K0 = np.full(n, 2.0)
+    f = np.zeros(n)
+    Uo, so = O.picard(G, K0, f, g, tol=1e-10)
+    for prec in ("f64", "mixed"):
+        plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, prec)
+        d = lambda a: to_dev(a, torch.float64)
+        u, info = plan.picard(d(K0), d(f), d(g), tol=1e-10, max_steps=40, opts=SolveOptions(rtol=1e-12))
+        uh = to_host(u)
+        log(f"picard {prec}: steps {info['picard_steps']} oracle {so}")
+        assert info["rc"] == 0
+        assert rel_l2(uh, Uo) <= 1e-8
+        ue = O.picard_closed_form_1d(G.x[0])[:, None, None]
+        assert np.max(np.abs(uh - ue)) <= 1e-7
+
+
+def test_picard_heterogeneous_vs_oracle():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    P = W.two_phase_problem(17, seed=1003, volume_fraction=0.3, contrast=100.0)
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+    Uo, so = O.picard(G, P.K, P.f, P.g, tol=1e-10)
+    plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "mixed")
+    d = lambda a: to_dev(a, torch.float64)
+    u, info = plan.picard(d(P.K), d(P.f), d(P.g), tol=1e-10, max_steps=60, opts=SolveOptions(rtol=1e-12))
+    log(f"picard hetero: {info}")
+    assert info["rc"] == 0
+    assert rel_l2(to_host(u), Uo) <= 1e-8
+
+
+def test_flux_average_vs_oracle():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    n = (17, 13, 9)
+    G = O.Grid3(n, LO, HI, W.MIXED_X_BC)
+    K = W.random_conductivity(n, 41, 0.5)
+    u = W.random_field(n, 42)
+    plan = Plan(n, LO, HI, W.MIXED_X_BC, "f64")
+    out = plan.flux_average(to_dev(K, torch.float64), to_dev(u, torch.float64))
+    ref = O.flux_average(G, K, u)
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))

@@ -1,0 +1,146 @@
+"""GPU solver parity: cheb_solve (FP64, FP32, MIXED) against the oracle's exact
+solution of the same collocation system, plus status handling."""
+import numpy as np
+import pytest
+
+from oracle import cheb_oracle as O
+from paper_2606_21410_amd import workloads as W
+from tests.gpu_util import log, rel_l2, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid(P):
+    return O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+
+
+def _plan(P, prec):
+    from paper_2606_21410_amd.api import Plan
+    return Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, prec)
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_solution(key, P):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = O.solve(_grid(P), P.K, P.f, P.g, tol=1e-14)
+    return _ORACLE_CACHE[key]
+
+
+def test_sincos_17_f64():
+    """u = sin(pi x) cos(pi y) e^z on [-1,1]^3, K = 1, Dirichlet x / Neumann y,z."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import SolveOptions
+    P = W.manufactured_sincos(17)
+    log("solve sincos 17 f64")
+    plan = _plan(P, "f64")
+    u, info = plan.solve(to_dev(P.K, torch.float64), to_dev(P.f, torch.float64), to_dev(P.g, torch.float64),
+                         opts=SolveOptions(rtol=1e-10))
+    uh = to_host(u)
+    uref = _oracle_solution("sincos17", P)
+    log(f"  info {info}  err_oracle {np.max(np.abs(uh - uref)):.3e} err_exact {np.max(np.abs(uh - P.u_exact)):.3e}")
+    assert info["status"] == 0
+    assert info["relres_final"] <= 1e-10
+    assert np.max(np.abs(uh - uref)) <= 1e-7
+    assert np.max(np.abs(uh - P.u_exact)) <= 1e-7
+    u2, info2 = plan.solve(to_dev(P.K, torch.float64), to_dev(P.f, torch.float64), to_dev(P.g, torch.float64),
+                           opts=SolveOptions(rtol=1e-13))
+    assert np.max(np.abs(to_host(u2) - uref)) <= 1e-10
+
+
+def test_paper_poisson_17_f64():
+    """Section 3.2 manufactured problem: local relative error below 1e-9 by N = 16."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import SolveOptions
+    P = W.manufactured_paper3d(17)
+    plan = _plan(P, "f64")
+    u, info = plan.solve(to_dev(P.K, torch.float64), to_dev(P.f, torch.float64), to_dev(P.g, torch.float64),
+                         opts=SolveOptions(rtol=1e-13))
+    uh = to_host(u)
+    assert info["status"] == 0
+    assert np.max(np.abs(uh - P.u_exact) / np.abs(P.u_exact)) <= 1e-9
+
+
+@pytest.mark.parametrize("prec,rtol,bar", [("f64", 1e-12, 1e-9), ("mixed", 1e-12, 1e-8), ("f32", 1e-5, 1e-3)])
+def test_two_phase_33(prec, rtol, bar):
+    """Spherical inclusions (vf 0.2, contrast 10), u = -1/+1 on the x faces,
+    zero flux elsewhere: relative error to the oracle's solution."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import SolveOptions
+    P = W.two_phase_problem(33, seed=1002, n_finest=129)
+    uref = _oracle_solution("tp33", P)
+    log(f"solve two-phase 33 {prec}")
+    plan = _plan(P, prec)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    u, info = plan.solve(to_dev(P.K, dt), to_dev(P.f, dt), to_dev(P.g, dt),
+                         opts=SolveOptions(rtol=rtol, history_len=64))
+    uh = to_host(u)
+    e = rel_l2(uh, uref)
+    log(f"  info {info}  rel err {e:.3e}")
+    assert info["status"] == 0
+    assert e <= bar
+
+
+def test_warm_start_reduces_matvecs():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions, prolong
+    Pc = W.two_phase_problem(17, seed=1002, n_finest=65)
+    Pf = W.two_phase_problem(33, seed=1002, n_finest=65)
+    pc, pf = _plan(Pc, "f64"), _plan(Pf, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    uc, _ = pc.solve(d(Pc.K), d(Pc.f), d(Pc.g), opts=SolveOptions(rtol=1e-12))
+    u0, _ = prolong(pc, pf, uc)
+    _, cold = pf.solve(d(Pf.K), d(Pf.f), d(Pf.g), opts=SolveOptions(rtol=1e-10))
+    uw, warm = pf.solve(d(Pf.K), d(Pf.f), d(Pf.g), u0=u0, opts=SolveOptions(rtol=1e-10))
+    log(f"cold {cold['matvecs']} warm {warm['matvecs']}")
+    assert warm["status"] == 0 and cold["status"] == 0
+    assert warm["matvecs"] < cold["matvecs"]
+
+
+def test_not_converged_status():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import SolveOptions
+    P = W.two_phase_problem(17, seed=1002)
+    plan = _plan(P, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    u, info = plan.solve(d(P.K), d(P.f), d(P.g), opts=SolveOptions(rtol=1e-12, maxiter=4))
+    assert info["status"] == 1 and info["rc"] == 1
+    assert info["relres_final"] > 1e-12
+    assert np.all(np.isfinite(to_host(u)))
+
+
+def test_bad_conductivity_rejected():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd._lib import ChebError
+    P = W.two_phase_problem(9, seed=1002)
+    plan = _plan(P, "f64")
+    K = P.K.copy()
+    K[3, 4, 5] = -1.0
+    d = lambda a: to_dev(a, torch.float64)
+    with pytest.raises(ChebError) as ei:
+        plan.solve(d(K), d(P.f), d(P.g))
+    assert ei.value.code == -3
+    K[3, 4, 5] = np.nan
+    with pytest.raises(ChebError):
+        plan.solve(d(K), d(P.f), d(P.g))
+
+
+def test_solve_deterministic():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import SolveOptions
+    P = W.two_phase_problem(17, seed=1002)
+    plan = _plan(P, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    u1, _ = plan.solve(d(P.K), d(P.f), d(P.g), opts=SolveOptions(rtol=1e-10))
+    u1 = u1.clone()
+    u2, _ = plan.solve(d(P.K), d(P.f), d(P.g), opts=SolveOptions(rtol=1e-10))
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
