@@ -29,7 +29,7 @@ class SolveOptions:
     maxiter: int = 10000
     inner_m: int = 30
     outer_k: int = 3
-    ir_inner_rtol: float = 1e-4
+    ir_inner_rtol: float = 1e-3
     ir_max_outer: int = 50
     history_len: int = 0
 

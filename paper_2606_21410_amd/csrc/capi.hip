@@ -141,7 +141,7 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
     if ((size_t)grid->n[a] > nmax) nmax = grid->n[a];
   }
   p->dconst_stride = round_up(nmax, 64);
-  const size_t cnt = 9 * p->dconst_stride;
+  const size_t cnt = 3 * kConstSlots * p->dconst_stride;
   std::vector<double> h64(cnt, 0.0);
   std::vector<float> h32(cnt, 0.0f);
   for (int a = 0; a < 3; ++a) {
@@ -154,9 +154,14 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
     c.mN0 = rN[0];
     c.mNN = rN[c.N];
     for (int j = 0; j <= c.N; ++j) {
-      h64[(3 * a + 0) * p->dconst_stride + j] = r0[j];
-      h64[(3 * a + 1) * p->dconst_stride + j] = rN[j];
-      h64[(3 * a + 2) * p->dconst_stride + j] = w[j];
+      h64[(kConstSlots * a + 0) * p->dconst_stride + j] = r0[j];
+      h64[(kConstSlots * a + 1) * p->dconst_stride + j] = rN[j];
+      h64[(kConstSlots * a + 2) * p->dconst_stride + j] = w[j];
+    }
+    // twiddles of the length-2N FFT of the even extension: W^j = exp(-i pi j / N)
+    for (int j = 0; j < 2 * c.N; ++j) {
+      h64[(kConstSlots * a + 3) * p->dconst_stride + 2 * j] = std::cos(M_PI * j / c.N);
+      h64[(kConstSlots * a + 3) * p->dconst_stride + 2 * j + 1] = -std::sin(M_PI * j / c.N);
     }
   }
   for (size_t i = 0; i < cnt; ++i) h32[i] = float(h64[i]);

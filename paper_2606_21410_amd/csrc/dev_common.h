@@ -64,110 +64,116 @@ constexpr double ct_cos2pi(long e, long R) { return ct_trig2pi(e, R, false); }
 constexpr double ct_sin2pi(long e, long R) { return ct_trig2pi(e, R, true); }
 
 // ---------------------------------------------------------------------------
-// Register DFTs, forward sign: X_k = sum_j x_j exp(-2 pi i j k / R).
-// Composite sizes use one Cooley-Tukey split R = A*B (input j = B*j1 + j2,
-// output k = k1 + A*k2) with compile-time twiddles.
+// Register DFTs, forward sign: X_k = sum_j x_j exp(-2 pi i j k / R), in place
+// on the slots O + S*i (i < R) of two register arrays.  Composite sizes use one
+// Cooley-Tukey split R = A*B (input j = B*j1 + j2, output k = k1 + A*k2) with
+// compile-time twiddles; outputs are left in digit-reversed slots, output k in
+// slot O + S*dft_pos(R, k).  Every index folds to a constant after unrolling.
 // ---------------------------------------------------------------------------
 constexpr int dft_split(int R) {
   return (R % 4 == 0 && R != 4) ? 4 : (R % 2 == 0 && R != 2) ? 2 : (R % 3 == 0 && R != 3) ? 3 : 0;
 }
 
+constexpr int dft_pos(int R, int k) {
+  return R <= 4 ? k : (R / dft_split(R)) * dft_pos(dft_split(R), k % dft_split(R)) +
+                          dft_pos(R / dft_split(R), k / dft_split(R));
+}
+
+// dft_pos as a constant table, so unrolled loops index registers with literals
 template <int R>
-struct DFT {
-  template <typename T>
-  __device__ __forceinline__ static void run(T* re, T* im) {
+struct PosTab {
+  int v[R];
+};
+template <int R>
+constexpr PosTab<R> make_pos_tab() {
+  PosTab<R> t{};
+  for (int k = 0; k < R; ++k) t.v[k] = dft_pos(R, k);
+  return t;
+}
+
+template <int R, int S, int O, typename T>
+__device__ __forceinline__ void dft_ip(T* re, T* im);
+
+// twiddle the outputs k1 = K1..A-1 of column J2 by W_R^{J2 k1}
+template <int R, int S, int O, int A, int B, int J2, int K1, typename T>
+__device__ __forceinline__ void dft_twiddle(T* re, T* im) {
+  if constexpr (K1 < A) {
+    constexpr int p = O + S * (B * dft_pos(A, K1) + J2);
+    constexpr double c = ct_cos2pi(J2 * K1, R);
+    constexpr double s = -ct_sin2pi(J2 * K1, R);
+    const T xr = re[p], xi = im[p];
+    re[p] = xr * T(c) - xi * T(s);
+    im[p] = xr * T(s) + xi * T(c);
+    dft_twiddle<R, S, O, A, B, J2, K1 + 1, T>(re, im);
+  }
+}
+
+template <int R, int S, int O, int A, int B, int J2, typename T>
+__device__ __forceinline__ void dft_cols(T* re, T* im) {
+  if constexpr (J2 < B) {
+    dft_ip<A, S * B, O + S * J2, T>(re, im);
+    if constexpr (J2 > 0) dft_twiddle<R, S, O, A, B, J2, 1, T>(re, im);
+    dft_cols<R, S, O, A, B, J2 + 1, T>(re, im);
+  }
+}
+
+template <int R, int S, int O, int A, int B, int K1, typename T>
+__device__ __forceinline__ void dft_rows(T* re, T* im) {
+  if constexpr (K1 < A) {
+    dft_ip<B, S, O + S * B * dft_pos(A, K1), T>(re, im);
+    dft_rows<R, S, O, A, B, K1 + 1, T>(re, im);
+  }
+}
+
+template <int R, int S, int O, typename T>
+__device__ __forceinline__ void dft_ip(T* re, T* im) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    const T ar = re[O], ai = im[O];
+    re[O] = ar + re[O + S];
+    im[O] = ai + im[O + S];
+    re[O + S] = ar - re[O + S];
+    im[O + S] = ai - im[O + S];
+  } else if constexpr (R == 3) {
+    const T h = T(0.5);
+    const T s3 = T(0.86602540378443864676372317075293618);  // sin(2 pi/3)
+    const T sr = re[O + S] + re[O + 2 * S], si = im[O + S] + im[O + 2 * S];
+    const T dr = re[O + S] - re[O + 2 * S], di = im[O + S] - im[O + 2 * S];
+    const T mr = re[O] - h * sr, mi = im[O] - h * si;
+    re[O] = re[O] + sr;
+    im[O] = im[O] + si;
+    re[O + S] = mr + s3 * di;
+    im[O + S] = mi - s3 * dr;
+    re[O + 2 * S] = mr - s3 * di;
+    im[O + 2 * S] = mi + s3 * dr;
+  } else if constexpr (R == 4) {
+    const T ar = re[O] + re[O + 2 * S], ai = im[O] + im[O + 2 * S];
+    const T br = re[O] - re[O + 2 * S], bi = im[O] - im[O + 2 * S];
+    const T cr = re[O + S] + re[O + 3 * S], ci = im[O + S] + im[O + 3 * S];
+    const T dr = re[O + S] - re[O + 3 * S], di = im[O + S] - im[O + 3 * S];
+    re[O] = ar + cr;
+    im[O] = ai + ci;
+    re[O + 2 * S] = ar - cr;
+    im[O + 2 * S] = ai - ci;
+    re[O + S] = br + di;   // X1 = b - i d
+    im[O + S] = bi - dr;
+    re[O + 3 * S] = br - di;  // X3 = b + i d
+    im[O + 3 * S] = bi + dr;
+  } else {
     constexpr int A = dft_split(R);
     static_assert(A != 0, "unsupported register DFT size");
     constexpr int B = R / A;
-    T zr[A][B], zi[A][B];
-#pragma unroll
-    for (int j2 = 0; j2 < B; ++j2) {
-      T ar[A], ai[A];
-#pragma unroll
-      for (int j1 = 0; j1 < A; ++j1) {
-        ar[j1] = re[B * j1 + j2];
-        ai[j1] = im[B * j1 + j2];
-      }
-      DFT<A>::run(ar, ai);
-#pragma unroll
-      for (int k1 = 0; k1 < A; ++k1) {
-        const T c = T(ct_cos2pi(j2 * k1, R));
-        const T s = T(-ct_sin2pi(j2 * k1, R));
-        if (j2 * k1 == 0) {
-          zr[k1][j2] = ar[k1];
-          zi[k1][j2] = ai[k1];
-        } else {
-          zr[k1][j2] = ar[k1] * c - ai[k1] * s;
-          zi[k1][j2] = ar[k1] * s + ai[k1] * c;
-        }
-      }
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) {
-      DFT<B>::run(zr[k1], zi[k1]);
-#pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) {
-        re[k1 + A * k2] = zr[k1][k2];
-        im[k1 + A * k2] = zi[k1][k2];
-      }
-    }
+    dft_cols<R, S, O, A, B, 0, T>(re, im);
+    dft_rows<R, S, O, A, B, 0, T>(re, im);
   }
-};
+}
 
-template <>
-struct DFT<1> {
-  template <typename T>
-  __device__ __forceinline__ static void run(T*, T*) {}
-};
-
-template <>
-struct DFT<2> {
+template <int R>
+struct DFT {
+  // forward DFT; afterwards output k sits in slot dft_pos(R, k)
   template <typename T>
   __device__ __forceinline__ static void run(T* re, T* im) {
-    T ar = re[0], ai = im[0];
-    re[0] = ar + re[1];
-    im[0] = ai + im[1];
-    re[1] = ar - re[1];
-    im[1] = ai - im[1];
-  }
-};
-
-template <>
-struct DFT<3> {
-  template <typename T>
-  __device__ __forceinline__ static void run(T* re, T* im) {
-    const T h = T(0.5);
-    const T s3 = T(0.86602540378443864676372317075293618);  // sin(2 pi/3)
-    T sr = re[1] + re[2], si = im[1] + im[2];
-    T dr = re[1] - re[2], di = im[1] - im[2];
-    T mr = re[0] - h * sr, mi = im[0] - h * si;
-    re[0] = re[0] + sr;
-    im[0] = im[0] + si;
-    // X1 = m - i s3 d, X2 = m + i s3 d
-    re[1] = mr + s3 * di;
-    im[1] = mi - s3 * dr;
-    re[2] = mr - s3 * di;
-    im[2] = mi + s3 * dr;
-  }
-};
-
-template <>
-struct DFT<4> {
-  template <typename T>
-  __device__ __forceinline__ static void run(T* re, T* im) {
-    T ar = re[0] + re[2], ai = im[0] + im[2];
-    T br = re[0] - re[2], bi = im[0] - im[2];
-    T cr = re[1] + re[3], ci = im[1] + im[3];
-    T dr = re[1] - re[3], di = im[1] - im[3];
-    re[0] = ar + cr;
-    im[0] = ai + ci;
-    re[2] = ar - cr;
-    im[2] = ai - ci;
-    // X1 = b - i d, X3 = b + i d
-    re[1] = br + di;
-    im[1] = bi - dr;
-    re[3] = br - di;
-    im[3] = bi + dr;
+    dft_ip<R, 1, 0, T>(re, im);
   }
 };
 

@@ -34,7 +34,8 @@ struct cheb_plan {
   hipStream_t stream;
   size_t npts;
   cheb::AxisConst ax[3];
-  // device constants: per axis [row0 | rowN | cc weights], n[a] entries each, f64 then f32
+  // device constants: per axis [row0 | rowN | cc weights | DCT twiddles W_2N^j (2N complex)],
+  // slots of dconst_stride entries (the twiddles take 4 slots), f64 then f32
   double* dconst64;
   float* dconst32;
   size_t dconst_stride;  // entries per (axis, row) slot
@@ -48,12 +49,13 @@ struct cheb_plan {
 
 namespace cheb {
 
-// device constant pointers (axis a, slot s: 0 = row 0, 1 = row N, 2 = CC weights)
+// device constant pointers (axis a, slot s: 0 = row 0, 1 = row N, 2 = CC weights, 3 = twiddles)
+constexpr int kConstSlots = 7;
 inline const double* dconst64(const cheb_plan* p, int a, int s) {
-  return p->dconst64 + (size_t)(3 * a + s) * p->dconst_stride;
+  return p->dconst64 + (size_t)(kConstSlots * a + s) * p->dconst_stride;
 }
 inline const float* dconst32(const cheb_plan* p, int a, int s) {
-  return p->dconst32 + (size_t)(3 * a + s) * p->dconst_stride;
+  return p->dconst32 + (size_t)(kConstSlots * a + s) * p->dconst_stride;
 }
 
 // ---- operator passes (pass_f64.hip / pass_f32.hip) ----

@@ -32,6 +32,7 @@ __device__ int node_owner(int i, int j, int k, const int* n, const int* bc) {
 struct LiftArgs {
   int n[3];
   int bc[6];
+  int bcmask;
   long long goff[6];
 };
 
@@ -58,7 +59,7 @@ __global__ void k_lift_axis(T* U, const T* g, int axis, const T* drow0, const T*
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int np = pencil_count(axis, a.n);
   long long base;
-  const int fl = pencil_flags(axis, p, np, a.n, a.bc, &base);
+  const int fl = pencil_flags(axis, p, np, a.n[0], a.n[1], a.n[2], a.bcmask, &base);
   if (!(fl & PF_VALID)) return;
   const bool nlo = (fl & PF_OWN_LO) && a.bc[2 * axis] == 1;
   const bool nhi = (fl & PF_OWN_HI) && a.bc[2 * axis + 1] == 1;
@@ -94,7 +95,7 @@ __global__ void k_lift_t_axis(T* W, int axis, const T* drow0, const T* drowN, do
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int np = pencil_count(axis, a.n);
   long long base;
-  const int fl = pencil_flags(axis, p, np, a.n, a.bc, &base);
+  const int fl = pencil_flags(axis, p, np, a.n[0], a.n[1], a.n[2], a.bcmask, &base);
   if (!(fl & PF_VALID)) return;
   const bool nlo = (fl & PF_OWN_LO) && a.bc[2 * axis] == 1;
   const bool nhi = (fl & PF_OWN_HI) && a.bc[2 * axis + 1] == 1;
@@ -128,6 +129,7 @@ LiftArgs make_args(const cheb_plan* p) {
   LiftArgs a;
   long long off = 0;
   for (int i = 0; i < 3; ++i) a.n[i] = p->g.n[i];
+  a.bcmask = bc_mask(p->g.bc);
   for (int f = 0; f < 6; ++f) {
     a.bc[f] = p->g.bc[f];
     a.goff[f] = off;

@@ -16,6 +16,11 @@
 // L = R1*R2, register DFTs, one LDS exchange).  The even symmetry of the input
 // makes columns n2 and R2-n2 of the exchange related, so only R2/2+1 columns
 // are computed and stored.
+//
+// Occupancy: a tile is one wave.  The exchange buffer aliases the pencil
+// buffer (every thread moves its items into registers, then a barrier, then
+// the writes), which roughly halves the LDS per pencil; strides are odd in
+// 16-byte units so the b128 exchange accesses are free of bank conflicts.
 #pragma once
 
 #include "dev_common.h"
@@ -32,52 +37,53 @@ struct PassArgs {
   T* y;
   const T* drow0;  // row 0 of the ascending, scaled differentiation matrix (n entries)
   const T* drowN;  // row N
+  const T* twg;    // W_2N^j, j < 2N, interleaved (re, im)
   int n[3];
   int axis;
   int N;      // n[axis] - 1
   int first;  // this pass initialises every row it owns ('='); later passes accumulate
-  int bc[6];
+  int bcmask; // bit f set when face f is Neumann
   T cscale;   // -1 / (N * L_axis)
   T m00, m0N, mN0, mNN;  // corner entries of that matrix
   int npencils;
 };
 
 // ---------------------------------------------------------------------------
-// Tile shape per transform size
+// Tile shape per transform size (NC = 0: generic size, direct DCT)
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int pass_pencils(int N) {
-  return N == 0 ? 16 : N <= 32 ? 64 : N <= 64 ? 32 : 16;
+__host__ __device__ constexpr int pass_threads(int NC) { return 64; }
+__host__ __device__ constexpr int pass_pencils(int NC) {
+  return NC == 0 ? 8 : NC <= 16 ? 16 : NC <= 48 ? 8 : NC <= 64 ? 4 : NC <= 128 ? 8 : 4;
 }
-__host__ __device__ constexpr int pass_threads(int N) { return N >= 256 ? 256 : 128; }
+__host__ __device__ constexpr int exch_stride(int r2) { return (r2 / 2 + 1) | 1; }
 
 struct PassLayout {
-  int e_off, tw_off, sv_off, tmp_off, ends_off, base_off, flags_off, bytes, svs;
+  int buf_off, tw_off, tmp_off, ends_off, base_off, flags_off, bytes, svs;
 };
 
-// LDS layout (bytes) of one tile; NC = compile-time N (0 = generic direct DCT).
+// LDS layout (bytes) of one tile.
 template <typename T>
 __host__ __device__ constexpr PassLayout pass_layout(int NC, int Nrt) {
   const int N = NC > 0 ? NC : Nrt;
   const int P = pass_pencils(NC);
   const int n = N + 1;
   const int svs = n + 1;
-  PassLayout l{0, 0, 0, 0, 0, 0, 0, 0, svs};
+  PassLayout l{0, 0, 0, 0, 0, 0, 0, svs};
   int off = 0;
+  const int sv_bytes = P * svs * (int)sizeof(T);
   if (NC > 0) {
     const Split sp = fft_split(2 * N);
-    const int EH = sp.r2 / 2 + 2;
-    l.e_off = off;
-    off += (P / 2) * sp.r1 * EH * 2 * (int)sizeof(T);
+    const int e_bytes = (P / 2) * sp.r1 * exch_stride(sp.r2) * 2 * (int)sizeof(T);
+    l.buf_off = 0;
+    off = ((e_bytes > sv_bytes ? e_bytes : sv_bytes) + 15) & ~15;
     l.tw_off = off;
     off += 2 * N * 2 * (int)sizeof(T);
-    l.sv_off = off;
-    off += P * svs * (int)sizeof(T);
     l.tmp_off = off;
   } else {
-    l.sv_off = off;
-    off += P * svs * (int)sizeof(T);
+    l.buf_off = 0;
+    off = (sv_bytes + 15) & ~15;
     l.tmp_off = off;
-    off += P * svs * (int)sizeof(T);
+    off += (sv_bytes + 15) & ~15;
     l.tw_off = off;  // cos(pi j / N), j < 2N
     off += 2 * N * (int)sizeof(T);
   }
@@ -86,7 +92,7 @@ __host__ __device__ constexpr PassLayout pass_layout(int NC, int Nrt) {
   off += 4 * P * (int)sizeof(T);
   off = (off + 15) & ~15;
   l.base_off = off;
-  off += P * 8;
+  off += P * 4;
   l.flags_off = off;
   off += P * 4;
   l.bytes = (off + 15) & ~15;
@@ -94,68 +100,106 @@ __host__ __device__ constexpr PassLayout pass_layout(int NC, int Nrt) {
 }
 
 // ---------------------------------------------------------------------------
-// DCT-I of all pencils of the tile, in place in sv (pencil stride SVS).
+// DCT-I of all pencils of the tile, in place in sv (pencil stride N+2); the
+// exchange buffer E aliases sv.
 // ---------------------------------------------------------------------------
 template <typename T, int NC, int P, int NT>
-__device__ __forceinline__ void dct_tile_fast(T* sv, cplx<T>* E, const cplx<T>* tw, int tid) {
+__device__ __forceinline__ void dct_tile_fast(T* sv, const cplx<T>* tw, int tid) {
   constexpr int N = NC, L = 2 * N, SVS = N + 2;
   constexpr Split sp = fft_split(L);
-  constexpr int R1 = sp.r1, R2 = sp.r2, H = R2 / 2 + 1, EH = H + 1, Q = P / 2;
+  constexpr int R1 = sp.r1, R2 = sp.r2, H = R2 / 2 + 1, EH = exch_stride(R2), Q = P / 2;
+  constexpr int IT1 = (Q * H + NT - 1) / NT, IT2 = (Q * R1 + NT - 1) / NT;
   static_assert(R1 > 0 && R2 % 2 == 0, "transform size not supported");
+  constexpr PosTab<R1> pos1 = make_pos_tab<R1>();
+  constexpr PosTab<R2> pos2 = make_pos_tab<R2>();
+  cplx<T>* E = reinterpret_cast<cplx<T>*>(sv);
   // stage 1: columns n2 = 0..R2/2, DFT over n1, twiddle W_L^{n2 k1}
-  for (int w = tid; w < Q * H; w += NT) {
-    const int q = w / H, n2 = w - q * H;
-    const T* a = sv + (2 * q) * SVS;
-    const T* b = a + SVS;
-    T re[R1], im[R1];
+  T re1[IT1][R1], im1[IT1][R1];
 #pragma unroll
-    for (int n1 = 0; n1 < R1; ++n1) {
-      const int m = R2 * n1 + n2;
-      const int s = m <= N ? m : L - m;
-      re[n1] = a[s];
-      im[n1] = b[s];
+  for (int it = 0; it < IT1; ++it) {
+    const int w = tid + it * NT;
+    if (w < Q * H) {
+      const int q = w / H, n2 = w - q * H;
+      const T* a = sv + (2 * q) * SVS;
+      const T* b = a + SVS;
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) {
+        const int m = R2 * n1 + n2;
+        const int s = m <= N ? m : L - m;
+        re1[it][n1] = a[s];
+        im1[it][n1] = b[s];
+      }
     }
-    DFT<R1>::run(re, im);
-    cplx<T>* e = E + (q * R1) * EH + n2;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) {
-      const cplx<T> t = tw[n2 * k1];
-      cplx<T> v;
-      v.x = re[k1] * t.x - im[k1] * t.y;
-      v.y = re[k1] * t.y + im[k1] * t.x;
-      e[k1 * EH] = v;
+  for (int it = 0; it < IT1; ++it) {
+    const int w = tid + it * NT;
+    if (w < Q * H) {
+      const int q = w / H, n2 = w - q * H;
+      DFT<R1>::run(re1[it], im1[it]);
+      cplx<T>* e = E + (q * R1) * EH + n2;
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) {
+        const cplx<T> t = tw[n2 * k1];
+        cplx<T> v;
+        const T xr = re1[it][pos1.v[k1]], xi = im1[it][pos1.v[k1]];
+        v.x = xr * t.x - xi * t.y;
+        v.y = xr * t.y + xi * t.x;
+        e[k1 * EH] = v;
+      }
     }
   }
   __syncthreads();
   // stage 2: rows k1, DFT over n2 (columns > R2/2 from the mirrored row)
-  for (int w = tid; w < Q * R1; w += NT) {
-    const int q = w / R1, k1 = w - q * R1;
-    const int k1p = k1 == 0 ? 0 : R1 - k1;
-    const cplx<T>* e = E + (q * R1) * EH;
-    T re[R2], im[R2];
+  T re2[IT2][R2], im2[IT2][R2];
 #pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) {
-      if (n2 <= R2 / 2) {
-        const cplx<T> v = e[k1 * EH + n2];
-        re[n2] = v.x;
-        im[n2] = v.y;
-      } else {
-        const cplx<T> v = e[k1p * EH + (R2 - n2)];
-        const T c = T(ct_cos2pi(n2, R2)), s = T(-ct_sin2pi(n2, R2));
-        const T vr = v.x * c - v.y * s, vi = v.x * s + v.y * c;
-        re[n2] = k1 ? vr : v.x;
-        im[n2] = k1 ? vi : v.y;
+  for (int it = 0; it < IT2; ++it) {
+    const int w = tid + it * NT;
+    if (w < Q * R1) {
+      const int q = w / R1, k1 = w - q * R1;
+      const int k1p = k1 == 0 ? 0 : R1 - k1;
+      const cplx<T>* e = E + (q * R1) * EH;
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) {
+        if (n2 <= R2 / 2) {
+          const cplx<T> v = e[k1 * EH + n2];
+          re2[it][n2] = v.x;
+          im2[it][n2] = v.y;
+        } else {
+          const cplx<T> v = e[k1p * EH + (R2 - n2)];
+          re2[it][n2] = v.x;
+          im2[it][n2] = v.y;
+        }
       }
     }
-    DFT<R2>::run(re, im);
-    T* a = sv + (2 * q) * SVS;
-    T* b = a + SVS;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int k = k1 + R1 * k2;
-      if (k <= N) {
-        a[k] = re[k2];
-        b[k] = im[k2];
+  for (int it = 0; it < IT2; ++it) {
+    const int w = tid + it * NT;
+    if (w < Q * R1) {
+      const int q = w / R1, k1 = w - q * R1;
+      if (k1 != 0) {
+#pragma unroll
+        for (int n2 = R2 / 2 + 1; n2 < R2; ++n2) {
+          const T c = T(ct_cos2pi(n2, R2)), s = T(-ct_sin2pi(n2, R2));
+          const T vr = re2[it][n2] * c - im2[it][n2] * s;
+          const T vi = re2[it][n2] * s + im2[it][n2] * c;
+          re2[it][n2] = vr;
+          im2[it][n2] = vi;
+        }
+      }
+      DFT<R2>::run(re2[it], im2[it]);
+      T* a = sv + (2 * q) * SVS;
+      T* b = a + SVS;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int k = k1 + R1 * k2;
+        if (k <= N) {
+          a[k] = re2[it][pos2.v[k2]];
+          b[k] = im2[it][pos2.v[k2]];
+        }
       }
     }
   }
@@ -187,10 +231,62 @@ __device__ __forceinline__ void dct_tile_direct(T* sv, T* tmp, const T* ctab, in
 }
 
 // ---------------------------------------------------------------------------
-// Coefficient-space recurrences on one pencil, G lanes per pencil.
+// Coefficient-space recurrences on one pencil, G lanes per pencil, each lane a
+// contiguous chunk of CH coefficients (CH even; compile-time for fast sizes).
 // ---------------------------------------------------------------------------
-template <typename T, int G>
+template <typename T, int G, int CH>
 __device__ __forceinline__ void recur_forward(T* pen, int N, T c, int g) {
+  const int n = N + 1;
+  const int j0 = g * CH;
+  T w[CH];
+  T t0 = T(0), t1 = T(0);
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    const int j = j0 + i;
+    T v = T(0);
+    if (j < n) v = pen[j] * T(j) * ((j == 0 || j == N) ? T(1) : T(2));
+    w[i] = v;
+    if (i & 1) t1 += v; else t0 += v;  // j0 even: parity of j = parity of i
+  }
+  T r0 = group_suffix_excl<G>(t0, g);
+  T r1 = group_suffix_excl<G>(t1, g);
+#pragma unroll
+  for (int i = CH - 1; i >= 0; --i) {
+    const int j = j0 + i;
+    const T beta = (i & 1) ? r0 : r1;  // sum of w_l, l > j, l of the other parity
+    if (j < n) pen[j] = c * beta;
+    if (i & 1) r1 += w[i]; else r0 += w[i];
+  }
+}
+
+template <typename T, int G, int CH>
+__device__ __forceinline__ void recur_transpose(T* pen, int N, T c, int g) {
+  const int n = N + 1;
+  const int j0 = g * CH;
+  T t[CH];
+  T t0 = T(0), t1 = T(0);
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    const int j = j0 + i;
+    T v = T(0);
+    if (j < n) v = pen[j] * ((j == 0 || j == N) ? T(1) : T(2));
+    t[i] = v;
+    if (i & 1) t1 += v; else t0 += v;
+  }
+  T r0 = group_prefix_excl<G>(t0, g);
+  T r1 = group_prefix_excl<G>(t1, g);
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    const int j = j0 + i;
+    const T rho = (i & 1) ? r0 : r1;  // sum of t_k, k < j, k of the other parity
+    if (j < n) pen[j] = c * T(j) * rho;
+    if (i & 1) r1 += t[i]; else r0 += t[i];
+  }
+}
+
+// runtime-size variants (generic path)
+template <typename T, int G>
+__device__ __forceinline__ void recur_forward_rt(T* pen, int N, T c, int g) {
   const int n = N + 1;
   const int C = (((n + G - 1) / G) + 1) & ~1;
   const int j0 = g * C < n ? g * C : n;
@@ -204,14 +300,14 @@ __device__ __forceinline__ void recur_forward(T* pen, int N, T c, int g) {
   T r1 = group_suffix_excl<G>(t1, g);
   for (int j = j1 - 1; j >= j0; --j) {
     const T w = pen[j] * T(j) * ((j == 0 || j == N) ? T(1) : T(2));
-    const T beta = (j & 1) ? r0 : r1;  // sum of w_i, i > j, i of the other parity
+    const T beta = (j & 1) ? r0 : r1;
     pen[j] = c * beta;
     if (j & 1) r1 += w; else r0 += w;
   }
 }
 
 template <typename T, int G>
-__device__ __forceinline__ void recur_transpose(T* pen, int N, T c, int g) {
+__device__ __forceinline__ void recur_transpose_rt(T* pen, int N, T c, int g) {
   const int n = N + 1;
   const int C = (((n + G - 1) / G) + 1) & ~1;
   const int j0 = g * C < n ? g * C : n;
@@ -225,31 +321,70 @@ __device__ __forceinline__ void recur_transpose(T* pen, int N, T c, int g) {
   T r1 = group_prefix_excl<G>(t1, g);
   for (int j = j0; j < j1; ++j) {
     const T t = pen[j] * ((j == 0 || j == N) ? T(1) : T(2));
-    const T rho = (j & 1) ? r0 : r1;  // sum of t_k, k < j, k of the other parity
+    const T rho = (j & 1) ? r0 : r1;
     pen[j] = c * T(j) * rho;
     if (j & 1) r1 += t; else r0 += t;
   }
 }
 
+template <typename T, int NC, int P, int NT>
+__device__ __forceinline__ void pass_dct(T* sv, T* tmp, const cplx<T>* tw, const T* ctab, int N, int tid) {
+  if constexpr (NC > 0) dct_tile_fast<T, NC, P, NT>(sv, tw, tid);
+  else dct_tile_direct<T, P, NT>(sv, tmp, ctab, N, tid);
+}
+
+template <typename T, int NC, int MODE, int G, int CH>
+__device__ __forceinline__ void pass_recur(T* pen, int N, T c, int g) {
+  constexpr bool tr = (MODE == MODE_TRANSPOSE || MODE == MODE_DERIV_T);
+  if constexpr (NC > 0) {
+    if constexpr (tr) recur_transpose<T, G, CH>(pen, N, c, g);
+    else recur_forward<T, G, CH>(pen, N, c, g);
+  } else {
+    if constexpr (tr) recur_transpose_rt<T, G>(pen, N, c, g);
+    else recur_forward_rt<T, G>(pen, N, c, g);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // The pass kernel
 // ---------------------------------------------------------------------------
+// element e of a tile -> (pencil slot pl, node m); pencils are contiguous in
+// memory along z, interleaved (slot fastest) along x and y.  (A macro: passing
+// pl and m by reference to a helper made the compiler keep them in scratch.)
+#define TILE_MAP(e, pl, m)  \
+  if (contig) {             \
+    pl = (e) / n;           \
+    m = (e) - pl * n;       \
+  } else {                  \
+    m = (e) / P;            \
+    pl = (e) - m * P;       \
+  }
+
 template <typename T, int NC, int MODE>
 __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
   constexpr int P = pass_pencils(NC);
   constexpr int NT = pass_threads(NC);
   constexpr int G = NT / P;
+  constexpr int CH = NC > 0 ? ((((NC + 1) + G - 1) / G + 1) & ~1) : 0;
   static_assert(NT % P == 0 && 64 % G == 0, "bad tile shape");
+  // elements of the tile per thread, and whether one register chunk holds them
+  constexpr int EPT = NC > 0 ? (P * (NC + 1) + NT - 1) / NT : 8;
+  constexpr int CHK = EPT < 24 ? EPT : 24;
+  constexpr bool ONE = NC > 0 && CHK * NT >= P * (NC + 1);
+  constexpr bool NEEDK = (MODE != MODE_DERIV && MODE != MODE_DERIV_T);
+  constexpr bool ACC = (MODE == MODE_FULL || MODE == MODE_REDUCED || MODE == MODE_TRANSPOSE);
+  constexpr bool PRE_K = ONE && NEEDK && CHK <= 12;  // K held in registers through the first derivative
+  constexpr bool PRE_Y = ONE && ACC && CHK <= 12;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = NC > 0 ? NC : a.N;
   const int n = N + 1;
   const PassLayout lay = pass_layout<T>(NC, N);
   const int SVS = lay.svs;
-  T* sv = (T*)(smem + lay.sv_off);
+  T* sv = (T*)(smem + lay.buf_off);
   T* ends = (T*)(smem + lay.ends_off);
-  long long* base = (long long*)(smem + lay.base_off);
+  int* base = (int*)(smem + lay.base_off);
   int* flags = (int*)(smem + lay.flags_off);
-  cplx<T>* E = (cplx<T>*)(smem + lay.e_off);
   cplx<T>* tw = (cplx<T>*)(smem + lay.tw_off);
   T* tmp = (T*)(smem + lay.tmp_off);
   T* ctab = (T*)(smem + lay.tw_off);
@@ -258,52 +393,74 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   const int p0 = tile * P;
   const int axis = a.axis;
-  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const long long stride = axis == 2 ? 1LL : axis == 1 ? (long long)n2 : (long long)n1 * n2;
+  const int n1 = a.n[1], n2 = a.n[2];
+  const int stride = axis == 2 ? 1 : axis == 1 ? n2 : n1 * n2;
   const bool contig = axis == 2;
+  const int TOT = P * n;
 
-  // twiddles W_L^j (fast path) or cos(pi j/N) (direct path)
+  // pencil classification (computed redundantly per lane, kept in LDS for the loops)
+  int my_fl = 0, my_base = 0;
+  if (tid < P) {
+    long long b = 0;
+    my_fl = pencil_flags(axis, p0 + tid, a.npencils, a.n[0], a.n[1], a.n[2], a.bcmask, &b);
+    my_base = (int)b;
+    flags[tid] = my_fl;
+    base[tid] = my_base;
+  }
+  // twiddles W_L^j from the plan's table (fast path) or cos(pi j/N) (direct path)
   if (NC > 0) {
-    for (int j = tid; j < 2 * N; j += NT) {
-      double s, c;
-      sincospi(double(j) / double(N), &s, &c);
-      cplx<T> t;
-      t.x = T(c);
-      t.y = T(-s);
-      tw[j] = t;
-    }
+    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.twg);
+    for (int j = tid; j < 2 * N; j += NT) tw[j] = twg[j];
   } else {
     for (int j = tid; j < 2 * N; j += NT) ctab[j] = T(cospi(double(j) / double(N)));
   }
-  // pencil classification
-  if (tid < P) {
-    long long b = 0;
-    flags[tid] = pencil_flags(axis, p0 + tid, a.npencils, a.n, a.bc, &b);
-    base[tid] = b;
-  }
   __syncthreads();
 
-  // load the tile
-  for (int e = tid; e < P * n; e += NT) {
-    int pl, m;
-    if (contig) { pl = e / n; m = e - pl * n; }
-    else { m = e / P; pl = e - m * P; }
-    const int fl = flags[pl];
-    T v = T(0);
-    if (fl & PF_VALID) {
-      const bool ld = (MODE == MODE_FULL || MODE == MODE_DERIV || MODE == MODE_DERIV_T) || (fl & PF_TIN);
-      if (ld) v = a.u[base[pl] + m * stride];
-      if (MODE == MODE_DERIV_T && m != 0 && m != N) v *= T(0.5);
-      if (MODE == MODE_REDUCED || MODE == MODE_TRANSPOSE) {
-        if (m == 0 || m == N) v = T(0);
-        else if (MODE == MODE_TRANSPOSE) v *= T(0.5);
-      }
-      if (MODE == MODE_FULL) {
-        if (m == 0) ends[4 * pl + 0] = v;
-        if (m == N) ends[4 * pl + 1] = v;
+
+  // Global loads: with ONE, u, K (and y when accumulating with few elements)
+  // are all requested up front so the tile waits for memory once.
+  T kv[PRE_K ? CHK : 1];
+  T yv[PRE_Y ? CHK : 1];
+  for (int e0 = 0; e0 < TOT; e0 += NT * CHK) {
+    T v[CHK];
+#pragma unroll
+    for (int c = 0; c < CHK; ++c) {
+      const int e = e0 + c * NT + tid;
+      v[c] = T(0);
+      if (PRE_K) kv[PRE_K ? c : 0] = T(0);
+      if (PRE_Y) yv[c] = T(0);
+      if (e < TOT) {
+        int pl, m;
+        TILE_MAP(e, pl, m);
+        const int fl = flags[pl];
+        if (fl & PF_VALID) {
+          const int ad = base[pl] + m * stride;
+          const bool ld = (MODE == MODE_FULL || MODE == MODE_DERIV || MODE == MODE_DERIV_T) || (fl & PF_TIN);
+          if (ld) v[c] = a.u[ad];
+          if (PRE_K) kv[PRE_K ? c : 0] = a.K[ad];
+          if (PRE_Y && !a.first && (fl & PF_TIN) && m != 0 && m != N) yv[c] = a.y[ad];
+        }
       }
     }
-    sv[pl * SVS + m] = v;
+#pragma unroll
+    for (int c = 0; c < CHK; ++c) {
+      const int e = e0 + c * NT + tid;
+      if (e < TOT) {
+        int pl, m;
+        TILE_MAP(e, pl, m);
+        T x = v[c];
+        if (MODE == MODE_DERIV_T && m != 0 && m != N) x *= T(0.5);
+        if (MODE == MODE_REDUCED || MODE == MODE_TRANSPOSE) {
+          if (m == 0 || m == N) x = T(0);
+          else if (MODE == MODE_TRANSPOSE) x *= T(0.5);
+        }
+        if (MODE == MODE_FULL) {
+          if (m == 0) ends[4 * pl + 0] = x;
+          if (m == N) ends[4 * pl + 1] = x;
+        }
+        sv[pl * SVS + m] = x;
+      }
+    }
   }
   __syncthreads();
 
@@ -322,7 +479,7 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
     sN = group_sum<G>(sN);
     const int fl = flags[pp];
     if (g == 0 && (fl & PF_TIN)) {
-      const bool nlo = a.bc[2 * axis] == 1, nhi = a.bc[2 * axis + 1] == 1;
+      const bool nlo = (a.bcmask >> (2 * axis)) & 1, nhi = (a.bcmask >> (2 * axis + 1)) & 1;
       T u0 = T(0), uN = T(0);
       if (nlo && nhi) {
         const T det = a.m00 * a.mNN - a.m0N * a.mN0;
@@ -340,45 +497,52 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
   }
 
   // first derivative (or its transpose)
-  if constexpr (NC > 0) dct_tile_fast<T, NC, P, NT>(sv, E, tw, tid);
-  else dct_tile_direct<T, P, NT>(sv, tmp, ctab, N, tid);
-  if (MODE == MODE_TRANSPOSE || MODE == MODE_DERIV_T) recur_transpose<T, G>(pen, N, a.cscale, g);
-  else recur_forward<T, G>(pen, N, a.cscale, g);
-  __syncthreads();
-  if constexpr (NC > 0) dct_tile_fast<T, NC, P, NT>(sv, E, tw, tid);
-  else dct_tile_direct<T, P, NT>(sv, tmp, ctab, N, tid);
+  pass_dct<T, NC, P, NT>(sv, tmp, tw, ctab, N, tid);
+  pass_recur<T, NC, MODE, G, CH>(pen, N, a.cscale, g);
+  pass_dct<T, NC, P, NT>(sv, tmp, tw, ctab, N, tid);
 
-  if (MODE != MODE_DERIV && MODE != MODE_DERIV_T) {
+  if (NEEDK) {
     // pointwise flux K * D_a u (boundary nodes included)
-    for (int e = tid; e < P * n; e += NT) {
-      int pl, m;
-      if (contig) { pl = e / n; m = e - pl * n; }
-      else { m = e / P; pl = e - m * P; }
-      const int fl = flags[pl];
-      T v = sv[pl * SVS + m];
-      if (MODE == MODE_FULL) {
-        if (m == 0) ends[4 * pl + 2] = v;
-        if (m == N) ends[4 * pl + 3] = v;
+    for (int e0 = 0; e0 < TOT; e0 += NT * CHK) {
+      T k2[PRE_K ? 1 : CHK];
+      if (!PRE_K) {
+#pragma unroll
+        for (int c = 0; c < CHK; ++c) {
+          const int e = e0 + c * NT + tid;
+          k2[PRE_K ? 0 : c] = T(0);
+          if (e < TOT) {
+            int pl, m;
+            TILE_MAP(e, pl, m);
+            if (flags[pl] & PF_VALID) k2[PRE_K ? 0 : c] = a.K[base[pl] + m * stride];
+          }
+        }
       }
-      T k = T(0);
-      if (fl & PF_VALID) k = a.K[base[pl] + m * stride];
-      sv[pl * SVS + m] = v * k;
+#pragma unroll
+      for (int c = 0; c < CHK; ++c) {
+        const int e = e0 + c * NT + tid;
+        if (e < TOT) {
+          int pl, m;
+          TILE_MAP(e, pl, m);
+          const T x = sv[pl * SVS + m];
+          if (MODE == MODE_FULL) {
+            if (m == 0) ends[4 * pl + 2] = x;
+            if (m == N) ends[4 * pl + 3] = x;
+          }
+          sv[pl * SVS + m] = x * (PRE_K ? kv[PRE_K ? c : 0] : k2[PRE_K ? 0 : c]);
+        }
+      }
     }
     __syncthreads();
     // divergence part
-    if constexpr (NC > 0) dct_tile_fast<T, NC, P, NT>(sv, E, tw, tid);
-    else dct_tile_direct<T, P, NT>(sv, tmp, ctab, N, tid);
-    if (MODE == MODE_TRANSPOSE) recur_transpose<T, G>(pen, N, a.cscale, g);
-    else recur_forward<T, G>(pen, N, a.cscale, g);
-    __syncthreads();
-    if constexpr (NC > 0) dct_tile_fast<T, NC, P, NT>(sv, E, tw, tid);
-    else dct_tile_direct<T, P, NT>(sv, tmp, ctab, N, tid);
+    pass_dct<T, NC, P, NT>(sv, tmp, tw, ctab, N, tid);
+    pass_recur<T, NC, MODE, G, CH>(pen, N, a.cscale, g);
+    pass_dct<T, NC, P, NT>(sv, tmp, tw, ctab, N, tid);
   }
 
   if (MODE == MODE_TRANSPOSE) {
     // transposed lift: mu = M^{-T} [z_0, z_N]; interior -= mu0 D_{0,:} + muN D_{N,:}
     if (g == 0) {
-      const bool nlo = a.bc[2 * axis] == 1, nhi = a.bc[2 * axis + 1] == 1;
+      const bool nlo = (a.bcmask >> (2 * axis)) & 1, nhi = (a.bcmask >> (2 * axis + 1)) & 1;
       const T z0 = pen[0], zN = pen[N];
       T mu0 = T(0), muN = T(0);
       if (nlo && nhi) {
@@ -396,43 +560,66 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
     __syncthreads();
   }
 
-  // store
-  for (int e = tid; e < P * n; e += NT) {
-    int pl, m;
-    if (contig) { pl = e / n; m = e - pl * n; }
-    else { m = e / P; pl = e - m * P; }
-    const int fl = flags[pl];
-    if (!(fl & PF_VALID)) continue;
-    const long long ad = base[pl] + m * stride;
-    T v = sv[pl * SVS + m];
-    const bool isend = (m == 0 || m == N);
-    if (MODE == MODE_DERIV) {
-      a.y[ad] = v;
-    } else if (MODE == MODE_DERIV_T) {
-      a.y[ad] = isend ? v : T(2) * v;
-    } else if (MODE == MODE_FULL) {
-      if (!isend) {
-        if (fl & PF_TIN) a.y[ad] = a.first ? v : a.y[ad] + v;
-      } else {
-        const bool own = (m == 0) ? (fl & PF_OWN_LO) : (fl & PF_OWN_HI);
-        if (own) {
-          const int bct = a.bc[2 * axis + (m == 0 ? 0 : 1)];
-          T r;
-          if (bct == 0) r = ends[4 * pl + (m == 0 ? 0 : 1)];
-          else r = (m == 0) ? -ends[4 * pl + 2] : ends[4 * pl + 3];
-          a.y[ad] = r;
+  // store (accumulating passes without prefetched y load their chunk first)
+  for (int e0 = 0; e0 < TOT; e0 += NT * CHK) {
+    T y2[PRE_Y ? 1 : CHK];
+    if (!PRE_Y) {
+#pragma unroll
+      for (int c = 0; c < CHK; ++c) {
+        const int e = e0 + c * NT + tid;
+        y2[PRE_Y ? 0 : c] = T(0);
+        if (ACC && !a.first && e < TOT) {
+          int pl, m;
+          TILE_MAP(e, pl, m);
+          const int fl = flags[pl];
+          if ((fl & PF_VALID) && (fl & PF_TIN) && m != 0 && m != N) y2[PRE_Y ? 0 : c] = a.y[base[pl] + m * stride];
         }
       }
-    } else {
-      if (!(fl & PF_TIN) || isend) {
-        if (a.first) a.y[ad] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < CHK; ++c) {
+      const int e = e0 + c * NT + tid;
+      if (e >= TOT) continue;
+      int pl, m;
+      TILE_MAP(e, pl, m);
+      const int fl = flags[pl];
+      if (!(fl & PF_VALID)) continue;
+      const int ad = base[pl] + m * stride;
+      const T yold = PRE_Y ? yv[PRE_Y ? c : 0] : y2[PRE_Y ? 0 : c];
+      T x = sv[pl * SVS + m];
+      const bool isend = (m == 0 || m == N);
+      if (MODE == MODE_DERIV) {
+        a.y[ad] = x;
+      } else if (MODE == MODE_DERIV_T) {
+        a.y[ad] = isend ? x : T(2) * x;
+      } else if (MODE == MODE_FULL) {
+        if (!isend) {
+          if (fl & PF_TIN) a.y[ad] = a.first ? x : yold + x;
+        } else {
+          const bool own = (m == 0) ? (fl & PF_OWN_LO) : (fl & PF_OWN_HI);
+          if (own) {
+            const int bct = (a.bcmask >> (2 * axis + (m == 0 ? 0 : 1))) & 1;
+            T r;
+            if (bct == 0) r = ends[4 * pl + (m == 0 ? 0 : 1)];
+            else r = (m == 0) ? -ends[4 * pl + 2] : ends[4 * pl + 3];
+            a.y[ad] = r;
+          }
+        }
       } else {
-        if (MODE == MODE_TRANSPOSE)
-          v = T(2) * v - ends[4 * pl + 0] * a.drow0[m] - ends[4 * pl + 1] * a.drowN[m];
-        a.y[ad] = a.first ? v : a.y[ad] + v;
+        if (!(fl & PF_TIN) || isend) {
+          if (a.first) a.y[ad] = T(0);
+        } else {
+          if (MODE == MODE_TRANSPOSE)
+            x = T(2) * x - ends[4 * pl + 0] * a.drow0[m] - ends[4 * pl + 1] * a.drowN[m];
+          a.y[ad] = a.first ? x : yold + x;
+        }
       }
     }
   }
+  (void)my_fl;
+  (void)my_base;
 }
+
+#undef TILE_MAP
 
 }  // namespace cheb

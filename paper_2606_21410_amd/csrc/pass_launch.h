@@ -76,8 +76,9 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
   a.y = y;
   a.drow0 = drow<T>(p, axis, 0);
   a.drowN = drow<T>(p, axis, 1);
+  a.twg = drow<T>(p, axis, 3);
   for (int i = 0; i < 3; ++i) a.n[i] = p->g.n[i];
-  for (int i = 0; i < 6; ++i) a.bc[i] = p->g.bc[i];
+  a.bcmask = bc_mask(p->g.bc);
   a.axis = axis;
   a.N = p->ax[axis].N;
   a.first = first;

@@ -15,12 +15,14 @@ enum PencilFlag { PF_VALID = 1, PF_TIN = 2, PF_OWN_LO = 4, PF_OWN_HI = 8 };
 // interior nodes).  PF_OWN_LO/HI: the end node's equation belongs to this
 // axis' face: a node on several faces is owned by the Dirichlet face of lowest
 // axis if any, else by the Neumann face of lowest axis.
-__host__ __device__ inline int pencil_flags(int axis, int p, int npencils, const int* n, const int* bc,
+__host__ __device__ inline int sel3(int a0, int a1, int a2, int i) { return i == 0 ? a0 : i == 1 ? a1 : a2; }
+
+// bcmask: bit f set when face f is Neumann
+__host__ __device__ inline int pencil_flags(int axis, int p, int npencils, int n0, int n1, int n2, int bcmask,
                                             long long* base) {
   *base = 0;
   if (p >= npencils) return 0;
   int fl = PF_VALID;
-  const int n1 = n[1], n2 = n[2];
   int ta, tb, ia, ib;
   if (axis == 2) {
     ta = 0; tb = 1; ia = p / n1; ib = p - ia * n1;
@@ -37,10 +39,10 @@ __host__ __device__ inline int pencil_flags(int axis, int p, int npencils, const
     const int bax = s == 0 ? ta : tb, idx = s == 0 ? ia : ib;
     int f = -1;
     if (idx == 0) f = 2 * bax;
-    else if (idx == n[bax] - 1) f = 2 * bax + 1;
+    else if (idx == sel3(n0, n1, n2, bax) - 1) f = 2 * bax + 1;
     if (f >= 0) {
       any = true;
-      const bool d = bc[f] == 0;
+      const bool d = ((bcmask >> f) & 1) == 0;
       hasD = hasD || d;
       if (bax < axis) {
         haslow = true;
@@ -49,10 +51,17 @@ __host__ __device__ inline int pencil_flags(int axis, int p, int npencils, const
     }
   }
   if (!any) fl |= PF_TIN;
-  const bool dlo = bc[2 * axis] == 0, dhi = bc[2 * axis + 1] == 0;
+  const bool dlo = ((bcmask >> (2 * axis)) & 1) == 0, dhi = ((bcmask >> (2 * axis + 1)) & 1) == 0;
   if (dlo ? !hasDlow : (!hasD && !haslow)) fl |= PF_OWN_LO;
   if (dhi ? !hasDlow : (!hasD && !haslow)) fl |= PF_OWN_HI;
   return fl;
+}
+
+__host__ __device__ inline int bc_mask(const int* bc) {
+  int m = 0;
+  for (int f = 0; f < 6; ++f)
+    if (bc[f] == 1) m |= 1 << f;
+  return m;
 }
 
 __host__ __device__ inline long long pencil_stride(int axis, const int* n) {

@@ -49,7 +49,7 @@ SolveParams params_from(const cheb_solve_opts* o) {
   s.maxiter = (o && o->maxiter > 0) ? o->maxiter : 10000;
   s.m = (o && o->inner_m > 0) ? o->inner_m : 30;
   s.k = !o || o->outer_k == 0 ? 3 : (o->outer_k < 0 ? 0 : o->outer_k);
-  s.ir_rtol = (o && o->ir_inner_rtol > 0) ? o->ir_inner_rtol : 1e-4;
+  s.ir_rtol = (o && o->ir_inner_rtol > 0) ? o->ir_inner_rtol : 1e-3;
   s.ir_max = (o && o->ir_max_outer > 0) ? o->ir_max_outer : 50;
   s.warm = o && (o->flags & 1);
   s.hist = o ? o->history : nullptr;
@@ -121,10 +121,13 @@ int vnorm(cheb_plan* p, const T* v, Scratch& s, double* out) {
 
 // LGMRES on  A x = b  with absolute tolerance tol_abs on ||b - A x||.
 // Returns CHEB_OK when converged, CHEB_NOT_CONVERGED when maxmv was reached.
+// stall > 0: stop with CHEB_STAGNATED when a restart cycle reduces the true
+// residual by less than that factor (used by the FP32 inner solves, whose
+// attainable accuracy is bounded by the FP32 operator).
 template <typename T, typename ApplyFn>
 int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_abs, int maxmv,
            KrylovWS<T>& kw, Scratch& sc, Stats& st, double* resid_out, double bnorm, double* hist,
-           int hist_len) {
+           int hist_len, double stall = 0.0) {
   const size_t npts = p->npts;
   hipStream_t s = p->stream;
   const int m = kw.m, kmax = kw.k;
@@ -136,7 +139,7 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
   T* w = kw.w;
   int rc;
   bool first = true;
-  double beta = 0.0;
+  double beta = 0.0, beta_prev = HUGE_VAL;
   for (;;) {
     // true residual r = b - A x  into V_0 (unnormalised)
     T* v0 = kw.V;
@@ -155,6 +158,8 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
     *resid_out = beta;
     if (!(beta > tol_abs)) return std::isfinite(beta) ? CHEB_OK : CHEB_NOT_CONVERGED;
     if (st.matvecs >= maxmv) return CHEB_NOT_CONVERGED;
+    if (stall > 0.0 && beta > stall * beta_prev) return CHEB_STAGNATED;
+    beta_prev = beta;
     rc = copy_scale<T>(v0, v0, 1.0 / beta, npts, s);
     if (rc) return rc;
     std::fill(H.begin(), H.end(), 0.0);
@@ -536,9 +541,11 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
       if (rc) break;
       Stats si;
       double res32 = 0;
-      const int budget = sp.maxiter - st.matvecs;
+      int budget = sp.maxiter - st.matvecs;
+      const int cap = 40 * (sp.m + sp.k + 1);
+      if (budget > cap) budget = cap;
       const int r2 = lgmres<float>(p, A32, w.b32, w.d32, true, sp.ir_rtol, budget > 1 ? budget : 1, w.kw,
-                                   w.sc, si, &res32, 1.0, nullptr, 0);
+                                   w.sc, si, &res32, 1.0, nullptr, 0, 0.9);
       if (r2 < 0) {
         rc = r2;
         break;
