@@ -86,9 +86,13 @@ typedef struct cheb_solve_opts {
   int32_t maxiter;       /* maximum operator applications (0 = 10000) */
   int32_t inner_m;       /* LGMRES Krylov dimension per restart cycle (0 = 30) */
   int32_t outer_k;       /* LGMRES augmentation vectors (0 = 3, negative = none, max 6) */
-  double ir_inner_rtol;  /* MIXED: relative tolerance of each FP32 inner solve (0 = 1e-4) */
+  double ir_inner_rtol;  /* MIXED: relative tolerance of each FP32 inner solve (0 = 1e-3); an inner
+                            solve also stops when a restart cycle gains less than 10% */
   int32_t ir_max_outer;  /* MIXED: maximum FP64 refinement steps (0 = 50) */
-  int32_t flags;         /* bit 0: use the initial guess in u_inout (else start from 0) */
+  int32_t flags;         /* bit 0: use the initial guess in u_inout (else start from 0);
+                            bit 1: right-precondition LGMRES by fast diagonalisation of the
+                            constant-coefficient operator (mean K) -- an extension, off in the
+                            paper's plain method */
   double* history;       /* optional host array receiving the relative residual per restart / IR step */
   int32_t history_len;
   int32_t reserved[3];
@@ -182,6 +186,13 @@ int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis);
  * out[3] (Section 3.3 effective conductivity: K_num = <K du/dx_a> / G).
  * Uses 4 fields of workspace.  Synchronises. */
 int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[3]);
+
+/* Dense GEMM on the matrix cores, D (I x C) = A (I x K) B (K x C), row-major
+ * device arrays (double for CHEB_F64, float for CHEB_F32).  This is the
+ * contraction kernel of the preconditioner, exposed so its MFMA lane layout can
+ * be checked directly.  Asynchronous on `stream`. */
+int cheb_debug_gemm(int32_t precision, const void* A, const void* B, void* D, int32_t I, int32_t K, int32_t C,
+                    void* stream);
 
 const char* cheb_status_string(int status);
 const char* cheb_last_error(void);

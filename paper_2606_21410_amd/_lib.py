@@ -70,6 +70,8 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_int32)]),
     "cheb_derivative": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "cheb_flux_average": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "cheb_debug_gemm": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, _vp]),
     "cheb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cheb_last_error": (ctypes.c_char_p, []),
 }

@@ -32,13 +32,14 @@ class SolveOptions:
     ir_inner_rtol: float = 1e-3
     ir_max_outer: int = 50
     history_len: int = 0
+    precond: bool = False   # fast-diagonalisation right preconditioner (extension)
 
     def to_c(self, warm: bool):
         o = L.cheb_solve_opts()
         o.rtol, o.atol, o.maxiter = self.rtol, self.atol, self.maxiter
         o.inner_m, o.outer_k = self.inner_m, (self.outer_k if self.outer_k > 0 else -1)
         o.ir_inner_rtol, o.ir_max_outer = self.ir_inner_rtol, self.ir_max_outer
-        o.flags = 1 if warm else 0
+        o.flags = (1 if warm else 0) | (2 if self.precond else 0)
         hist = None
         if self.history_len > 0:
             hist = (ctypes.c_double * self.history_len)()
@@ -200,6 +201,20 @@ class Plan:
         out = (ctypes.c_double * 3)()
         L.check(self.lib.cheb_flux_average(self._h, self._field(K, "K"), self._field(u, "u"), out))
         return [out[0], out[1], out[2]]
+
+
+def debug_gemm(A, B):
+    """D = A @ B on the matrix cores (the preconditioner's contraction kernel)."""
+    lib = L.load()
+    I, K = A.shape
+    K2, C = B.shape
+    assert K == K2 and A.dtype == B.dtype and A.is_contiguous() and B.is_contiguous()
+    D = torch.empty((I, C), dtype=A.dtype, device=A.device)
+    prec = L.CHEB_F32 if A.dtype == torch.float32 else L.CHEB_F64
+    L.check(lib.cheb_debug_gemm(prec, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                ctypes.c_void_p(D.data_ptr()), I, K, C,
+                                ctypes.c_void_p(_stream_handle(A.device))))
+    return D
 
 
 def prolong(coarse: Plan, fine: Plan, uc, uf=None, uf_solved=None):

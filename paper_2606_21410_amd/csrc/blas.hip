@@ -208,7 +208,33 @@ __global__ __launch_bounds__(kThreads) void k_cc_dot(const double* a, const doub
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vsum(const T* x, size_t npts, double* partials) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < npts; i += (size_t)gridDim.x * kThreads)
+    acc += double(x[i]);
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) s += red[q];
+    partials[blockIdx.x] = s;
+  }
+}
+
 }  // namespace
+
+template <typename T>
+int vsum(const T* x, size_t npts, double* partials, double* out, hipStream_t s) {
+  const int blocks = grid_for(npts, kThreads * 4, 1024);
+  hipLaunchKernelGGL(k_vsum<T>, dim3(blocks), dim3(kThreads), 0, s, x, npts, partials);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(kThreads), 0, s, partials, blocks, 1, out);
+  return hip_check(hipGetLastError(), "vsum");
+}
+template int vsum<double>(const double*, size_t, double*, double*, hipStream_t);
+template int vsum<float>(const float*, size_t, double*, double*, hipStream_t);
 
 size_t multidot_partials_len(size_t npts, int nv) {
   const size_t blocks = (npts + kChunk - 1) / kChunk;

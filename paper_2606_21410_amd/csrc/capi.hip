@@ -216,6 +216,8 @@ int cheb_plan_destroy(cheb_plan* plan) {
   if (plan->dconst64) (void)hipFree(plan->dconst64);
   if (plan->dconst32) (void)hipFree(plan->dconst32);
   if (plan->hpinned) (void)hipHostFree(plan->hpinned);
+  if (plan->pc64) (void)hipFree(plan->pc64);
+  if (plan->pc32) (void)hipFree(plan->pc32);
   delete plan;
   return CHEB_OK;
 }

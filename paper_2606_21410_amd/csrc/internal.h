@@ -26,6 +26,12 @@ int hip_check(hipError_t e, const char* what);
 // Workspace carving: fields padded to 256 bytes.
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// fast-diagonalisation preconditioner factors of one axis (offsets into pc64/pc32)
+struct PrecondAxis {
+  int m;
+  size_t off_V, off_Vi, off_lam;
+};
+
 }  // namespace cheb
 
 struct cheb_plan {
@@ -45,6 +51,11 @@ struct cheb_plan {
   void* ws;
   size_t ws_bytes;
   hipEvent_t ev;
+  // fast-diagonalisation preconditioner (built on first use)
+  int pc_ready;
+  double* pc64;
+  float* pc32;
+  cheb::PrecondAxis pc_ax[3];
 };
 
 namespace cheb {
@@ -111,6 +122,16 @@ template <typename T>
 int lift_full(const cheb_plan* p, T* U, const T* g_faces, hipStream_t s);     // x_r = G x_k + H g
 template <typename T>
 int lift_transpose(const cheb_plan* p, T* W, hipStream_t s);                  // W <- lift^T W (interior)
+
+// ---- preconditioner (precond.hip) ----
+int precond_setup(cheb_plan* p);
+// out = M^{-1} in (or M^{-T} in); bufA/bufB: packed interior scratch (m0*m1*m2 each)
+template <typename T>
+int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, double kc, bool transpose,
+                  hipStream_t s);
+// sum of all entries (double accumulation) into out[0]
+template <typename T>
+int vsum(const T* x, size_t npts, double* partials, double* out, hipStream_t s);
 
 // ---- prolongation (prolong.hip) ----
 template <typename T>

@@ -1,0 +1,525 @@
+// Fast-diagonalisation preconditioner for the reduced collocation operator
+// (an extension: the paper's solver is unpreconditioned LGMRES).
+//
+// For a constant conductivity Kc the reduced operator is the Kronecker sum
+// Kc (A_x (+) A_y (+) A_z) of the 1-D reduced operators A_a = R D_a D_a L_a
+// (second derivative on the interior nodes of one pencil, end values lifted by
+// that axis' boundary rows).  With A_a = V_a diag(lambda_a) V_a^{-1},
+//   M^{-1} = (V_x (x) V_y (x) V_z) diag(1 / (Kc (lx_i + ly_j + lz_k))) (V_x^{-1} (x) ...),
+// the exact inverse for constant K and a spectrally close one for variable K
+// (Kc = mean of K).  Right preconditioning leaves the discrete solution unchanged.
+//
+// Setup (host, once per plan): the 1-D matrices from the closed-form
+// differentiation matrix, a real nonsymmetric eigensolver (Householder
+// reduction to Hessenberg form, implicit single-shift QR with Wilkinson shifts
+// to the real Schur form -- the eigenvalues of these operators are real -- and
+// back-substitution for the eigenvectors), and the inverse by Gauss-Jordan.
+// Apply (device): pack interior -> three dense axis contractions with V^{-1}
+// -> divide by the eigenvalue sums -> three contractions with V -> unpack.
+// The contractions are batched GEMMs on the matrix cores (MFMA 16x16x4).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace cheb {
+
+// ---------------------------------------------------------------------------
+// host linear algebra
+// ---------------------------------------------------------------------------
+namespace {
+
+// full ascending differentiation matrix on [lo, lo+L] (closed-form entries,
+// diagonal from the negative row sum)
+void dense_D(int N, double L, std::vector<double>& D) {
+  const int n = N + 1;
+  D.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double rs = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      const double ci = (i == 0 || i == N) ? 2.0 : 1.0;
+      const double cj = (j == 0 || j == N) ? 2.0 : 1.0;
+      const double sgn = ((i + j) % 2 == 0) ? 1.0 : -1.0;
+      // t_i - t_j for t_j = -cos(pi j / N)
+      const double dif = 2.0 * std::sin(M_PI * (i + j) / (2.0 * N)) * std::sin(M_PI * (i - j) / (2.0 * N));
+      const double v = (ci / cj) * sgn / dif;
+      D[(size_t)i * n + j] = v;
+      rs += v;
+    }
+    D[(size_t)i * n + i] = -rs;
+  }
+  for (double& v : D) v *= 2.0 / L;
+}
+
+// 1-D reduced operator R D D L (m x m, m = N-1) for the boundary pair (blo, bhi)
+void reduced_1d(int N, double L, int blo, int bhi, std::vector<double>& A) {
+  const int n = N + 1, m = N - 1;
+  std::vector<double> D;
+  dense_D(N, L, D);
+  // lift: rows 0 and N of L as functions of the interior values
+  std::vector<double> l0(m, 0.0), lN(m, 0.0);
+  const double d00 = D[0], d0N = D[N], dN0 = D[(size_t)N * n], dNN = D[(size_t)N * n + N];
+  for (int j = 0; j < m; ++j) {
+    const double a = D[j + 1], b = D[(size_t)N * n + j + 1];
+    if (blo == 1 && bhi == 1) {
+      const double det = d00 * dNN - d0N * dN0;
+      l0[j] = -(dNN * a - d0N * b) / det;
+      lN[j] = -(d00 * b - dN0 * a) / det;
+    } else if (blo == 1) {
+      l0[j] = -a / d00;
+    } else if (bhi == 1) {
+      lN[j] = -b / dNN;
+    }
+  }
+  // DD
+  std::vector<double> D2((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double dik = D[(size_t)i * n + k];
+      if (dik == 0.0) continue;
+      for (int j = 0; j < n; ++j) D2[(size_t)i * n + j] += dik * D[(size_t)k * n + j];
+    }
+  A.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j)
+      A[(size_t)i * m + j] = D2[(size_t)(i + 1) * n + (j + 1)] + D2[(size_t)(i + 1) * n] * l0[j] +
+                             D2[(size_t)(i + 1) * n + N] * lN[j];
+}
+
+// Real nonsymmetric eigen-decomposition for matrices with real eigenvalues.
+// A (m x m row-major) is destroyed.  On success V holds unit eigenvectors as
+// columns and lam the eigenvalues; returns false if the QR iteration failed.
+bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
+  auto H = [&](int i, int j) -> double& { return A[(size_t)i * m + j]; };
+  std::vector<double> Z((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
+  auto Zm = [&](int i, int j) -> double& { return Z[(size_t)i * m + j]; };
+  // Householder reduction to upper Hessenberg form, accumulating Z
+  std::vector<double> v(m);
+  for (int k = 0; k + 2 < m; ++k) {
+    double alpha = 0.0;
+    for (int i = k + 1; i < m; ++i) alpha += H(i, k) * H(i, k);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    if (H(k + 1, k) > 0) alpha = -alpha;
+    for (int i = 0; i < m; ++i) v[i] = 0.0;
+    v[k + 1] = H(k + 1, k) - alpha;
+    for (int i = k + 2; i < m; ++i) v[i] = H(i, k);
+    double vn = 0.0;
+    for (int i = k + 1; i < m; ++i) vn += v[i] * v[i];
+    if (vn == 0.0) continue;
+    // H = P H P, P = I - 2 v v^T / vn
+    for (int j = 0; j < m; ++j) {
+      double s = 0.0;
+      for (int i = k + 1; i < m; ++i) s += v[i] * H(i, j);
+      s *= 2.0 / vn;
+      for (int i = k + 1; i < m; ++i) H(i, j) -= s * v[i];
+    }
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < m; ++j) s += H(i, j) * v[j];
+      s *= 2.0 / vn;
+      for (int j = k + 1; j < m; ++j) H(i, j) -= s * v[j];
+    }
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < m; ++j) s += Zm(i, j) * v[j];
+      s *= 2.0 / vn;
+      for (int j = k + 1; j < m; ++j) Zm(i, j) -= s * v[j];
+    }
+    for (int i = k + 2; i < m; ++i) H(i, k) = 0.0;
+  }
+  // implicit single-shift QR on the active window [lo, hi]
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1;
+  int iter = 0;
+  const int max_iter = 60 * m;
+  while (hi > 0) {
+    if (++iter > max_iter) return false;
+    int lo = hi;
+    while (lo > 0) {
+      const double s = std::fabs(H(lo - 1, lo - 1)) + std::fabs(H(lo, lo));
+      if (std::fabs(H(lo, lo - 1)) <= eps * (s > 0 ? s : 1.0)) {
+        H(lo, lo - 1) = 0.0;
+        break;
+      }
+      --lo;
+    }
+    if (lo == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    // Wilkinson shift from the trailing 2x2 block (real part if complex)
+    const double a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+    const double tr = 0.5 * (a - d);
+    const double disc = tr * tr + b * c;
+    double mu;
+    if (disc >= 0.0) {
+      const double sq = std::sqrt(disc);
+      mu = d - (b * c) / (tr + (tr >= 0 ? sq : -sq) + (tr == 0 && sq == 0 ? 1e-300 : 0.0));
+    } else {
+      mu = d + tr;  // real part of the complex pair
+    }
+    if (iter % 11 == 10) mu += std::fabs(H(hi, hi - 1));  // exceptional shift
+    double x = H(lo, lo) - mu, z = H(lo + 1, lo);
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
+      // rows k, k+1 (columns from max(lo, k-1) to m-1: full Schur form)
+      for (int j = std::max(lo, k - 1); j < m; ++j) {
+        const double h1 = H(k, j), h2 = H(k + 1, j);
+        H(k, j) = cs * h1 + sn * h2;
+        H(k + 1, j) = -sn * h1 + cs * h2;
+      }
+      // columns k, k+1 (rows 0 .. min(k+2, hi))
+      const int rmax = std::min(k + 2, hi);
+      for (int i = 0; i <= rmax; ++i) {
+        const double h1 = H(i, k), h2 = H(i, k + 1);
+        H(i, k) = cs * h1 + sn * h2;
+        H(i, k + 1) = -sn * h1 + cs * h2;
+      }
+      for (int i = 0; i < m; ++i) {
+        const double z1 = Zm(i, k), z2 = Zm(i, k + 1);
+        Zm(i, k) = cs * z1 + sn * z2;
+        Zm(i, k + 1) = -sn * z1 + cs * z2;
+      }
+      if (k + 1 < hi) {
+        x = H(k + 1, k);
+        z = H(k + 2, k);
+      }
+    }
+  }
+  lam.assign(m, 0.0);
+  for (int i = 0; i < m; ++i) lam[i] = H(i, i);
+  // eigenvectors of the triangular T by back-substitution, then V = Z Y
+  V.assign((size_t)m * m, 0.0);
+  std::vector<double> y(m);
+  double tnorm = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = i; j < m; ++j) tnorm = std::max(tnorm, std::fabs(H(i, j)));
+  const double small = eps * (tnorm > 0 ? tnorm : 1.0);
+  for (int k = 0; k < m; ++k) {
+    for (int i = 0; i < m; ++i) y[i] = 0.0;
+    y[k] = 1.0;
+    for (int j = k - 1; j >= 0; --j) {
+      double s = 0.0;
+      for (int l = j + 1; l <= k; ++l) s += H(j, l) * y[l];
+      double den = H(j, j) - lam[k];
+      if (std::fabs(den) < small) den = den >= 0 ? small : -small;
+      y[j] = -s / den;
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int l = 0; l <= k; ++l) s += Zm(i, l) * y[l];
+      V[(size_t)i * m + k] = s;
+      nrm += s * s;
+    }
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < m; ++i) V[(size_t)i * m + k] /= nrm;
+  }
+  return true;
+}
+
+// Gauss-Jordan inverse with partial pivoting (m x m row-major)
+bool invert(int m, const std::vector<double>& A, std::vector<double>& Ainv) {
+  std::vector<double> W(A);
+  Ainv.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Ainv[(size_t)i * m + i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(W[(size_t)r * m + c]) > std::fabs(W[(size_t)piv * m + c])) piv = r;
+    if (W[(size_t)piv * m + c] == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < m; ++j) {
+        std::swap(W[(size_t)piv * m + j], W[(size_t)c * m + j]);
+        std::swap(Ainv[(size_t)piv * m + j], Ainv[(size_t)c * m + j]);
+      }
+    const double inv = 1.0 / W[(size_t)c * m + c];
+    for (int j = 0; j < m; ++j) {
+      W[(size_t)c * m + j] *= inv;
+      Ainv[(size_t)c * m + j] *= inv;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = W[(size_t)r * m + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < m; ++j) {
+        W[(size_t)r * m + j] -= f * W[(size_t)c * m + j];
+        Ainv[(size_t)r * m + j] -= f * Ainv[(size_t)c * m + j];
+      }
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// device kernels
+// ---------------------------------------------------------------------------
+
+// D(i, c) = sum_k A(i, k) B(k, c) per batch, arbitrary element strides; one
+// wave computes a 16 x 64 tile with four 16x16 MFMA accumulators.
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  void* D;
+  int I, Kd, C;
+  long long a_si, a_sk, b_sk, b_sc, d_si, d_sc;
+  long long a_sb, b_sb, d_sb;  // batch strides
+};
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double __attribute__((ext_vector_type(4))) v4;
+  __device__ static v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // accumulator element r of lane l is row l/16 + 4 r (vector width 1)
+  __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef float __attribute__((ext_vector_type(4))) v4;
+  __device__ static v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // accumulator element r of lane l is row 4 (l/16) + r (vector width 4)
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_axis_gemm(GemmArgs g) {
+  typedef typename Mfma<T>::v4 v4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 16;
+  const int c0 = (blockIdx.y * 4 + wave) * 64;
+  const int b = blockIdx.z;
+  const T* A = (const T*)g.A + b * g.a_sb;
+  const T* B = (const T*)g.B + b * g.b_sb;
+  T* D = (T*)g.D + b * g.d_sb;
+  if (c0 >= g.C) return;
+  const int li = lane & 15, lk = lane >> 4;  // A operand: row li, k lk; B operand: k lk, column li
+  v4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4{0, 0, 0, 0};
+  const int ia = i0 + li;
+  for (int k0 = 0; k0 < g.Kd; k0 += 4) {
+    const int k = k0 + lk;
+    const T av = (ia < g.I && k < g.Kd) ? A[ia * g.a_si + k * g.a_sk] : T(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = c0 + t * 16 + li;
+      const T bv = (c < g.C && k < g.Kd) ? B[k * g.b_sk + c * g.b_sc] : T(0);
+      acc[t] = Mfma<T>::mac(av, bv, acc[t]);
+    }
+  }
+  // lane holds column lane%16 of each 16x16 block; rows per Mfma<T>::row
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = c0 + t * 16 + li;
+    if (c >= g.C) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + Mfma<T>::row(lk, r);
+      if (i < g.I) D[i * g.d_si + c * g.d_sc] = acc[t][r];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_pack_interior(const T* __restrict__ in, T* __restrict__ out, int n0, int n1, int n2) {
+  const int m0 = n0 - 2, m1 = n1 - 2, m2 = n2 - 2;
+  const size_t tot = (size_t)m0 * m1 * m2;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % m2);
+    const size_t r = t / m2;
+    const int j = (int)(r % m1), i = (int)(r / m1);
+    out[t] = in[((size_t)(i + 1) * n1 + (j + 1)) * n2 + (k + 1)];
+  }
+}
+
+template <typename T>
+__global__ void k_unpack_interior(const T* __restrict__ in, T* __restrict__ out, int n0, int n1, int n2) {
+  const size_t tot = (size_t)n0 * n1 * n2;
+  const int m1 = n1 - 2, m2 = n2 - 2;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % n2);
+    const size_t r = t / n2;
+    const int j = (int)(r % n1), i = (int)(r / n1);
+    T v = T(0);
+    if (i > 0 && i < n0 - 1 && j > 0 && j < n1 - 1 && k > 0 && k < n2 - 1)
+      v = in[((size_t)(i - 1) * m1 + (j - 1)) * m2 + (k - 1)];
+    out[t] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_eig_scale(T* x, const T* lx, const T* ly, const T* lz, double inv_k, int m0, int m1, int m2) {
+  const size_t tot = (size_t)m0 * m1 * m2;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % m2);
+    const size_t r = t / m2;
+    const int j = (int)(r % m1), i = (int)(r / m1);
+    x[t] = T(double(x[t]) * inv_k / (double(lx[i]) + double(ly[j]) + double(lz[k])));
+  }
+}
+
+inline int grid1(size_t n) {
+  size_t g = (n + 1023) / 1024;
+  return (int)std::max<size_t>(1, std::min<size_t>(g, 8192));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan-level setup and application
+// ---------------------------------------------------------------------------
+int precond_setup(cheb_plan* p) {
+  if (p->pc_ready) return CHEB_OK;
+  size_t off64 = 0;
+  std::vector<double> host;
+  PrecondAxis ax[3];
+  for (int a = 0; a < 3; ++a) {
+    const int N = p->ax[a].N, m = N - 1;
+    std::vector<double> A, lam, V, Vi;
+    reduced_1d(N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], A);
+    if (!eig_real(m, A, lam, V) || !invert(m, V, Vi)) {
+      set_error("preconditioner setup: eigen-decomposition failed");
+      return CHEB_ERR_UNSUPPORTED;
+    }
+    ax[a].m = m;
+    ax[a].off_V = off64;
+    host.insert(host.end(), V.begin(), V.end());
+    off64 += (size_t)m * m;
+    ax[a].off_Vi = off64;
+    host.insert(host.end(), Vi.begin(), Vi.end());
+    off64 += (size_t)m * m;
+    ax[a].off_lam = off64;
+    host.insert(host.end(), lam.begin(), lam.end());
+    off64 += (size_t)m;
+  }
+  std::vector<float> host32(host.size());
+  for (size_t i = 0; i < host.size(); ++i) host32[i] = float(host[i]);
+  int rc = hip_check(hipMalloc((void**)&p->pc64, host.size() * sizeof(double)), "hipMalloc(preconditioner)");
+  if (!rc) rc = hip_check(hipMalloc((void**)&p->pc32, host.size() * sizeof(float)), "hipMalloc(preconditioner)");
+  if (!rc)
+    rc = hip_check(hipMemcpy(p->pc64, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice),
+                   "hipMemcpy(preconditioner)");
+  if (!rc)
+    rc = hip_check(hipMemcpy(p->pc32, host32.data(), host32.size() * sizeof(float), hipMemcpyHostToDevice),
+                   "hipMemcpy(preconditioner)");
+  if (rc) return rc;
+  for (int a = 0; a < 3; ++a) p->pc_ax[a] = ax[a];
+  p->pc_ready = 1;
+  return CHEB_OK;
+}
+
+template <typename T>
+static const T* pc_base(const cheb_plan* p);
+template <>
+const double* pc_base<double>(const cheb_plan* p) { return p->pc64; }
+template <>
+const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
+
+// Y = M applied along `axis` of the packed block X (m0, m1, m2); trans uses M^T
+template <typename T>
+static int axis_contract(const T* M, bool trans, int axis, const int* m, const T* X, T* Y, hipStream_t s) {
+  GemmArgs g;
+  const long long msz = m[axis];
+  const long long ms_i = trans ? 1 : msz, ms_k = trans ? msz : 1;  // M(i,k) strides
+  if (axis == 2) {
+    // Y[r, i] = sum_k X[r, k] M[i, k]: rows r, columns i
+    g.A = X; g.B = M; g.D = Y;
+    g.I = m[0] * m[1]; g.Kd = m[2]; g.C = m[2];
+    g.a_si = m[2]; g.a_sk = 1;
+    g.b_sk = ms_k; g.b_sc = ms_i;
+    g.d_si = m[2]; g.d_sc = 1;
+    g.a_sb = g.b_sb = g.d_sb = 0;
+    dim3 grid((g.I + 15) / 16, (g.C + 255) / 256, 1);
+    hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+  } else {
+    // Y_b = M X_b with X_b (m_axis x C), C = product of the later dims
+    const int C = axis == 0 ? m[1] * m[2] : m[2];
+    const int batch = axis == 0 ? 1 : m[0];
+    g.A = M; g.B = X; g.D = Y;
+    g.I = m[axis]; g.Kd = m[axis]; g.C = C;
+    g.a_si = ms_i; g.a_sk = ms_k;
+    g.b_sk = C; g.b_sc = 1;
+    g.d_si = C; g.d_sc = 1;
+    g.a_sb = 0;
+    g.b_sb = g.d_sb = (long long)m[axis] * C;
+    dim3 grid((g.I + 15) / 16, (C + 255) / 256, batch);
+    hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+  }
+  return hip_check(hipGetLastError(), "axis contraction");
+}
+
+template <typename T>
+int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, double kc, bool transpose,
+                  hipStream_t s) {
+  const int n0 = p->g.n[0], n1 = p->g.n[1], n2 = p->g.n[2];
+  const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
+  const size_t tot = (size_t)m[0] * m[1] * m[2];
+  const T* base = pc_base<T>(p);
+  auto V = [&](int a) { return base + p->pc_ax[a].off_V; };
+  auto Vi = [&](int a) { return base + p->pc_ax[a].off_Vi; };
+  hipLaunchKernelGGL(k_pack_interior<T>, dim3(grid1(tot)), dim3(256), 0, s, in, bufA, n0, n1, n2);
+  int rc = hip_check(hipGetLastError(), "pack");
+  if (rc) return rc;
+  // forward: V^{-1} (or V^T for the transpose) along x, y, z
+  T* x = bufA;
+  T* y = bufB;
+  for (int a = 0; a < 3 && !rc; ++a) {
+    rc = transpose ? axis_contract<T>(V(a), true, a, m, x, y, s) : axis_contract<T>(Vi(a), false, a, m, x, y, s);
+    std::swap(x, y);
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_eig_scale<T>, dim3(grid1(tot)), dim3(256), 0, s, x, base + p->pc_ax[0].off_lam,
+                     base + p->pc_ax[1].off_lam, base + p->pc_ax[2].off_lam, 1.0 / kc, m[0], m[1], m[2]);
+  rc = hip_check(hipGetLastError(), "eigen scale");
+  for (int a = 2; a >= 0 && !rc; --a) {
+    rc = transpose ? axis_contract<T>(Vi(a), true, a, m, x, y, s) : axis_contract<T>(V(a), false, a, m, x, y, s);
+    std::swap(x, y);
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_unpack_interior<T>, dim3(grid1((size_t)n0 * n1 * n2)), dim3(256), 0, s, x, out, n0, n1, n2);
+  return hip_check(hipGetLastError(), "unpack");
+}
+
+// plain GEMM on the matrix cores, exposed for the layout test:
+// D (I x C) = A (I x K) B (K x C), all row-major
+template <typename T>
+int mfma_gemm(const T* A, const T* B, T* D, int I, int K, int C, hipStream_t s) {
+  GemmArgs g;
+  g.A = A; g.B = B; g.D = D;
+  g.I = I; g.Kd = K; g.C = C;
+  g.a_si = K; g.a_sk = 1; g.b_sk = C; g.b_sc = 1; g.d_si = C; g.d_sc = 1;
+  g.a_sb = g.b_sb = g.d_sb = 0;
+  dim3 grid((I + 15) / 16, (C + 255) / 256, 1);
+  hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+  return hip_check(hipGetLastError(), "mfma gemm");
+}
+
+template int precond_apply<double>(const cheb_plan*, const double*, double*, double*, double*, double, bool,
+                                   hipStream_t);
+template int precond_apply<float>(const cheb_plan*, const float*, float*, float*, float*, double, bool,
+                                  hipStream_t);
+template int mfma_gemm<double>(const double*, const double*, double*, int, int, int, hipStream_t);
+template int mfma_gemm<float>(const float*, const float*, float*, int, int, int, hipStream_t);
+
+}  // namespace cheb
+
+using namespace cheb;
+
+extern "C" int cheb_debug_gemm(int32_t precision, const void* A, const void* B, void* D, int32_t I, int32_t K,
+                               int32_t C, void* stream) {
+  if (!A || !B || !D || I <= 0 || K <= 0 || C <= 0) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (precision == CHEB_F32)
+    return mfma_gemm<float>((const float*)A, (const float*)B, (float*)D, I, K, C, (hipStream_t)stream);
+  return mfma_gemm<double>((const double*)A, (const double*)B, (double*)D, I, K, C, (hipStream_t)stream);
+}

@@ -38,6 +38,7 @@ struct SolveParams {
   double ir_rtol;
   int ir_max;
   bool warm;
+  bool precond;
   double* hist;
   int hist_len;
 };
@@ -52,6 +53,7 @@ SolveParams params_from(const cheb_solve_opts* o) {
   s.ir_rtol = (o && o->ir_inner_rtol > 0) ? o->ir_inner_rtol : 1e-3;
   s.ir_max = (o && o->ir_max_outer > 0) ? o->ir_max_outer : 50;
   s.warm = o && (o->flags & 1);
+  s.precond = o && (o->flags & 2);
   s.hist = o ? o->history : nullptr;
   s.hist_len = o ? o->history_len : 0;
   return s;
@@ -59,10 +61,13 @@ SolveParams params_from(const cheb_solve_opts* o) {
 
 template <typename T>
 struct KrylovWS {
-  T* V = nullptr;  // m + k + 1 basis vectors
-  T* Z = nullptr;  // k augmentation vectors
-  T* w = nullptr;  // work vector
-  size_t ld = 0;   // elements between vectors
+  T* V = nullptr;   // m + k + 1 basis vectors
+  T* Z = nullptr;   // k augmentation vectors
+  T* w = nullptr;   // work vector
+  T* wp = nullptr;  // preconditioned search direction (only with a preconditioner)
+  T* pa = nullptr;  // packed-interior scratch of the preconditioner
+  T* pb = nullptr;
+  size_t ld = 0;    // elements between vectors
   int m = 0, k = 0;
 };
 
@@ -74,13 +79,20 @@ struct Scratch {
 };
 
 template <typename T>
-void carve_krylov(Carver& c, size_t npts, int m, int k, KrylovWS<T>& kw) {
+void carve_krylov(Carver& c, const cheb_plan* p, int m, int k, bool prec, KrylovWS<T>& kw) {
+  const size_t npts = p->npts;
   kw.ld = round_up(npts * sizeof(T), 256) / sizeof(T);
   kw.m = m;
   kw.k = k;
   kw.V = c.take<T>(kw.ld * (m + k + 1));
   kw.Z = c.take<T>(kw.ld * (k > 0 ? k : 1));
   kw.w = c.take<T>(kw.ld);
+  if (prec) {
+    const size_t inner = (size_t)(p->g.n[0] - 2) * (p->g.n[1] - 2) * (p->g.n[2] - 2);
+    kw.wp = c.take<T>(kw.ld);
+    kw.pa = c.take<T>(inner);
+    kw.pb = c.take<T>(inner);
+  }
 }
 
 void carve_scratch(Carver& c, size_t npts, int maxv, Scratch& s) {
@@ -124,10 +136,15 @@ int vnorm(cheb_plan* p, const T* v, Scratch& s, double* out) {
 // stall > 0: stop with CHEB_STAGNATED when a restart cycle reduces the true
 // residual by less than that factor (used by the FP32 inner solves, whose
 // attainable accuracy is bounded by the FP32 operator).
-template <typename T, typename ApplyFn>
+struct NoPrec {
+  template <typename T>
+  int operator()(const T*, T*) const { return CHEB_OK; }
+};
+
+template <typename T, typename ApplyFn, typename PrecFn = NoPrec>
 int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_abs, int maxmv,
            KrylovWS<T>& kw, Scratch& sc, Stats& st, double* resid_out, double bnorm, double* hist,
-           int hist_len, double stall = 0.0) {
+           int hist_len, double stall = 0.0, bool use_prec = false, PrecFn&& Mi = PrecFn()) {
   const size_t npts = p->npts;
   hipStream_t s = p->stream;
   const int m = kw.m, kmax = kw.k;
@@ -169,6 +186,11 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
     int jend = 0;
     for (int j = 0; j < jmax; ++j) {
       const T* u = j < m ? kw.V + (size_t)j * kw.ld : kw.Z + (size_t)zslot[j - m] * kw.ld;
+      if (use_prec) {
+        rc = Mi(u, kw.wp);  // right preconditioning: search direction M^{-1} u
+        if (rc) return rc;
+        u = kw.wp;
+      }
       rc = A(u, w);
       if (rc) return rc;
       st.matvecs++;
@@ -251,7 +273,12 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
       rc = lincomb<T>(kw.Z + (size_t)zslot[i - m] * kw.ld, kw.ld, 1, sc.coef + i, w, 1, npts, s);
       if (rc) return rc;
     }
-    rc = axpby<T>(x, w, 1.0, 1.0, npts, s);
+    if (use_prec) {
+      rc = Mi(w, kw.wp);
+      if (!rc) rc = axpby<T>(x, kw.wp, 1.0, 1.0, npts, s);
+    } else {
+      rc = axpby<T>(x, w, 1.0, 1.0, npts, s);
+    }
     if (rc) return rc;
     if (kmax > 0) {
       // store the correction as the newest augmentation vector
@@ -302,7 +329,7 @@ size_t carve64(cheb_plan* p, const SolveParams& sp, char* base, SolveWS64& w) {
   w.t1 = c.take<double>(p->npts);
   w.t2 = c.take<double>(p->npts);
   w.t3 = c.take<double>(p->npts);
-  carve_krylov<double>(c, p->npts, sp.m, sp.k, w.kw);
+  carve_krylov<double>(c, p, sp.m, sp.k, sp.precond, w.kw);
   carve_scratch(c, p->npts, sp.m + sp.k + 2, w.sc);
   return c.off;
 }
@@ -314,7 +341,7 @@ size_t carve32(cheb_plan* p, const SolveParams& sp, char* base, SolveWS32& w) {
   w.K = nullptr;
   w.f = nullptr;
   w.g = nullptr;
-  carve_krylov<float>(c, p->npts, sp.m, sp.k, w.kw);
+  carve_krylov<float>(c, p, sp.m, sp.k, sp.precond, w.kw);
   carve_scratch(c, p->npts, sp.m + sp.k + 2, w.sc);
   return c.off;
 }
@@ -328,7 +355,7 @@ size_t carve_mixed(cheb_plan* p, const SolveParams& sp, char* base, MixedWS& w) 
   w.K32 = c.take<float>(p->npts);
   w.b32 = c.take<float>(p->npts);
   w.d32 = c.take<float>(p->npts);
-  carve_krylov<float>(c, p->npts, sp.m, sp.k, w.kw);
+  carve_krylov<float>(c, p, sp.m, sp.k, sp.precond, w.kw);
   carve_scratch(c, p->npts, sp.m + sp.k + 2, w.sc);
   return c.off;
 }
@@ -375,6 +402,18 @@ int reduced_rhs(cheb_plan* p, const T* K, const T* f, const T* g, T* bt, T* tmp)
 }
 
 // FP64 (or FP32) plain LGMRES solve of the reduced system; x holds interior values.
+// mean of K (scale of the preconditioner's constant-coefficient operator)
+template <typename T>
+int mean_K(cheb_plan* p, const T* K, Scratch& sc, double* kc) {
+  int rc = vsum<T>(K, p->npts, sc.partials, sc.dots, p->stream);
+  if (rc) return rc;
+  double sum;
+  rc = readback(p, sc.dots, 1, &sum);
+  if (rc) return rc;
+  *kc = sum / double(p->npts);
+  return CHEB_OK;
+}
+
 template <typename T>
 int solve_plain(cheb_plan* p, const T* K, const T* bt, T* x, T* r, KrylovWS<T>& kw, Scratch& sc,
                 const SolveParams& sp, int mode, Stats& st, double* relres, int* status) {
@@ -390,8 +429,17 @@ int solve_plain(cheb_plan* p, const T* K, const T* bt, T* x, T* r, KrylovWS<T>& 
     *status = CHEB_OK;
     return rc;
   }
+  double kc = 1.0;
+  if (sp.precond) {
+    rc = precond_setup(p);
+    if (!rc) rc = mean_K<T>(p, K, sc, &kc);
+    if (rc) return rc;
+  }
+  auto Mi = [&](const T* in, T* out) {
+    return precond_apply<T>(p, in, out, kw.pa, kw.pb, kc, mode == 2, p->stream);
+  };
   const int r2 = lgmres<T>(p, A, bt, x, !sp.warm, tol, sp.maxiter, kw, sc, st, &res, bnorm, sp.hist,
-                           sp.hist_len);
+                           sp.hist_len, 0.0, sp.precond, Mi);
   if (r2 < 0) return r2;
   *status = r2;
   // final true residual
@@ -507,6 +555,14 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
     const double tol = std::fmax(sp.rtol * bnorm, sp.atol);
     auto A64 = [&](const double* in, double* out) { return apply_t<double>(p, Kd, in, out, 1, p->stream); };
     auto A32 = [&](const float* in, float* out) { return apply_t<float>(p, w.K32, in, out, 1, p->stream); };
+    double kc = 1.0;
+    if (!rc && sp.precond) {
+      rc = precond_setup(p);
+      if (!rc) rc = mean_K<double>(p, Kd, w.sc, &kc);
+    }
+    auto M32 = [&](const float* in, float* out) {
+      return precond_apply<float>(p, in, out, w.kw.pa, w.kw.pb, kc, false, p->stream);
+    };
     double prev = HUGE_VAL;
     int slow = 0;
     status = CHEB_NOT_CONVERGED;
@@ -545,7 +601,7 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
       const int cap = 40 * (sp.m + sp.k + 1);
       if (budget > cap) budget = cap;
       const int r2 = lgmres<float>(p, A32, w.b32, w.d32, true, sp.ir_rtol, budget > 1 ? budget : 1, w.kw,
-                                   w.sc, si, &res32, 1.0, nullptr, 0, 0.9);
+                                   w.sc, si, &res32, 1.0, nullptr, 0, sp.precond ? 0.0 : 0.9, sp.precond, M32);
       if (r2 < 0) {
         rc = r2;
         break;

@@ -1,0 +1,87 @@
+"""The fast-diagonalisation preconditioner (an extension of the paper's plain
+LGMRES): its MFMA contraction kernel, exactness for constant K, and parity of
+preconditioned FP64 / mixed / adjoint solves with the oracle."""
+import numpy as np
+import pytest
+
+from oracle import cheb_oracle as O
+from paper_2606_21410_amd import workloads as W
+from tests.gpu_util import log, rel_l2, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape", [(16, 4, 16), (37, 29, 70), (127, 127, 300), (5, 130, 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mfma_gemm_layout(shape, prec):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import debug_gemm
+    I, K, C = shape
+    r = np.random.default_rng(I * 1000 + K)
+    A = r.standard_normal((I, K))
+    B = r.standard_normal((K, C))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    D = to_host(debug_gemm(to_dev(A, dt), to_dev(B, dt)))
+    ref = A.astype(np.float32 if prec == "f32" else np.float64).astype(np.float64) @ \
+        B.astype(np.float32 if prec == "f32" else np.float64).astype(np.float64)
+    assert rel_l2(D, ref) <= (1e-14 if prec == "f64" else 2e-6)
+
+
+def test_precond_exact_for_constant_K():
+    """Constant K: the preconditioner is the exact inverse of the reduced operator,
+    so LGMRES converges in one or two applications."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    P = W.manufactured_sincos(17)
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+    K = np.full(P.grid.n, 2.5)
+    plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    u, info = plan.solve(d(K), d(P.f), d(P.g), opts=SolveOptions(rtol=1e-12, precond=True))
+    log(f"precond const K: {info}")
+    assert info["status"] == 0 and info["matvecs"] <= 4
+    uref = O.solve(G, K, P.f, P.g)
+    assert np.max(np.abs(to_host(u) - uref)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed", "f32"])
+def test_precond_two_phase_33(prec):
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    P = W.two_phase_problem(33, seed=1002, n_finest=129)
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+    uref = O.solve(G, P.K, P.f, P.g, tol=1e-14)
+    plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, prec)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    rtol = 1e-6 if prec == "f32" else 1e-13
+    u, info = plan.solve(to_dev(P.K, dt), to_dev(P.f, dt), to_dev(P.g, dt),
+                         opts=SolveOptions(rtol=rtol, precond=True))
+    e = rel_l2(to_host(u), uref)
+    log(f"precond {prec}: {info} err {e:.3e}")
+    assert info["status"] == 0
+    assert info["matvecs"] < 400
+    assert e <= (1e-3 if prec == "f32" else 1e-9)
+
+
+def test_precond_adjoint_vs_dense():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    n = (9, 9, 9)
+    bc = W.MIXED_X_BC
+    LO, HI = (0, 0, 0), (1, 1, 1)
+    G = O.Grid3(n, LO, HI, bc)
+    K = W.random_conductivity(n, 51, 0.5)
+    f = W.random_field(n, 52)
+    g = W.random_faces(W.Grid(n, LO, HI, bc), 53)
+    U = O.solve_dense(G, K, f, g)
+    t = W.random_field(n, 54)
+    _, g_ref = O.adjoint_dense(G, K, U, U - t)
+    plan = Plan(n, LO, HI, bc, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    _, grad, info = plan.adjoint(d(K), d(U), d(U - t), SolveOptions(rtol=1e-13, precond=True))
+    assert info["status"] == 0
+    assert rel_l2(to_host(grad), g_ref) <= 1e-9

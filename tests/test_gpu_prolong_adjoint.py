@@ -67,41 +67,64 @@ def test_adjoint_vs_dense_oracle(bc):
     assert rel_l2(to_host(lam)[G.interior], lam_ref[G.interior]) <= 1e-9
 
 
-def test_adjoint_finite_differences_33():
-    """dL/dlogK against central differences of the GPU forward solve on random
-    node directions (h = 1e-6, FP64)."""
-    require_gpu()
+def _fd_check(n, ndir, hs, seed_k=1005, seed_t=1006, seed_v=1007):
+    """Central differences of L = 1/2 ||u - t||^2 along random node directions
+    against <dL/dlogK, v>.  ``hs`` maps each step h to its relative bar.
+    L(+h) - L(-h) is formed as 1/2 sum (u+ - u-)(u+ + u- - 2t), which avoids
+    cancelling two O(n) sums.  The forward solves are preconditioned and run to
+    the FP64 floor, whose O(kappa u_64) error in u sets the noise of the
+    difference quotient: ~ ||u - t|| ||du|| / (2h)."""
     import torch
     from paper_2606_21410_amd.api import Plan, SolveOptions
-    n = (33, 33, 33)
     bc = W.MIXED_X_BC
     grid = W.Grid(n, (0, 0, 0), (1, 1, 1), bc)
-    logK = np.log(W.lognormal_conductivity(grid, 1005, 1.0, 0.2))
-    t = np.exp(0.5 * W.gaussian_field_rff(grid, 1006, 0.3))
+    logK = np.log(W.lognormal_conductivity(grid, seed_k, 1.0, 0.2))
+    t = np.exp(0.5 * W.gaussian_field_rff(grid, seed_t, 0.3))
     g = W.dirichlet_x_faces(grid, -1.0, 1.0)
     f = np.zeros(n)
     plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
     d = lambda a: to_dev(a, torch.float64)
-    opts = SolveOptions(rtol=1e-14, maxiter=20000)
+    opts = SolveOptions(rtol=1e-15, maxiter=4000, precond=True)
 
-    def loss(lk):
-        u, info = plan.solve(d(np.exp(lk)), d(f), d(g), opts=opts)
-        uh = to_host(u)
-        return 0.5 * np.sum((uh - t) ** 2), uh
+    def solve(lk, u0=None):
+        u, info = plan.solve(d(np.exp(lk)), d(f), d(g), u0=u0, opts=opts)
+        assert info["status"] in (0, 2), info
+        return u
 
-    L0, U = loss(logK)
+    Ud = solve(logK)
+    U = to_host(Ud)
     _, grad, _ = plan.adjoint(d(np.exp(logK)), d(U), d(U - t), opts)
     gh = to_host(grad)
-    r = np.random.default_rng(1007)
-    h = 1e-6
-    for s in range(3):
-        v = r.standard_normal(n)
-        Lp, _ = loss(logK + h * v)
-        Lm, _ = loss(logK - h * v)
-        fd = (Lp - Lm) / (2 * h)
-        ad = float(np.sum(gh * v))
-        log(f"  FD {fd:.10e} adjoint {ad:.10e}")
-        assert abs(fd - ad) <= 1e-5 * abs(ad)
+    r = np.random.default_rng(seed_v)
+    vs = [r.standard_normal(n) for _ in range(ndir)]
+    for h, bar in hs.items():
+        worst = 0.0
+        for s, v in enumerate(vs):
+            up = to_host(solve(logK + h * v, Ud))
+            um = to_host(solve(logK - h * v, Ud))
+            fd = 0.5 * np.sum((up - um) * (up + um - 2.0 * t)) / (2 * h)
+            ad = float(np.sum(gh * v))
+            rel = abs(fd - ad) / abs(ad)
+            worst = max(worst, rel)
+            log(f"  n={n[0]} h={h:g} dir {s}: FD {fd:.12e} adjoint {ad:.12e} rel {rel:.2e}")
+        assert worst <= bar, (h, worst)
+
+
+def test_adjoint_finite_differences_33():
+    """dL/dlogK against central differences (h = 1e-6, FP64) at 33^3."""
+    require_gpu()
+    _fd_check((33, 33, 33), 4, {1e-6: 1e-5})
+
+
+def test_adjoint_finite_differences_129():
+    """The adjoint-sensitivity workload: 129^3, log-normal K (sigma 1, l 0.2),
+    target from a log-normal field (sigma 0.5, l 0.3), 8 random node directions.
+    With h = 1e-6 the FP64 solve floor (relative error ~1e-13 in u, |u - t| ~
+    1e3) leaves difference-quotient noise of a few 1e-4 relative, so that step
+    gets a 2e-3 bar; h = 1e-4 moves the noise to ~1e-6 while the O(h^2)
+    truncation stays ~1e-8, and is held to the 1e-5 agreement bar."""
+    require_gpu()
+    _fd_check((129, 129, 129), 8, {1e-4: 1e-5, 1e-6: 2e-3})
 
 
 def test_autograd_function():
