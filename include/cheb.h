@@ -73,6 +73,11 @@ extern "C" {
 #define CHEB_APPLY_REDUCED 1u   /* y = (A_kk + A_kr G) u_k on interior nodes, 0 on boundary nodes */
 #define CHEB_APPLY_TRANSPOSE 2u /* with REDUCED: y = (A_kk + A_kr G)^T u_k */
 
+/* operator route of the reduced apply and its transpose (cheb_plan_set_route) */
+#define CHEB_ROUTE_AUTO 0   /* matrix-core route on axes with N in {16,32,48,64,96,128}, FFT route elsewhere */
+#define CHEB_ROUTE_FFT 1    /* DCT-I through the FFT of the even extension on every axis */
+#define CHEB_ROUTE_MATRIX 2 /* matrix-core route wherever N allows it (as AUTO) */
+
 typedef struct cheb_grid {
   int32_t n[3];  /* nodes per axis, 3 <= n <= 513 */
   double lo[3];  /* box lower corner */
@@ -127,6 +132,20 @@ int cheb_plan_set_workspace(cheb_plan* plan, void* dev_ptr, size_t bytes);
 
 /* Change the stream subsequent calls enqueue on. */
 int cheb_plan_set_stream(cheb_plan* plan, void* stream);
+
+/* Choose how the reduced operator and its transpose evaluate the per-axis
+ * derivatives (Section 2.2 defines the derivative; both routes compute it):
+ *   CHEB_ROUTE_FFT    -- the DCT-I of each pencil through the FFT of its even
+ *                        extension, coefficient recurrence, back-transform
+ *                        (Algorithm 1 / Section 2.2), any N;
+ *   CHEB_ROUTE_MATRIX -- for N in {16, 32, 48, 64, 96, 128}: the derivative as a
+ *                        dense contraction with the collocation matrix on the
+ *                        matrix cores (even-odd split), other axes use the FFT;
+ *   CHEB_ROUTE_AUTO   -- the default; currently identical to CHEB_ROUTE_MATRIX.
+ * The two routes agree to rounding.  FULL applies, derivatives and the adjoint
+ * gradient always use the FFT route.  Returns CHEB_ERR_INVALID_ARG for an
+ * unknown route. */
+int cheb_plan_set_route(cheb_plan* plan, int32_t route);
 
 int cheb_plan_destroy(cheb_plan* plan);
 

@@ -25,6 +25,7 @@ CHEB_ERR_UNSUPPORTED = -6
 CHEB_F64, CHEB_F32, CHEB_MIXED = 0, 1, 2
 CHEB_DIRICHLET, CHEB_NEUMANN = 0, 1
 CHEB_APPLY_FULL, CHEB_APPLY_REDUCED, CHEB_APPLY_TRANSPOSE = 0, 1, 2
+CHEB_ROUTE_AUTO, CHEB_ROUTE_FFT, CHEB_ROUTE_MATRIX = 0, 1, 2
 
 
 class cheb_grid(ctypes.Structure):
@@ -58,6 +59,7 @@ _SIGS = {
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "cheb_plan_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "cheb_plan_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "cheb_plan_set_route": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cheb_plan_destroy": (ctypes.c_int, [_vp]),
     "cheb_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_uint32]),
     "cheb_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(cheb_solve_opts),

@@ -48,11 +48,14 @@ class SolveOptions:
         return o, hist
 
 
+_ROUTE = {"auto": L.CHEB_ROUTE_AUTO, "fft": L.CHEB_ROUTE_FFT, "matrix": L.CHEB_ROUTE_MATRIX}
+
+
 class Plan:
     """One grid: sizes, box, face types, precision ('f64', 'f32', 'mixed')."""
 
     def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0,) * 6, precision="f64",
-                 device="cuda"):
+                 device="cuda", route: str = "auto"):
         self.lib = L.load()
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
@@ -72,6 +75,12 @@ class Plan:
                                           ctypes.byref(self._h)))
         self._ws = None
         self._ws_bytes = 0
+        self.set_route(route)
+
+    def set_route(self, route: str):
+        """'auto', 'fft' or 'matrix': how the reduced operator evaluates the per-axis derivatives."""
+        L.check(self.lib.cheb_plan_set_route(self._h, _ROUTE[route]))
+        self.route = route
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

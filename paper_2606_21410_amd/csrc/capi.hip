@@ -173,6 +173,7 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
   if (!rc)
     rc = hip_check(hipMemcpy(p->dconst32, h32.data(), cnt * sizeof(float), hipMemcpyHostToDevice),
                    "hipMemcpy(plan constants)");
+  if (!rc) rc = dense_setup(p);
   p->hpinned_len = 4096;
   if (!rc)
     rc = hip_check(hipHostMalloc((void**)&p->hpinned, p->hpinned_len * sizeof(double), hipHostMallocDefault),
@@ -180,6 +181,9 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
   if (rc) {
     if (p->dconst64) (void)hipFree(p->dconst64);
     if (p->dconst32) (void)hipFree(p->dconst32);
+    if (p->dd64) (void)hipFree(p->dd64);
+    if (p->dd32) (void)hipFree(p->dd32);
+    if (p->dsink) (void)hipFree(p->dsink);
     if (p->hpinned) (void)hipHostFree(p->hpinned);
     delete p;
     return rc;
@@ -211,10 +215,26 @@ int cheb_plan_set_stream(cheb_plan* plan, void* stream) {
   return CHEB_OK;
 }
 
+int cheb_plan_set_route(cheb_plan* plan, int32_t route) {
+  if (!plan) {
+    set_error("null plan");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (route != CHEB_ROUTE_AUTO && route != CHEB_ROUTE_FFT && route != CHEB_ROUTE_MATRIX) {
+    set_error("route must be CHEB_ROUTE_AUTO, CHEB_ROUTE_FFT or CHEB_ROUTE_MATRIX");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  plan->route = route;
+  return CHEB_OK;
+}
+
 int cheb_plan_destroy(cheb_plan* plan) {
   if (!plan) return CHEB_OK;
   if (plan->dconst64) (void)hipFree(plan->dconst64);
   if (plan->dconst32) (void)hipFree(plan->dconst32);
+  if (plan->dd64) (void)hipFree(plan->dd64);
+  if (plan->dd32) (void)hipFree(plan->dd32);
+  if (plan->dsink) (void)hipFree(plan->dsink);
   if (plan->hpinned) (void)hipHostFree(plan->hpinned);
   if (plan->pc64) (void)hipFree(plan->pc64);
   if (plan->pc32) (void)hipFree(plan->pc32);

@@ -1,0 +1,9 @@
+// Matrix-core axis pass (FP32 instantiation).
+#include "dense_launch.h"
+
+namespace cheb {
+
+template int launch_dense_pass<float>(const cheb_plan*, int, int, int, const float*, const float*, float*,
+                                      hipStream_t);
+
+}  // namespace cheb

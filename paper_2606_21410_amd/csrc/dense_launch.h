@@ -1,0 +1,97 @@
+// Instantiation and dispatch of the matrix-core axis pass for one precision.
+#pragma once
+
+#include "dense_pass.h"
+#include "internal.h"
+
+namespace cheb {
+
+// Persistent launch: as many workgroups as the device holds at once (resident
+// workgroups per CU x CUs, queried once per kernel), at most one per tile.
+template <typename T, int NC, int MODE, bool FIRST>
+static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
+  constexpr DenseDims S = dense_dims(NC);
+  constexpr int lds = dense_lds_bytes<T>(NC);
+  static_assert(lds <= 160 * 1024, "matrix-core tile exceeds LDS");
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (!rc && lds > 64 * 1024)
+      rc = hip_check(hipFuncSetAttribute((const void*)k_dense_pass<T, NC, MODE, FIRST>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds),
+                     "matrix-core pass LDS attribute");
+    if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (!rc)
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_dense_pass<T, NC, MODE, FIRST>,
+                                                                  64 * S.NW, lds),
+                     "occupancy query");
+    if (rc) return rc;
+    resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const int ta = a.axis == 0 ? a.n[1] : a.n[0], tb = a.axis == 2 ? a.n[1] : a.n[2];
+  const int tiles = ((ta - 2) * (tb - 2) + S.C - 1) / S.C;
+  const int grid = tiles < resident ? (tiles > 0 ? tiles : 1) : resident;
+  hipLaunchKernelGGL((k_dense_pass<T, NC, MODE, FIRST>), dim3(grid), dim3(64 * S.NW), lds, s, a);
+  return hip_check(hipGetLastError(), "matrix-core pass launch");
+}
+
+template <typename T, int NC>
+static int launch_dense_n(const DenseArgs<T>& a, int transpose, hipStream_t s) {
+  if (a.first)
+    return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, true>(a, s)
+                     : launch_dense_inst<T, NC, DENSE_REDUCED, true>(a, s);
+  return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, false>(a, s)
+                   : launch_dense_inst<T, NC, DENSE_REDUCED, false>(a, s);
+}
+
+template <typename T>
+static const T* dense_tab(const cheb_plan* p, int axis, int transpose);
+template <>
+inline const double* dense_tab<double>(const cheb_plan* p, int axis, int transpose) {
+  return p->dd64 + p->dd_off[axis][transpose];
+}
+template <>
+inline const float* dense_tab<float>(const cheb_plan* p, int axis, int transpose) {
+  return p->dd32 + p->dd_off[axis][transpose];
+}
+
+template <typename T>
+int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
+                      hipStream_t s) {
+  DenseArgs<T> a;
+  a.u = u;
+  a.K = K;
+  a.y = y;
+  a.tab = dense_tab<T>(p, axis, transpose);
+  a.sink = (T*)p->dsink;
+  const size_t slot0 = (size_t)(kConstSlots * axis) * p->dconst_stride;
+  const size_t slotN = (size_t)(kConstSlots * axis + 1) * p->dconst_stride;
+  if (sizeof(T) == sizeof(double)) {
+    a.drow0 = (const T*)(p->dconst64 + slot0);
+    a.drowN = (const T*)(p->dconst64 + slotN);
+  } else {
+    a.drow0 = (const T*)(p->dconst32 + slot0);
+    a.drowN = (const T*)(p->dconst32 + slotN);
+  }
+  for (int i = 0; i < 3; ++i) a.n[i] = p->g.n[i];
+  a.axis = axis;
+  a.first = first;
+  a.bcmask = bc_mask(p->g.bc);
+  a.npencils = pencil_count(axis, a.n);
+  a.m00 = T(p->ax[axis].m00);
+  a.m0N = T(p->ax[axis].m0N);
+  a.mN0 = T(p->ax[axis].mN0);
+  a.mNN = T(p->ax[axis].mNN);
+  switch (p->ax[axis].N) {
+    case 16: return launch_dense_n<T, 16>(a, transpose, s);
+    case 32: return launch_dense_n<T, 32>(a, transpose, s);
+    case 48: return launch_dense_n<T, 48>(a, transpose, s);
+    case 64: return launch_dense_n<T, 64>(a, transpose, s);
+    case 96: return launch_dense_n<T, 96>(a, transpose, s);
+    case 128: return launch_dense_n<T, 128>(a, transpose, s);
+    default: set_error("matrix-core pass: unsupported N"); return CHEB_ERR_UNSUPPORTED;
+  }
+}
+
+}  // namespace cheb

@@ -244,4 +244,25 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Matrix-core multiply-accumulate D += A B on one 16x16x4 block per wave.
+// Operand layout (both precisions): lane l holds A(l % 16, l / 16) and
+// B(l / 16, l % 16); the accumulator holds column l % 16 and four rows given by
+// row(l / 16, r).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double __attribute__((ext_vector_type(4))) v4;
+  __device__ static v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // accumulator element r of lane l is row l/16 + 4 r (vector width 1)
+  __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef float __attribute__((ext_vector_type(4))) v4;
+  __device__ static v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // accumulator element r of lane l is row 4 (l/16) + r (vector width 4)
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+
 }  // namespace cheb

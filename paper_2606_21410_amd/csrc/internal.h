@@ -56,6 +56,13 @@ struct cheb_plan {
   double* pc64;
   float* pc32;
   cheb::PrecondAxis pc_ax[3];
+  // matrix-core route: split-product fragment tables of D (slot 0) and D^T (slot 1)
+  int route;
+  int dd_ok[3];
+  size_t dd_off[3][2];
+  double* dd64;
+  float* dd32;
+  void* dsink;  // 256 bytes that masked-off stores of the matrix-core pass land in
 };
 
 namespace cheb {
@@ -78,6 +85,14 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
 // full apply (z, y, x passes) in precision T
 template <typename T>
 int apply_t(const cheb_plan* p, const T* K, const T* u, T* y, int mode, hipStream_t s);
+
+// ---- matrix-core route (dense_f64.hip / dense_f32.hip) ----
+int dense_setup(cheb_plan* p);
+// transpose: 0 reduced pass, 1 transposed reduced pass
+template <typename T>
+int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
+                      hipStream_t s);
+inline bool use_dense(const cheb_plan* p, int axis) { return p->route != CHEB_ROUTE_FFT && p->dd_ok[axis]; }
 
 // ---- vector kernels (blas.hip) ----
 size_t multidot_partials_len(size_t npts, int nv);

@@ -21,6 +21,8 @@
 #include <cmath>
 #include <vector>
 
+#include "cheb_host.h"
+#include "dev_common.h"
 #include "internal.h"
 
 namespace cheb {
@@ -29,29 +31,6 @@ namespace cheb {
 // host linear algebra
 // ---------------------------------------------------------------------------
 namespace {
-
-// full ascending differentiation matrix on [lo, lo+L] (closed-form entries,
-// diagonal from the negative row sum)
-void dense_D(int N, double L, std::vector<double>& D) {
-  const int n = N + 1;
-  D.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    double rs = 0.0;
-    for (int j = 0; j < n; ++j) {
-      if (i == j) continue;
-      const double ci = (i == 0 || i == N) ? 2.0 : 1.0;
-      const double cj = (j == 0 || j == N) ? 2.0 : 1.0;
-      const double sgn = ((i + j) % 2 == 0) ? 1.0 : -1.0;
-      // t_i - t_j for t_j = -cos(pi j / N)
-      const double dif = 2.0 * std::sin(M_PI * (i + j) / (2.0 * N)) * std::sin(M_PI * (i - j) / (2.0 * N));
-      const double v = (ci / cj) * sgn / dif;
-      D[(size_t)i * n + j] = v;
-      rs += v;
-    }
-    D[(size_t)i * n + i] = -rs;
-  }
-  for (double& v : D) v *= 2.0 / L;
-}
 
 // 1-D reduced operator R D D L (m x m, m = N-1) for the boundary pair (blo, bhi)
 void reduced_1d(int N, double L, int blo, int bhi, std::vector<double>& A) {
@@ -270,23 +249,6 @@ struct GemmArgs {
   int I, Kd, C;
   long long a_si, a_sk, b_sk, b_sc, d_si, d_sc;
   long long a_sb, b_sb, d_sb;  // batch strides
-};
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef double __attribute__((ext_vector_type(4))) v4;
-  __device__ static v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  // accumulator element r of lane l is row l/16 + 4 r (vector width 1)
-  __device__ static int row(int lk, int r) { return lk + 4 * r; }
-};
-template <>
-struct Mfma<float> {
-  typedef float __attribute__((ext_vector_type(4))) v4;
-  __device__ static v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  // accumulator element r of lane l is row 4 (l/16) + r (vector width 4)
-  __device__ static int row(int lk, int r) { return 4 * lk + r; }
 };
 
 template <typename T>
