@@ -29,7 +29,7 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, seconds_budget=20.0):
+def cpu_baseline(P, seconds_budget=15.0):
     """Time the oracle's reduced-operator apply (np.tensordot with dense D) on
     the host on a bounded sample: as many applies of the same 129^3 input as fit
     in the budget (at least one)."""
@@ -45,7 +45,7 @@ def cpu_baseline(P, seconds_budget=20.0):
         O.apply_reduced(G, P.K, u)
         reps += 1
         el = time.perf_counter() - t0
-        if el > seconds_budget or reps >= 50:
+        if el > seconds_budget or reps >= 2000:
             break
     npts = float(np.prod(P.grid.n))
     return {"value": npts * reps / el / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
@@ -160,6 +160,9 @@ def main():
     ap.add_argument("--n", type=int, default=129)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-apply", action="store_true",
+                    help="for profiler runs: 4 plain device copies of one FP64 field (the byte-counter "
+                         "calibration), then the FP64 applies only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
@@ -185,41 +188,76 @@ def main():
 
     res = {}
     stream = torch.cuda.current_stream(dev)
-    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        plan = Plan(shape, P.grid.lo, P.grid.hi, P.grid.bc, prec, device=dev)
-        K = d(P.K, dt)
-        us = [d(W.random_field(shape, 100 + i), dt) for i in range(N_ROT)]
-        ys = [torch.empty_like(us[0]) for _ in range(N_ROT)]
-        for i in range(args.warmup):
+
+    def time_applies(plan, K, us, ys, steps, warmup):
+        for i in range(warmup):
             plan.apply(K, us[i % N_ROT], ys[i % N_ROT], "reduced")
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record(stream)
-        for i in range(args.steps):
+        for i in range(steps):
             plan.apply(K, us[i % N_ROT], ys[i % N_ROT], "reduced")
         ev1.record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = ev0.elapsed_time(ev1) / args.steps
-        res[prec] = {"ms_per_apply": ms, "gdofs": npts / (ms * 1e-3) / 1e9, "wall_s": wall}
-        _log(f"apply {prec}: {ms * 1e3:.1f} us/apply, {res[prec]['gdofs']:.2f} GDOF/s")
+        return ev0.elapsed_time(ev1) / steps, time.perf_counter() - t0
+
+    if args.profile_apply:
+        args.no_solve = args.no_cpu = True
+        src = d(P.K)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _log(f"calibration copies: 4 x {src.numel() * 8} bytes read and written")
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        if args.profile_apply and prec == "f32":
+            continue
+        plan = Plan(shape, P.grid.lo, P.grid.hi, P.grid.bc, prec, device=dev)
+        K = d(P.K, dt)
+        us = [d(W.random_field(shape, 100 + i), dt) for i in range(N_ROT)]
+        ys = [torch.empty_like(us[0]) for _ in range(N_ROT)]
+        tune = plan.autotune(K, us[0])[prec]
+        _log(f"autotune {prec}: {tune}")
+        ms, wall = time_applies(plan, K, us, ys, args.steps, args.warmup)
+        res[prec] = {"ms_per_apply": ms, "gdofs": npts / (ms * 1e-3) / 1e9, "wall_s": wall,
+                     "autotune_us": tune, "route": tune["chosen"]}
+        _log(f"apply {prec} ({tune['chosen']}): {ms * 1e3:.1f} us/apply, {res[prec]['gdofs']:.2f} GDOF/s")
+        plan.set_route("fft")
+        ms_fft, _ = time_applies(plan, K, us, ys, max(args.steps // 4, 10), 5)
+        res[prec]["fft_route_gdofs"] = npts / (ms_fft * 1e-3) / 1e9
+        _log(f"apply {prec} (fft route): {ms_fft * 1e3:.1f} us/apply")
         del us, ys, K, plan
         torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel (the axis pass): its own I/O per launch is
-    # read u + read K + write y (24 B/pt) for the first pass and + read y (32 B/pt)
-    # for the two accumulating passes -> 29.33 B/pt averaged over the 3 launches
+    # roofline of the dominant kernel (the axis pass; three launches per apply):
+    # algorithmic HBM bytes per launch = read u + read K + write y (24 B/pt in
+    # FP64) for the first pass, plus read y (32 B/pt) for the two accumulating
+    # passes -> 29.33 B/pt averaged over the launches; the launch duration is the
+    # event-timed apply divided by three
+    if args.profile_apply:
+        print(json.dumps({"profile_apply": res["f64"]["ms_per_apply"], "route": res["f64"]["route"]}), flush=True)
+        return
     ms = res["f64"]["ms_per_apply"]
     launch_s = ms * 1e-3 / 3.0
     bytes_per_launch = (24.0 + 32.0 + 32.0) / 3.0 * npts
     achieved = bytes_per_launch / launch_s / 1e9
+    kname = ("k_dense_pass<double,128,REDUCED> (matrix-core route" if res["f64"]["route"] != "fft"
+             else "k_axis_pass<double,128,REDUCED> (FFT route")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_axis_pass<double,128,REDUCED> (one axis pass; 3 launches per apply)",
-                "apply_level_frac": round(24.0 * npts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-
+                "kernel": kname + f", tile shape {res['f64']['route']}; 3 launches per apply)",
+                "bytes_per_point_per_launch": 29.33}
+    if res["f64"]["route"] != "fft":
+        # the same launches priced against the FP64 matrix-core peak: the
+        # even-odd split contraction does 2 (n/2)(n/2 + 1) multiply-adds per
+        # pencil per derivative, two derivatives per pass, on the (n-2)^2
+        # interior-transverse pencils
+        nn = shape[0]
+        flops = 2 * 2 * 2 * (nn // 2) * (nn // 2 + 1) * (nn - 2) ** 2
+        roofline["mfma_tflops"] = round(flops / launch_s / 1e12, 2)
+        roofline["mfma_frac"] = round(flops / launch_s / 78.6e12, 4)
     solve = None
     if not args.no_solve and n == 129:
         solve = solve_section(P, d, dev, shape)
@@ -246,6 +284,8 @@ def main():
                                f"tanh width 2h, seed 1002), u=-1/+1 on x faces, zero flux elsewhere; "
                                f"reduced operator apply", "grid": list(shape), "rotating_buffers": N_ROT},
         "f32_apply_gdofs": round(res["f32"]["gdofs"], 3),
+        "apply_detail": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
+                             if kk != "wall_s"} for k, v in res.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_1e-8_129": solve,

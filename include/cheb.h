@@ -147,6 +147,19 @@ int cheb_plan_set_stream(cheb_plan* plan, void* stream);
  * unknown route. */
 int cheb_plan_set_route(cheb_plan* plan, int32_t route);
 
+/* Autotuner of the reduced operator: times the FFT route and the two tile
+ * shapes of the matrix-core route (12 reduced applies each, HIP events on the
+ * plan's stream) on the caller's fields and keeps the fastest for
+ * CHEB_ROUTE_AUTO in that precision.  field_precision selects which passes are
+ * tuned and the type of K, u, y (device, n0*n1*n2 each, y distinct from u and
+ * K; y is overwritten): CHEB_F64 (F64 or MIXED plans) or CHEB_F32 (F32 or MIXED
+ * plans).  report (host, may be NULL when report_len is 0) receives up to 4
+ * values: microseconds per apply for [FFT route, matrix tile shape 0, matrix
+ * tile shape 1] (-1 where not applicable) and the index chosen.  Synchronises
+ * the plan's stream.  Without this call AUTO uses fixed tile shapes. */
+int cheb_plan_autotune(cheb_plan* plan, int32_t field_precision, const void* K, const void* u, void* y,
+                       double* report, int32_t report_len);
+
 int cheb_plan_destroy(cheb_plan* plan);
 
 /* Operator application (Algorithm 3 with the rows of Section 2.3.1).

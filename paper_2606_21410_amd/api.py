@@ -82,6 +82,29 @@ class Plan:
         L.check(self.lib.cheb_plan_set_route(self._h, _ROUTE[route]))
         self.route = route
 
+    def autotune(self, K=None, u=None):
+        """Time the FFT route and the matrix-core tile shapes of the reduced
+        operator (per precision the plan computes in) and keep the fastest for
+        route 'auto'.  Returns {precision: {"fft": us, "matrix0": us,
+        "matrix1": us, "chosen": name}}."""
+        out = {}
+        precs = {"f64": [("f64", torch.float64)], "f32": [("f32", torch.float32)],
+                 "mixed": [("f64", torch.float64), ("f32", torch.float32)]}[self.precision]
+        names = ["fft", "matrix0", "matrix1"]
+        for pname, dt in precs:
+            Kt = (K if K is not None else torch.ones(self.n, device=self.device, dtype=torch.float64)).to(dt)
+            ut = (u if u is not None else torch.randn(self.n, device=self.device, dtype=torch.float64)).to(dt)
+            Kt, ut = Kt.contiguous(), ut.contiguous()
+            yt = torch.empty_like(ut)
+            rep = (ctypes.c_double * 4)()
+            self._sync_stream()
+            L.check(self.lib.cheb_plan_autotune(self._h, _PREC[pname], ctypes.c_void_p(Kt.data_ptr()),
+                                                ctypes.c_void_p(ut.data_ptr()), ctypes.c_void_p(yt.data_ptr()),
+                                                rep, 4))
+            out[pname] = {names[i]: rep[i] for i in range(3)}
+            out[pname]["chosen"] = names[int(rep[3])]
+        return out
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             self.lib.cheb_plan_destroy(self._h)

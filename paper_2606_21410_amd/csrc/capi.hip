@@ -71,6 +71,62 @@ void cc_weights(int N, double L, std::vector<double>& w) {
 
 using namespace cheb;
 
+namespace {
+
+// Time one reduced apply configuration: 2 warm-up applies, then `reps` timed
+// with events on the plan's stream; returns microseconds per apply.
+template <typename T>
+static int time_apply(cheb_plan* p, const T* K, const T* u, T* y, int reps, double* us) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_check(hipEventCreate(&e0), "hipEventCreate");
+  if (!rc) rc = hip_check(hipEventCreate(&e1), "hipEventCreate");
+  for (int i = 0; !rc && i < 2; ++i) rc = apply_t<T>(p, K, u, y, 1, p->stream);
+  if (!rc) rc = hip_check(hipEventRecord(e0, p->stream), "hipEventRecord");
+  for (int i = 0; !rc && i < reps; ++i) rc = apply_t<T>(p, K, u, y, 1, p->stream);
+  if (!rc) rc = hip_check(hipEventRecord(e1, p->stream), "hipEventRecord");
+  if (!rc) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+  float ms = 0.f;
+  if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  *us = 1e3 * ms / reps;
+  return rc;
+}
+
+template <typename T>
+static int autotune_t(cheb_plan* p, const T* K, const T* u, T* y, double* report, int report_len) {
+  const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
+  const int saved_route = p->route;
+  int saved_var[3];
+  for (int a = 0; a < 3; ++a) saved_var[a] = p->dense_var[a][pi];
+  bool any = false;
+  for (int a = 0; a < 3; ++a) any = any || p->dd_ok[a];
+  double t[3] = {-1.0, -1.0, -1.0};  // FFT route, matrix route tile shape 0, tile shape 1
+  int rc = CHEB_OK;
+  p->route = CHEB_ROUTE_FFT;
+  rc = time_apply<T>(p, K, u, y, 10, &t[0]);
+  for (int v = 0; !rc && any && v < 2; ++v) {
+    p->route = CHEB_ROUTE_MATRIX;
+    for (int a = 0; a < 3; ++a) p->dense_var[a][pi] = v;
+    rc = time_apply<T>(p, K, u, y, 10, &t[1 + v]);
+  }
+  p->route = saved_route;
+  if (rc) {
+    for (int a = 0; a < 3; ++a) p->dense_var[a][pi] = saved_var[a];
+    return rc;
+  }
+  int best = 0;
+  for (int c = 1; c < 3; ++c)
+    if (t[c] >= 0.0 && t[c] < t[best]) best = c;
+  p->auto_fft[pi] = best == 0;
+  for (int a = 0; a < 3; ++a) p->dense_var[a][pi] = best == 0 ? saved_var[a] : best - 1;
+  for (int c = 0; c < 3 && c < report_len; ++c) report[c] = t[c];
+  if (report_len > 3) report[3] = best;
+  return CHEB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* cheb_last_error(void) { return g_last_error.c_str(); }
@@ -262,6 +318,20 @@ int cheb_apply(cheb_plan* plan, const void* K, const void* u, void* y, uint32_t 
   if (plan->prec == CHEB_F32)
     return apply_t<float>(plan, (const float*)K, (const float*)u, (float*)y, mode, plan->stream);
   return apply_t<double>(plan, (const double*)K, (const double*)u, (double*)y, mode, plan->stream);
+}
+
+int cheb_plan_autotune(cheb_plan* plan, int32_t field_precision, const void* K, const void* u, void* y,
+                       double* report, int32_t report_len) {
+  if (!plan || !K || !u || !y || y == u || y == K || (report_len > 0 && !report)) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (field_precision == CHEB_F64 && plan->prec != CHEB_F32)
+    return autotune_t<double>(plan, (const double*)K, (const double*)u, (double*)y, report, report_len);
+  if (field_precision == CHEB_F32 && plan->prec != CHEB_F64)
+    return autotune_t<float>(plan, (const float*)K, (const float*)u, (float*)y, report, report_len);
+  set_error("field precision must match the plan (F64 plan: CHEB_F64; F32 plan: CHEB_F32; MIXED: either)");
+  return CHEB_ERR_INVALID_ARG;
 }
 
 int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis) {

@@ -8,22 +8,22 @@ namespace cheb {
 
 // Persistent launch: as many workgroups as the device holds at once (resident
 // workgroups per CU x CUs, queried once per kernel), at most one per tile.
-template <typename T, int NC, int MODE, bool FIRST>
+template <typename T, int NC, int MODE, bool FIRST, int V>
 static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
-  constexpr DenseDims S = dense_dims(NC);
-  constexpr int lds = dense_lds_bytes<T>(NC);
+  constexpr DenseDims S = dense_dims(NC, V);
+  constexpr int lds = dense_lds_bytes<T>(NC, V);
   static_assert(lds <= 160 * 1024, "matrix-core tile exceeds LDS");
   static int resident = 0;
   if (resident == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (!rc && lds > 64 * 1024)
-      rc = hip_check(hipFuncSetAttribute((const void*)k_dense_pass<T, NC, MODE, FIRST>,
+      rc = hip_check(hipFuncSetAttribute((const void*)k_dense_pass<T, NC, MODE, FIRST, V>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, lds),
                      "matrix-core pass LDS attribute");
     if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     if (!rc)
-      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_dense_pass<T, NC, MODE, FIRST>,
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_dense_pass<T, NC, MODE, FIRST, V>,
                                                                   64 * S.NW, lds),
                      "occupancy query");
     if (rc) return rc;
@@ -32,17 +32,22 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
   const int ta = a.axis == 0 ? a.n[1] : a.n[0], tb = a.axis == 2 ? a.n[1] : a.n[2];
   const int tiles = ((ta - 2) * (tb - 2) + S.C - 1) / S.C;
   const int grid = tiles < resident ? (tiles > 0 ? tiles : 1) : resident;
-  hipLaunchKernelGGL((k_dense_pass<T, NC, MODE, FIRST>), dim3(grid), dim3(64 * S.NW), lds, s, a);
+  hipLaunchKernelGGL((k_dense_pass<T, NC, MODE, FIRST, V>), dim3(grid), dim3(64 * S.NW), lds, s, a);
   return hip_check(hipGetLastError(), "matrix-core pass launch");
 }
 
-template <typename T, int NC>
-static int launch_dense_n(const DenseArgs<T>& a, int transpose, hipStream_t s) {
+template <typename T, int NC, int V>
+static int launch_dense_v(const DenseArgs<T>& a, int transpose, hipStream_t s) {
   if (a.first)
-    return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, true>(a, s)
-                     : launch_dense_inst<T, NC, DENSE_REDUCED, true>(a, s);
-  return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, false>(a, s)
-                   : launch_dense_inst<T, NC, DENSE_REDUCED, false>(a, s);
+    return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, true, V>(a, s)
+                     : launch_dense_inst<T, NC, DENSE_REDUCED, true, V>(a, s);
+  return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, false, V>(a, s)
+                   : launch_dense_inst<T, NC, DENSE_REDUCED, false, V>(a, s);
+}
+
+template <typename T, int NC>
+static int launch_dense_n(const DenseArgs<T>& a, int transpose, int variant, hipStream_t s) {
+  return variant == 1 ? launch_dense_v<T, NC, 1>(a, transpose, s) : launch_dense_v<T, NC, 0>(a, transpose, s);
 }
 
 template <typename T>
@@ -83,13 +88,14 @@ int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, co
   a.m0N = T(p->ax[axis].m0N);
   a.mN0 = T(p->ax[axis].mN0);
   a.mNN = T(p->ax[axis].mNN);
+  const int variant = p->dense_var[axis][sizeof(T) == sizeof(double) ? 0 : 1];
   switch (p->ax[axis].N) {
-    case 16: return launch_dense_n<T, 16>(a, transpose, s);
-    case 32: return launch_dense_n<T, 32>(a, transpose, s);
-    case 48: return launch_dense_n<T, 48>(a, transpose, s);
-    case 64: return launch_dense_n<T, 64>(a, transpose, s);
-    case 96: return launch_dense_n<T, 96>(a, transpose, s);
-    case 128: return launch_dense_n<T, 128>(a, transpose, s);
+    case 16: return launch_dense_n<T, 16>(a, transpose, variant, s);
+    case 32: return launch_dense_n<T, 32>(a, transpose, variant, s);
+    case 48: return launch_dense_n<T, 48>(a, transpose, variant, s);
+    case 64: return launch_dense_n<T, 64>(a, transpose, variant, s);
+    case 96: return launch_dense_n<T, 96>(a, transpose, variant, s);
+    case 128: return launch_dense_n<T, 128>(a, transpose, variant, s);
     default: set_error("matrix-core pass: unsupported N"); return CHEB_ERR_UNSUPPORTED;
   }
 }

@@ -31,11 +31,14 @@ enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1 };
 // Compile-time shape of the split product for one N (also used by the host
 // code that writes the fragment tables and sizes the LDS).
 struct DenseDims {
-  int N, HALF, KO, KE, KO4, KE4, R, RM, MT, WC, NW, C, OFF_E, OFF_MID, TAB;
+  int N, HALF, KO, KE, KO4, KE4, R, RM, MT, WC, NW, C, OFF_E, OFF_MID, OFF_COL, TAB;
   bool EVEN, MIDV;
 };
 
-__host__ __device__ constexpr DenseDims dense_dims(int N) {
+// Two tile shapes: V = 0 keeps the fragment table in LDS and runs 8-wave
+// workgroups (one per CU); V = 1 keeps each wave's fragments in registers and
+// runs 4-wave workgroups (two per CU, so one overlaps the other's memory phases).
+__host__ __device__ constexpr DenseDims dense_dims(int N, int V = 0) {
   DenseDims d{};
   d.N = N;
   d.HALF = N / 2;
@@ -48,13 +51,16 @@ __host__ __device__ constexpr DenseDims dense_dims(int N) {
   d.MIDV = d.EVEN && (d.R % 16 == 1);    // a lone middle row goes to the vector ALUs
   d.RM = d.MIDV ? d.R - 1 : d.R;         // rows on the matrix cores
   d.MT = (d.RM + 15) / 16;               // 16-row blocks, one per wave
-  d.WC = d.MT == 3 ? 2 : 8 / d.MT;       // 16-column groups per workgroup
-  d.NW = d.MT * d.WC;                    // waves per workgroup (8, or 6 for MT = 3)
+  d.WC = V == 0 ? (d.MT == 3 ? 2 : 8 / d.MT)   // 16-column groups per workgroup
+               : (d.MT >= 3 ? 1 : 4 / d.MT);
+  d.NW = d.MT * d.WC;                    // waves per workgroup
   d.C = 16 * d.WC;                       // pencils per tile
-  // fragment table: [mt][ks][lane] for Ao, then Ae, then the middle row of Ao
+  // fragment table: [mt][ks][lane] for Ao, then Ae, then the middle row of Ao,
+  // then the end columns M[:][0] and M[:][N] (the lift's rank-2 correction)
   d.OFF_E = d.MT * d.KO4 * 64;
   d.OFF_MID = d.OFF_E + d.MT * d.KE4 * 64;
-  d.TAB = d.OFF_MID + d.KO4 * 4;
+  d.OFF_COL = d.OFF_MID + d.KO4 * 4;
+  d.TAB = d.OFF_COL + 2 * (N + 1);
   return d;
 }
 
@@ -68,13 +74,14 @@ __host__ __device__ constexpr int pow2_floor(int x) {
   return p;
 }
 
-// LDS carve of one workgroup (bytes): fragment table, tile, face rows, the
-// transposed-lift multipliers, column bookkeeping
+// LDS carve of one workgroup (bytes): fragment table, tile, K tile, face rows,
+// the per-column lift values / transposed-lift multipliers, column bookkeeping
 template <typename T>
-__host__ __device__ constexpr int dense_lds_bytes(int N) {
-  const DenseDims d = dense_dims(N);
+__host__ __device__ constexpr int dense_lds_bytes(int N, int V) {
+  const DenseDims d = dense_dims(N, V);
   const int n = N + 1, SC = d.C + 1;
-  return (d.TAB + n * SC + 2 * n + 2 * d.C) * (int)sizeof(T) + 2 * d.C * (int)sizeof(int);
+  const int tabl = V == 0 ? d.TAB : d.TAB - d.OFF_MID;  // V = 1: only the middle row and end columns
+  return (tabl + 2 * n * SC + 2 * n + 2 * d.C) * (int)sizeof(T) + 2 * d.C * (int)sizeof(int);
 }
 
 template <typename T>
@@ -107,45 +114,95 @@ struct DenseArgs {
 // ACCO/ACCE = split products of the LDS tile (B operand) with this wave's A
 // fragments (from the LDS table).  Rows j > N/2 of the last k-step meet zero
 // table entries.
-#define DENSE_GEMM(ACCO, ACCE)                                                 \
+#define DENSE_GEMM(ACCO, ACCE, ISSUE)                                          \
   do {                                                                         \
     ACCO = V4{0, 0, 0, 0};                                                     \
     ACCE = V4{0, 0, 0, 0};                                                     \
     _Pragma("unroll") for (int ks = 0; ks < S.KE4; ++ks) {                     \
+      ISSUE(ks);                                                               \
       const int j = 4 * ks + lk;                                               \
       const T x0 = U[j * SC + col], x1 = U[(N - j) * SC + col];                \
-      if (ks < S.KO4) ACCO = Mfma<T>::mac(Ao[ks * 64], x0 - x1, ACCO);         \
-      ACCE = Mfma<T>::mac(Ae[ks * 64], x0 + x1, ACCE);                         \
+      if (ks < S.KO4) ACCO = Mfma<T>::mac(V == 0 ? Ao[ks * 64] : ao[ks], x0 - x1, ACCO); \
+      ACCE = Mfma<T>::mac(V == 0 ? Ae[ks * 64] : ae[ks], x0 + x1, ACCE);       \
     }                                                                          \
   } while (0)
 
-// middle row N/2 (odd part only) when it does not fill a 16-row block
-#define DENSE_MID(OUT)                                                                 \
-  do {                                                                                 \
-    OUT = T(0);                                                                        \
-    if (S.MIDV) {                                                                      \
-      if (lc < C)                                                                      \
-        for (int j = lg; j < S.KO; j += LPC) OUT += amid[j] * (U[j * SC + lc] - U[(N - j) * SC + lc]); \
-      OUT = group_sum<LPC>(OUT);                                                       \
-    }                                                                                  \
+// vector-ALU dot products of each tile column with the LDS tile: the middle row
+// N/2 of the odd part (when it does not fill a 16-row block) and, with LIFT, the
+// two face rows that give the homogeneous lift of the end values (Section
+// 2.3.1); lane lg == 0 of each column's group holds the sums.
+#define DENSE_VDOT(MIDOUT, LIFT)                                                   \
+  do {                                                                             \
+    MIDOUT = T(0);                                                                 \
+    T s0_ = T(0), sN_ = T(0);                                                      \
+    if (S.MIDV || (LIFT)) {                                                        \
+      if (lc < C)                                                                  \
+        for (int j = lg; j < n; j += LPC) {                                        \
+          const T v = U[j * SC + lc];                                              \
+          if (S.MIDV && j < S.KO) MIDOUT += amid[j] * (v - U[(N - j) * SC + lc]); \
+          if (LIFT) {                                                              \
+            s0_ += drw[j] * v;                                                     \
+            sN_ += drw[n + j] * v;                                                 \
+          }                                                                        \
+        }                                                                          \
+      if (S.MIDV) MIDOUT = group_sum<LPC>(MIDOUT);                                 \
+      if (LIFT) {                                                                  \
+        s0_ = group_sum<LPC>(s0_);                                                 \
+        sN_ = group_sum<LPC>(sN_);                                                 \
+        if (lc < C && lg == 0) {                                                   \
+          T u0 = T(0), uN = T(0);                                                  \
+          if (nlo && nhi) {                                                        \
+            const T det = a.m00 * a.mNN - a.m0N * a.mN0;                           \
+            u0 = (-s0_ * a.mNN + sN_ * a.m0N) / det;                               \
+            uN = (-sN_ * a.m00 + s0_ * a.mN0) / det;                               \
+          } else if (nlo) {                                                        \
+            u0 = -s0_ / a.m00;                                                     \
+          } else if (nhi) {                                                        \
+            uN = -sN_ / a.mNN;                                                     \
+          }                                                                        \
+          cend[2 * lc] = u0;                                                       \
+          cend[2 * lc + 1] = uN;                                                   \
+        }                                                                          \
+      }                                                                            \
+    }                                                                              \
   } while (0)
 
-// accumulators -> LDS tile rows i and N-i
-#define DENSE_EPI(ACCO, ACCE, MIDVAL)                                      \
-  do {                                                                     \
-    _Pragma("unroll") for (int r = 0; r < 4; ++r) {                        \
-      const int i = 16 * mt + Mfma<T>::row(lk, r);                         \
-      if (i < S.RM) {                                                      \
-        const T o = ACCO[r], e = ACCE[r];                                  \
-        if (2 * i == N) {                                                  \
-          U[i * SC + col] = o;                                             \
-        } else {                                                           \
-          U[i * SC + col] = o + e;                                         \
-          U[(N - i) * SC + col] = o - e;                                   \
-        }                                                                  \
-      }                                                                    \
-    }                                                                      \
-    if (S.MIDV && lc < C && lg == 0) U[S.HALF * SC + lc] = MIDVAL;         \
+// accumulators -> LDS tile rows i and N-i.  FLUX (first product): add the
+// lift's rank-2 correction u0 M[:][0] + uN M[:][N] (LIFT) and multiply by K.
+#define DENSE_EPI(ACCO, ACCE, MIDVAL, FLUX, LIFT)                            \
+  do {                                                                       \
+    T u0_ = T(0), uN_ = T(0);                                                \
+    if (LIFT) {                                                              \
+      u0_ = cend[2 * col];                                                   \
+      uN_ = cend[2 * col + 1];                                               \
+    }                                                                        \
+    _Pragma("unroll") for (int r = 0; r < 4; ++r) {                          \
+      const int i = 16 * mt + Mfma<T>::row(lk, r);                           \
+      if (i < S.RM) {                                                        \
+        const T o = ACCO[r], e = ACCE[r];                                    \
+        T lo = o + e, hi = o - e;                                            \
+        if (LIFT) {                                                          \
+          lo += u0_ * dc0[i] + uN_ * dcN[i];                                 \
+          hi += u0_ * dc0[N - i] + uN_ * dcN[N - i];                         \
+        }                                                                    \
+        if (FLUX) {                                                          \
+          lo *= Kt[i * SC + col];                                            \
+          hi *= Kt[(N - i) * SC + col];                                      \
+        }                                                                    \
+        if (2 * i == N) {                                                    \
+          U[i * SC + col] = lo;                                              \
+        } else {                                                             \
+          U[i * SC + col] = lo;                                              \
+          U[(N - i) * SC + col] = hi;                                        \
+        }                                                                    \
+      }                                                                      \
+    }                                                                        \
+    if (S.MIDV && lc < C && lg == 0) {                                       \
+      T m_ = MIDVAL;                                                         \
+      if (LIFT) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
+      if (FLUX) m_ *= Kt[S.HALF * SC + lc];                                  \
+      U[S.HALF * SC + lc] = m_;                                              \
+    }                                                                        \
   } while (0)
 
 // column bookkeeping of tile TILE into slot SLOT: linear offset of each
@@ -193,9 +250,9 @@ struct DenseArgs {
 // interior-transverse pencils and keeps the next tile's u and K loads in flight
 // in registers while it computes the current one.  In the first pass it also
 // clears the pencils that lie in a face (all their nodes are boundary nodes).
-template <typename T, int NC, int MODE, bool FIRST>
-__global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs<T> a) {
-  constexpr DenseDims S = dense_dims(NC);
+template <typename T, int NC, int MODE, bool FIRST, int V>
+__global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(DenseArgs<T> a) {
+  constexpr DenseDims S = dense_dims(NC, V);
   constexpr int N = NC, n = NC + 1;
   constexpr int NT = 64 * S.NW;
   constexpr int C = S.C;
@@ -206,12 +263,17 @@ __global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs
   typedef typename Mfma<T>::v4 V4;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  T* tab = (T*)smem;
+  // V = 0: whole table in LDS; V = 1: LDS holds the table from OFF_MID on
+  constexpr int TB = V == 0 ? 0 : S.OFF_MID;  // first table entry kept in LDS
+  T* tab = (T*)smem - TB;
   T* U = tab + S.TAB;
-  T* drw = U + n * SC;  // face rows D[0][:], D[N][:]
+  T* Kt = U + n * SC;
+  T* drw = Kt + n * SC;  // face rows D[0][:], D[N][:]
   T* cend = drw + 2 * n;
   int(*cbase)[C] = (int(*)[C])(cend + 2 * C);
   const T* amid = tab + S.OFF_MID;
+  const T* dc0 = tab + S.OFF_COL;  // end columns M[:][0], M[:][N]
+  const T* dcN = dc0 + n;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mt = wave % S.MT, cg = wave / S.MT;
@@ -228,22 +290,12 @@ __global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs
   const bool nlo = (a.bcmask >> (2 * axis)) & 1, nhi = (a.bcmask >> (2 * axis + 1)) & 1;
   const T* Ao = tab + mt * S.KO4 * 64 + lane;
   const T* Ae = tab + S.OFF_E + mt * S.KE4 * 64 + lane;
-
-  {
-    // fragment table and face rows into LDS, loads batched
-    constexpr int TI = (S.TAB + NT - 1) / NT;
-    T tv[TI];
+  T ao[V == 1 ? S.KO4 : 1], ae[V == 1 ? S.KE4 : 1];
+  if (V == 1) {
 #pragma unroll
-    for (int i = 0; i < TI; ++i) tv[i] = a.tab[tid + i * NT < S.TAB ? tid + i * NT : S.TAB - 1];
-    const int jr = tid < n ? tid : n - 1;
-    const T r0 = a.drow0[jr], rN = a.drowN[jr];
+    for (int ks = 0; ks < S.KO4; ++ks) ao[ks] = a.tab[(mt * S.KO4 + ks) * 64 + lane];
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
-      if (tid + i * NT < S.TAB) tab[tid + i * NT] = tv[i];
-    for (int j = tid; j < n; j += NT) {
-      drw[j] = j == jr ? r0 : a.drow0[j];
-      drw[n + j] = j == jr ? rN : a.drowN[j];
-    }
+    for (int ks = 0; ks < S.KE4; ++ks) ae[ks] = a.tab[S.OFF_E + (mt * S.KE4 + ks) * 64 + lane];
   }
 
   if (FIRST) {
@@ -265,16 +317,49 @@ __global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs
     }
   }
 
-  int tile = blockIdx.x;
+  // prologue: fragment-table loads, then the first tile's loads, both in
+  // flight before the table is written to LDS
+  constexpr int TI = (S.TAB - TB + NT - 1) / NT;
+  T tv[TI];
+#pragma unroll
+  for (int i = 0; i < TI; ++i) tv[i] = a.tab[TB + (tid + i * NT < S.TAB - TB ? tid + i * NT : S.TAB - TB - 1)];
+  const int jr = tid < n ? tid : n - 1;
+  const T r0v = a.drow0[jr], rNv = a.drowN[jr];
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // workgroup b serves a contiguous range of tiles of XCD b % 8 and tiles that
+  // share cache lines at their edges meet in the same L2
+  int t_step = gridDim.x, t_end = ntiles, tile = blockIdx.x;
+  if ((gridDim.x & 7) == 0 && ntiles >= (int)gridDim.x) {
+    const int per = (ntiles + 7) >> 3;
+    const int x = blockIdx.x & 7;
+    tile = x * per + (blockIdx.x >> 3);
+    t_step = gridDim.x >> 3;
+    t_end = min(ntiles, (x + 1) * per);
+  }
   int slot = 0;
   DENSE_COLS(0, tile);
   __syncthreads();
+  // V = 0 prefetches the next tile into registers; V = 1 loads each tile when
+  // it starts and relies on the second workgroup of the CU for overlap
+  constexpr bool PREF = V == 0;
   T ureg[EPT], kreg[EPT];
-  DENSE_LOAD(0, ureg, kreg);
+  if (PREF) DENSE_LOAD(0, ureg, kreg);
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+    if (tid + i * NT < S.TAB - TB) tab[TB + tid + i * NT] = tv[i];
+  if (tid < n) {
+    drw[tid] = r0v;
+    drw[n + tid] = rNv;
+  }
+  for (int j = tid + NT; j < n; j += NT) {
+    drw[j] = a.drow0[j];
+    drw[n + j] = a.drowN[j];
+  }
 
-  for (; tile < ntiles; tile += gridDim.x, slot ^= 1) {
-    const int nxt = tile + gridDim.x;
+  for (; tile < t_end; tile += t_step, slot ^= 1) {
+    const int nxt = tile + t_step < t_end ? tile + t_step : ntiles;
     __syncthreads();  // previous tile's readers of U and of slot^1 are done
+    if (!PREF) DENSE_LOAD(slot, ureg, kreg);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
@@ -282,6 +367,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs
         int j, c;
         DENSE_MAP(e, j, c);
         U[j * SC + c] = ureg[q];
+        Kt[j * SC + c] = kreg[q];
       }
     }
     if (nxt < ntiles) DENSE_COLS(slot ^ 1, nxt);
@@ -289,76 +375,81 @@ __global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs
 
     // in flight during this tile: next tile's u and K (the last tile reloads
     // its own columns), this tile's y
-    T unx[EPT], knx[EPT], yreg[EPT];
-    DENSE_LOAD(nxt < ntiles ? (slot ^ 1) : slot, unx, knx);
-    if (!FIRST) {
-      int ad[EPT];
+    // Their addresses are formed here and the loads are issued a few at a time
+    // between the first product's matrix instructions, so the matrix cores keep
+    // working while load issue waits for queue space.
+    T unx[PREF ? EPT : 1], knx[PREF ? EPT : 1], yreg[EPT];
+    int pad[PREF ? EPT : 1], yad[EPT];
+    bool pok[PREF ? EPT : 1], pin[PREF ? EPT : 1];
+    {
+      const int ps = slot ^ 1;
+      const bool more = nxt < ntiles;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * NT < TOT ? tid + q * NT : TOT - 1;
         int j, c;
         DENSE_MAP(e, j, c);
         const int b = cbase[slot][c];
-        ad[q] = b >= 0 ? b + j * stride : 0;
-      }
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) yreg[q] = a.y[ad[q]];
-    }
-
-    if (MODE == DENSE_REDUCED) {
-      // homogeneous lift of the end values through the Neumann face rows
-      T s0 = T(0), sN = T(0);
-      if (lc < C)
-        for (int m = 1 + lg; m < N; m += LPC) {
-          const T v = U[m * SC + lc];
-          s0 += drw[m] * v;
-          sN += drw[n + m] * v;
+        yad[q] = b >= 0 ? b + j * stride : 0;
+        if (PREF) {
+          const int bn = more ? cbase[ps][c] : -1;
+          const bool ok = bn >= 0 && tid + q * NT < TOT;
+          pok[PREF ? q : 0] = ok;
+          pin[PREF ? q : 0] = ok && j != 0 && j != N;
+          pad[PREF ? q : 0] = ok ? bn + j * stride : 0;
         }
-      s0 = group_sum<LPC>(s0);
-      sN = group_sum<LPC>(sN);
-      if (lc < C && lg == 0) {
-        T u0 = T(0), uN = T(0);
-        if (nlo && nhi) {
-          const T det = a.m00 * a.mNN - a.m0N * a.mN0;
-          u0 = (-s0 * a.mNN + sN * a.m0N) / det;
-          uN = (-sN * a.m00 + s0 * a.mN0) / det;
-        } else if (nlo) {
-          u0 = -s0 / a.m00;
-        } else if (nhi) {
-          uN = -sN / a.mNN;
-        }
-        U[lc] = u0;
-        U[N * SC + lc] = uN;
       }
-      __syncthreads();
     }
+    // loads issued at k-step KS of the first product: prefetch element KS/2 (u
+    // at even steps, K at odd ones); y loads go between the second product's
+    // k-steps
+#define DENSE_ISSUE1(KS)                                                          \
+  do {                                                                            \
+    if (PREF && (KS) < 2 * EPT) {                                                 \
+      if ((KS) % 2 == 0) unx[PREF ? (KS) / 2 : 0] = a.u[pad[PREF ? (KS) / 2 : 0]]; \
+      else knx[PREF ? (KS) / 2 : 0] = a.K[pad[PREF ? (KS) / 2 : 0]];              \
+    }                                                                             \
+  } while (0)
+#define DENSE_ISSUE2(KS)                                                          \
+  do {                                                                            \
+    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = a.y[yad[(KS) < EPT ? (KS) : 0]]; \
+  } while (0)
+#define DENSE_ISSUE_NONE(KS) \
+  do {                       \
+  } while (0)
 
     V4 acco, acce;
     T midv;
-    // first derivative (all n rows)
-    DENSE_GEMM(acco, acce);
-    DENSE_MID(midv);
-    __syncthreads();
-    DENSE_EPI(acco, acce, midv);
-    __syncthreads();
-
-    // pointwise flux K * (M u)
+    // first derivative of the lifted pencil (all n rows), then the flux K * (M u)
+    DENSE_GEMM(acco, acce, DENSE_ISSUE1);
+    // whatever did not fit between the k-steps
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      if (e < TOT) {
-        int j, c;
-        DENSE_MAP(e, j, c);
-        U[j * SC + c] *= kreg[q];
+    for (int ks = S.KE4; ks < (PREF ? 2 * EPT : 0); ++ks) {
+      if (PREF && ks < 2 * EPT) {
+        if (ks % 2 == 0) unx[PREF ? ks / 2 : 0] = a.u[pad[PREF ? ks / 2 : 0]];
+        else knx[PREF ? ks / 2 : 0] = a.K[pad[PREF ? ks / 2 : 0]];
       }
     }
+    DENSE_VDOT(midv, MODE == DENSE_REDUCED);
+    __syncthreads();
+    DENSE_EPI(acco, acce, midv, true, MODE == DENSE_REDUCED);
     __syncthreads();
 
     // divergence part
-    DENSE_GEMM(acco, acce);
-    DENSE_MID(midv);
+    if (PREF) {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        unx[PREF ? q : 0] = pin[PREF ? q : 0] ? unx[PREF ? q : 0] : T(0);
+        knx[PREF ? q : 0] = pok[PREF ? q : 0] ? knx[PREF ? q : 0] : T(0);
+      }
+    }
+    DENSE_GEMM(acco, acce, DENSE_ISSUE2);
+#pragma unroll
+    for (int q = S.KE4; q < EPT; ++q)
+      if (!FIRST) yreg[q] = a.y[yad[q]];
+    DENSE_VDOT(midv, false);
     __syncthreads();
-    DENSE_EPI(acco, acce, midv);
+    DENSE_EPI(acco, acce, midv, false, false);
     __syncthreads();
 
     if (MODE == DENSE_TRANSPOSE) {
@@ -403,17 +494,22 @@ __global__ __launch_bounds__(64 * dense_dims(NC).NW) void k_dense_pass(DenseArgs
 #pragma unroll
       for (int q = 0; q < EPT; ++q) *op[q] = ov[q];
     }
+    if (PREF) {
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      ureg[q] = unx[q];
-      kreg[q] = knx[q];
+      for (int q = 0; q < EPT; ++q) {
+        ureg[q] = unx[PREF ? q : 0];
+        kreg[q] = knx[PREF ? q : 0];
+      }
     }
   }
 }
 
 #undef DENSE_MAP
 #undef DENSE_GEMM
-#undef DENSE_MID
+#undef DENSE_ISSUE1
+#undef DENSE_ISSUE_NONE
+#undef DENSE_ISSUE2
+#undef DENSE_VDOT
 #undef DENSE_EPI
 #undef DENSE_COLS
 #undef DENSE_LOAD

@@ -60,6 +60,8 @@ struct cheb_plan {
   int route;
   int dd_ok[3];
   size_t dd_off[3][2];
+  int dense_var[3][2];  // tile shape of the matrix-core pass, [axis][f64, f32]
+  int auto_fft[2];      // CHEB_ROUTE_AUTO resolved to the FFT route, [f64, f32] (autotuner)
   double* dd64;
   float* dd32;
   void* dsink;  // 256 bytes that masked-off stores of the matrix-core pass land in
@@ -92,7 +94,11 @@ int dense_setup(cheb_plan* p);
 template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
                       hipStream_t s);
-inline bool use_dense(const cheb_plan* p, int axis) { return p->route != CHEB_ROUTE_FFT && p->dd_ok[axis]; }
+// pi: 0 for the FP64 passes, 1 for the FP32 passes
+inline bool use_dense(const cheb_plan* p, int axis, int pi) {
+  if (!p->dd_ok[axis] || p->route == CHEB_ROUTE_FFT) return false;
+  return p->route == CHEB_ROUTE_MATRIX || !p->auto_fft[pi];
+}
 
 // ---- vector kernels (blas.hip) ----
 size_t multidot_partials_len(size_t npts, int nv);

@@ -70,7 +70,7 @@ inline const float* drow<float>(const cheb_plan* p, int a, int slot) { return dc
 template <typename T>
 int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T* K, const T* u, T* y,
                      hipStream_t s) {
-  if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && use_dense(p, axis))
+  if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && use_dense(p, axis, sizeof(T) == sizeof(double) ? 0 : 1))
     return launch_dense_pass<T>(p, axis, mode == MODE_TRANSPOSE ? 1 : 0, first, K, u, y, s);
   PassArgs<T> a;
   a.u = u;

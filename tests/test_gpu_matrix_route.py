@@ -111,3 +111,29 @@ def test_solve_matrix_route_matches_fft_route():
     ref = out[("fft", "f64")]
     for k, v in out.items():
         assert rel_l2(v, ref) <= 1e-10, k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
+def test_autotune_then_parity(prec):
+    """The autotuner times every route / tile shape, picks one, and the reduced
+    operator stays within the parity bar afterwards."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    n = (65, 33, 49)
+    bc = BC_SETS["NDNNDN"]
+    G, u, K = _case(n, bc, 900)
+    plan = Plan(n, G.lo, G.hi, bc, prec)
+    rep = plan.autotune(to_dev(K, torch.float64), to_dev(u, torch.float64))
+    log(f"autotune {prec}: {rep}")
+    for pname, r in rep.items():
+        assert r["fft"] > 0 and r["matrix0"] > 0 and r["matrix1"] > 0
+        assert r["chosen"] in ("fft", "matrix0", "matrix1")
+    if prec == "f32":
+        u32 = u.astype(np.float32).astype(np.float64)
+        K32 = K.astype(np.float32).astype(np.float64)
+        y = to_host(plan.apply(to_dev(K32, torch.float32), to_dev(u32, torch.float32), mode="reduced"))
+        assert rel_l2(y, O.apply_reduced(G, K32, u32)) <= F32_TOL
+    else:
+        y = to_host(plan.apply(to_dev(K, torch.float64), to_dev(u, torch.float64), mode="reduced"))
+        assert rel_l2(y, O.apply_reduced(G, K, u)) <= F64_TOL
