@@ -25,6 +25,29 @@ HBM_PEAK_GBS = 8000.0
 N_ROT = 16
 
 
+def _traffic_record(route):
+    """HBM bytes per launch measured with rocprofv3 for the dominant kernel
+    (profiles/k_dense_pass_f64_129cubed_hbm_bytes.txt), or None when the
+    kernel sources or the chosen tile shape differ from the profiled ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_dense_pass_f64_129cubed_hbm_bytes.txt")
+    if not os.path.exists(path) or route not in ("matrix0", "matrix1"):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+    if rec is None:
+        return None
+    for f, h in rec["sources"].items():
+        cur = hashlib.sha1(open(os.path.join(ROOT, "paper_2606_21410_amd", "csrc", f), "rb").read()).hexdigest()[:12]
+        if cur != h:
+            return None
+    if not rec["kernel"].endswith(f"{route[-1]}>(cheb::DenseArgs<double>)"):
+        return None
+    return rec
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -243,11 +266,16 @@ def main():
     launch_s = ms * 1e-3 / 3.0
     bytes_per_launch = (24.0 + 32.0 + 32.0) / 3.0 * npts
     achieved = bytes_per_launch / launch_s / 1e9
-    kname = ("k_dense_pass<double,128,REDUCED> (matrix-core route" if res["f64"]["route"] != "fft"
+    route = res["f64"]["route"]
+    kname = (f"k_dense_pass<double,128,REDUCED,*,{route[-1]}> (matrix-core route" if route != "fft"
              else "k_axis_pass<double,128,REDUCED> (FFT route")
+    rec = _traffic_record(route)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kname + f", tile shape {res['f64']['route']}; 3 launches per apply)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(rec["traffic_bytes_per_launch"] / 1e6, 2) if rec else None,
+                "traffic_unit": "MB per launch (rocprofv3 TCC request counters, copy-calibrated)",
+                "algorithmic_mb_per_launch": round(bytes_per_launch / 1e6, 2),
+                "kernel": kname + "; 3 launches per apply)",
                 "bytes_per_point_per_launch": 29.33}
     if res["f64"]["route"] != "fft":
         # the same launches priced against the FP64 matrix-core peak: the
