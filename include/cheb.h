@@ -229,6 +229,41 @@ int cheb_debug_gemm(int32_t precision, const void* A, const void* B, void* D, in
 const char* cheb_status_string(int status);
 const char* cheb_last_error(void);
 
+/* ---- batched solves (many independent systems in lockstep) --------------
+ * For studies that solve many small problems at once, e.g. the homogenisation
+ * of a set of microstructures under three load cases each (Section 3.3 defines
+ * the effective conductivity from such solves).  Every Krylov step of all
+ * systems is a few launches: one matrix-core operator pass per group of
+ * identical grids and axis, over a tile queue spanning the group, one
+ * fast-diagonalisation contraction per group of identical grids and face types,
+ * and segmented vector kernels.  Systems that converge drop out of the queues.
+ */
+typedef struct cheb_batch cheb_batch;
+
+/* nprob systems, system s on grids[s] (any sizes and face types; systems with
+ * the same n, lo, hi share operator launches).  precision: CHEB_F64 or
+ * CHEB_MIXED (FP64 fields at the ABI).  Allocates the per-system plans and a few
+ * KB of device tables. */
+int cheb_batch_create(const cheb_grid* grids, int32_t nprob, int32_t precision, void* stream, cheb_batch** out);
+
+/* Device workspace of cheb_batch_solve (all systems' fields packed back to back). */
+int cheb_batch_workspace_bytes(const cheb_batch* batch, const cheb_solve_opts* opts, size_t* bytes);
+int cheb_batch_set_workspace(cheb_batch* batch, void* dev_ptr, size_t bytes);
+int cheb_batch_set_stream(cheb_batch* batch, void* stream);
+
+/* Solve all systems.  K, f, g_faces, u_inout: host arrays of nprob device
+ * pointers (FP64, each system's own layout as in cheb_solve; systems may share
+ * a K pointer, e.g. the load cases of one microstructure).  opts apply to every
+ * system (rtol relative to each system's own right-hand side; flags bit 0 warm
+ * start, bit 1 preconditioner).  infos (host, nprob entries, may be NULL)
+ * receive the per-system results.  Returns the worst per-system status, or a
+ * negative error (outputs untouched on CHEB_ERR_BAD_INPUT).  Synchronises the
+ * stream. */
+int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const* f, const void* const* g_faces,
+                     void* const* u_inout, const cheb_solve_opts* opts, cheb_solve_info* infos);
+
+int cheb_batch_destroy(cheb_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,16 @@ _SIGS = {
     "cheb_flux_average": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "cheb_debug_gemm": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp]),
+    "cheb_batch_create": (ctypes.c_int, [ctypes.POINTER(cheb_grid), ctypes.c_int32, ctypes.c_int32, _vp,
+                                         ctypes.POINTER(_vp)]),
+    "cheb_batch_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(cheb_solve_opts),
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "cheb_batch_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "cheb_batch_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "cheb_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_vp), ctypes.POINTER(cheb_solve_opts),
+                                        ctypes.POINTER(cheb_solve_info)]),
+    "cheb_batch_destroy": (ctypes.c_int, [_vp]),
     "cheb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cheb_last_error": (ctypes.c_char_p, []),
 }

@@ -235,6 +235,129 @@ class Plan:
         return [out[0], out[1], out[2]]
 
 
+class Batch:
+    """Many independent systems solved in lockstep (cheb_batch_*).
+
+    ``grids``: list of (n, lo, hi, bc) tuples, one per system.  Systems with the
+    same n, lo, hi share operator launches; systems that also share the face
+    types share preconditioner launches."""
+
+    def __init__(self, grids, precision="f64", device="cuda"):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.precision = precision
+        self.grids = [(tuple(int(v) for v in n), tuple(float(v) for v in lo), tuple(float(v) for v in hi),
+                       tuple(int(v) for v in bc)) for n, lo, hi, bc in grids]
+        arr = (L.cheb_grid * len(self.grids))()
+        for i, (n, lo, hi, bc) in enumerate(self.grids):
+            for a in range(3):
+                arr[i].n[a], arr[i].lo[a], arr[i].hi[a] = n[a], lo[a], hi[a]
+            for f in range(6):
+                arr[i].bc[f] = bc[f]
+        self._h = ctypes.c_void_p()
+        L.check(self.lib.cheb_batch_create(arr, len(self.grids), _PREC[precision],
+                                           ctypes.c_void_p(_stream_handle(self.device)), ctypes.byref(self._h)))
+        self._ws = None
+        self._ws_bytes = 0
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.cheb_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, opts=None):
+        o, _ = (opts or SolveOptions()).to_c(False)
+        b = ctypes.c_size_t()
+        L.check(self.lib.cheb_batch_workspace_bytes(self._h, ctypes.byref(o), ctypes.byref(b)))
+        return int(b.value)
+
+    def ensure_workspace(self, opts=None):
+        need = self.workspace_bytes(opts)
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws_bytes = need
+            L.check(self.lib.cheb_batch_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()),
+                                                      ctypes.c_size_t(need)))
+        return self._ws
+
+    def solve(self, Ks, fs, gs, us=None, opts=None):
+        """Solve every system; returns (list of full-grid solutions, list of info dicts)."""
+        opts = opts or SolveOptions()
+        ns = len(self.grids)
+        assert len(Ks) == len(fs) == len(gs) == ns
+        warm = us is not None
+        if us is None:
+            us = [torch.zeros(g[0], dtype=torch.float64, device=self.device) for g in self.grids]
+        for i, (n, _, _, _) in enumerate(self.grids):
+            for name, t, shape in (("K", Ks[i], n), ("f", fs[i], n), ("u", us[i], n)):
+                if t.dtype != torch.float64 or tuple(t.shape) != n or not t.is_contiguous():
+                    raise ValueError(f"{name}[{i}]: expected a contiguous float64 tensor of shape {n}")
+            if gs[i].dtype != torch.float64 or not gs[i].is_contiguous():
+                raise ValueError(f"g[{i}]: expected a contiguous float64 tensor")
+        self.ensure_workspace(opts)
+        L.check(self.lib.cheb_batch_set_stream(self._h, ctypes.c_void_p(_stream_handle(self.device))))
+        arr = lambda ts: (ctypes.c_void_p * ns)(*[t.data_ptr() for t in ts])
+        o, hist = opts.to_c(warm)
+        infos = (L.cheb_solve_info * ns)()
+        rc = L.check(self.lib.cheb_batch_solve(self._h, arr(Ks), arr(fs), arr(gs), arr(us), ctypes.byref(o), infos))
+        out = []
+        for i in range(ns):
+            d = infos[i].as_dict()
+            d["rc"] = rc
+            out.append(d)
+        return us, out
+
+
+def load_case(n, axis, device="cuda"):
+    """Boundary data of homogenisation load case `axis`: u = 0 on the axis' lo
+    face, 1 on its hi face (unit mean gradient on the unit box), zero flux on
+    the other four faces.  Returns (bc, packed face data)."""
+    bc = [1] * 6
+    bc[2 * axis] = bc[2 * axis + 1] = 0
+    sizes = [n[1] * n[2], n[1] * n[2], n[0] * n[2], n[0] * n[2], n[0] * n[1], n[0] * n[1]]
+    g = torch.zeros(sum(sizes), dtype=torch.float64, device=device)
+    start = sum(sizes[:2 * axis + 1])
+    g[start:start + sizes[2 * axis + 1]] = 1.0
+    return tuple(bc), g
+
+
+def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", opts=None, device="cuda"):
+    """Apparent conductivity tensors of several microstructures (Section 3.3):
+    three load cases per microstructure (unit mean gradient along x, y, z
+    through Dirichlet faces, zero flux elsewhere) solved together in one batch,
+    then K_app[b][a] = <K du^(a)/dx_b>_CC / G_a with Clenshaw-Curtis volume
+    averages.  Returns (list of 3x3 nested lists, per-system infos, solutions)."""
+    grids, KK, ff, gg = [], [], [], []
+    for K in Ks:
+        n = tuple(K.shape)
+        for a in range(3):
+            bc, g = load_case(n, a, device)
+            grids.append((n, lo, hi, bc))
+            KK.append(K)
+            ff.append(torch.zeros(n, dtype=torch.float64, device=device))
+            gg.append(g)
+    batch = Batch(grids, precision, device)
+    us, infos = batch.solve(KK, ff, gg, opts=opts)
+    out = []
+    for s, K in enumerate(Ks):
+        n = tuple(K.shape)
+        plan = Plan(n, lo, hi, grids[3 * s][3], "f64", device)
+        Kapp = [[0.0] * 3 for _ in range(3)]
+        for a in range(3):
+            G = 1.0 / (hi[a] - lo[a])
+            fa = plan.flux_average(K, us[3 * s + a])
+            for b in range(3):
+                Kapp[b][a] = fa[b] / G
+        out.append(Kapp)
+    return out, infos, us
+
+
 def debug_gemm(A, B):
     """D = A @ B on the matrix cores (the preconditioner's contraction kernel)."""
     lib = L.load()

@@ -7,6 +7,8 @@
 
 namespace cheb {
 
+template int launch_dense_batch<double>(const cheb_plan*, int, int, const double*, const double*, double*, const DenseSys*,
+                                      const int*, int, hipStream_t);
 template int launch_dense_pass<double>(const cheb_plan*, int, int, int, const double*, const double*, double*,
                                        hipStream_t);
 

@@ -30,7 +30,7 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
     resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
   }
   const int ta = a.axis == 0 ? a.n[1] : a.n[0], tb = a.axis == 2 ? a.n[1] : a.n[2];
-  const int tiles = ((ta - 2) * (tb - 2) + S.C - 1) / S.C;
+  const int tiles = ((ta - 2) * (tb - 2) + S.C - 1) / S.C * (a.sys ? a.nact : 1);
   const int grid = tiles < resident ? (tiles > 0 ? tiles : 1) : resident;
   hipLaunchKernelGGL((k_dense_pass<T, NC, MODE, FIRST, V>), dim3(grid), dim3(64 * S.NW), lds, s, a);
   return hip_check(hipGetLastError(), "matrix-core pass launch");
@@ -62,12 +62,15 @@ inline const float* dense_tab<float>(const cheb_plan* p, int axis, int transpose
 }
 
 template <typename T>
-int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
-                      hipStream_t s) {
+static int launch_dense_common(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u,
+                               T* y, const DenseSys* sys, const int* act, int nact, hipStream_t s) {
   DenseArgs<T> a;
   a.u = u;
   a.K = K;
   a.y = y;
+  a.sys = sys;
+  a.act = act;
+  a.nact = nact;
   a.tab = dense_tab<T>(p, axis, transpose);
   a.sink = (T*)p->dsink;
   const size_t slot0 = (size_t)(kConstSlots * axis) * p->dconst_stride;
@@ -98,6 +101,19 @@ int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, co
     case 128: return launch_dense_n<T, 128>(a, transpose, variant, s);
     default: set_error("matrix-core pass: unsupported N"); return CHEB_ERR_UNSUPPORTED;
   }
+}
+
+template <typename T>
+int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
+                      hipStream_t s) {
+  return launch_dense_common<T>(p, axis, transpose, first, K, u, y, nullptr, nullptr, 0, s);
+}
+
+template <typename T>
+int launch_dense_batch(const cheb_plan* rep, int axis, int first, const T* K, const T* u, T* y,
+                       const DenseSys* sys, const int* act, int nact, hipStream_t s) {
+  if (nact <= 0) return CHEB_OK;
+  return launch_dense_common<T>(rep, axis, 0, first, K, u, y, sys, act, nact, s);
 }
 
 }  // namespace cheb

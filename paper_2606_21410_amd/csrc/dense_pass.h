@@ -84,17 +84,28 @@ __host__ __device__ constexpr int dense_lds_bytes(int N, int V) {
   return (tabl + 2 * n * SC + 2 * n + 2 * d.C) * (int)sizeof(T) + 2 * d.C * (int)sizeof(int);
 }
 
+// one system of a batched pass (same N, box and tile shape as the others): its
+// offset in the packed fields and its face types
+struct DenseSys {
+  long long off;
+  int bcmask;
+  int pad_;
+};
+
 template <typename T>
 struct DenseArgs {
-  const T* u;
+  const T* u;  // single system (sys == nullptr)
   const T* K;
   T* y;
+  const DenseSys* sys;  // batched: system table (device) and the active systems' indices
+  const int* act;
+  int nact;
   const T* tab;    // fragment table of D (reduced) or D^T (transpose)
   const T* drow0;  // face rows D[0][:], D[N][:] for the lift
   const T* drowN;
   T* sink;         // one word that stores of off-tile elements go to
   int n[3];
-  int axis, first, bcmask, npencils;
+  int axis, first, bcmask, npencils;  // bcmask of the single system
   T m00, m0N, mN0, mNN;
 };
 
@@ -210,7 +221,7 @@ struct DenseArgs {
 #define DENSE_COLS(SLOT, TILE)                                             \
   do {                                                                     \
     if (tid < C) {                                                         \
-      const int q_ = (TILE) * C + tid;                                     \
+      const int q_ = ((TILE) % tps) * C + tid;                             \
       int b_ = -1;                                                         \
       if (q_ < npen) {                                                     \
         const int ia_ = 1 + q_ / nbi, ib_ = 1 + (q_ - (q_ / nbi) * nbi);   \
@@ -223,7 +234,7 @@ struct DenseArgs {
 // global -> registers: u (interior nodes) and K of the tile in slot SLOT.
 // Every load is issued (off-tile elements read node 0 and are discarded), so
 // the number of outstanding loads is static and the compiler's waits stay exact.
-#define DENSE_LOAD(SLOT, UR, KR)                                      \
+#define DENSE_LOAD(SLOT, UR, KR, PU, PK)                              \
   do {                                                                \
     int ad_[EPT];                                                     \
     bool ok_[EPT], in_[EPT];                                          \
@@ -237,13 +248,30 @@ struct DenseArgs {
       ad_[q] = ok_[q] ? b + j * stride : 0;                           \
     }                                                                 \
     _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
-      UR[q] = a.u[ad_[q]];                                            \
-      KR[q] = a.K[ad_[q]];                                            \
+      UR[q] = (PU)[ad_[q]];                                           \
+      KR[q] = (PK)[ad_[q]];                                           \
     }                                                                 \
     _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
       UR[q] = in_[q] ? UR[q] : T(0);                                  \
       KR[q] = ok_[q] ? KR[q] : T(0);                                  \
     }                                                                 \
+  } while (0)
+
+// pointers and face types of the system that owns tile TILE
+#define DENSE_SYS(TILE, PU, PK, PY, BM)                   \
+  do {                                                    \
+    if (a.sys) {                                          \
+      const DenseSys s_ = a.sys[a.act[(TILE) / tps]];     \
+      PU = a.u + s_.off;                                  \
+      PK = a.K + s_.off;                                  \
+      PY = a.y + s_.off;                                  \
+      BM = s_.bcmask;                                     \
+    } else {                                              \
+      PU = a.u;                                           \
+      PK = a.K;                                           \
+      PY = a.y;                                           \
+      BM = a.bcmask;                                      \
+    }                                                     \
   } while (0)
 
 // Persistent: each workgroup walks tiles blockIdx.x, +gridDim.x, ... over the
@@ -286,8 +314,10 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   const bool contig = axis == 2;
   const int nai = (axis == 0 ? n1 : n0) - 2, nbi = (axis == 2 ? n1 : n2) - 2;
   const int npen = nai * nbi;
-  const int ntiles = (npen + C - 1) / C;
-  const bool nlo = (a.bcmask >> (2 * axis)) & 1, nhi = (a.bcmask >> (2 * axis + 1)) & 1;
+  const int tps = (npen + C - 1) / C;  // tiles per system
+  const int nsys = a.sys ? a.nact : 1;
+  const int ntiles = nsys * tps;
+  bool nlo = false, nhi = false;
   const T* Ao = tab + mt * S.KO4 * 64 + lane;
   const T* Ae = tab + S.OFF_E + mt * S.KE4 * 64 + lane;
   T ao[V == 1 ? S.KO4 : 1], ae[V == 1 ? S.KE4 : 1];
@@ -302,7 +332,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     // pencils in a face: every node is a boundary node of the reduced system
     const int na = nai + 2, nb = nbi + 2;
     const int nface = na * nb - npen;
-    for (int f = blockIdx.x; f < nface; f += gridDim.x) {
+    for (int fs = blockIdx.x; fs < nsys * nface; fs += gridDim.x) {
+      const int f = fs % nface;
+      T* ys = a.sys ? a.y + a.sys[a.act[fs / nface]].off : a.y;
       int ia, ib;
       if (f < 2 * nb) {
         ia = f < nb ? 0 : na - 1;
@@ -313,7 +345,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         ib = (g & 1) ? nb - 1 : 0;
       }
       const int b = axis == 2 ? (ia * n1 + ib) * n2 : axis == 1 ? ia * n1 * n2 + ib : ia * n2 + ib;
-      for (int j = tid; j < n; j += NT) a.y[b + j * stride] = T(0);
+      for (int j = tid; j < n; j += NT) ys[b + j * stride] = T(0);
     }
   }
 
@@ -338,12 +370,18 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   }
   int slot = 0;
   DENSE_COLS(0, tile);
+  const T *cu, *cK, *nu, *nK;
+  T* cy;
+  int cbm;
+  DENSE_SYS(tile < ntiles ? tile : 0, cu, cK, cy, cbm);
+  nu = cu;
+  nK = cK;
   __syncthreads();
   // V = 0 prefetches the next tile into registers; V = 1 loads each tile when
   // it starts and relies on the second workgroup of the CU for overlap
   constexpr bool PREF = V == 0;
   T ureg[EPT], kreg[EPT];
-  if (PREF) DENSE_LOAD(0, ureg, kreg);
+  if (PREF) DENSE_LOAD(0, ureg, kreg, cu, cK);
 #pragma unroll
   for (int i = 0; i < TI; ++i)
     if (tid + i * NT < S.TAB - TB) tab[TB + tid + i * NT] = tv[i];
@@ -359,7 +397,10 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   for (; tile < t_end; tile += t_step, slot ^= 1) {
     const int nxt = tile + t_step < t_end ? tile + t_step : ntiles;
     __syncthreads();  // previous tile's readers of U and of slot^1 are done
-    if (!PREF) DENSE_LOAD(slot, ureg, kreg);
+    DENSE_SYS(tile, cu, cK, cy, cbm);
+    nlo = (cbm >> (2 * axis)) & 1;
+    nhi = (cbm >> (2 * axis + 1)) & 1;
+    if (!PREF) DENSE_LOAD(slot, ureg, kreg, cu, cK);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
@@ -382,6 +423,11 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     int pad[PREF ? EPT : 1], yad[EPT];
     bool pok[PREF ? EPT : 1], pin[PREF ? EPT : 1];
     {
+      T* ny_;
+      int nbm_;
+      DENSE_SYS(nxt < ntiles ? nxt : tile, nu, nK, ny_, nbm_);
+      (void)ny_;
+      (void)nbm_;
       const int ps = slot ^ 1;
       const bool more = nxt < ntiles;
 #pragma unroll
@@ -406,13 +452,13 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 #define DENSE_ISSUE1(KS)                                                          \
   do {                                                                            \
     if (PREF && (KS) < 2 * EPT) {                                                 \
-      if ((KS) % 2 == 0) unx[PREF ? (KS) / 2 : 0] = a.u[pad[PREF ? (KS) / 2 : 0]]; \
-      else knx[PREF ? (KS) / 2 : 0] = a.K[pad[PREF ? (KS) / 2 : 0]];              \
+      if ((KS) % 2 == 0) unx[PREF ? (KS) / 2 : 0] = nu[pad[PREF ? (KS) / 2 : 0]];  \
+      else knx[PREF ? (KS) / 2 : 0] = nK[pad[PREF ? (KS) / 2 : 0]];               \
     }                                                                             \
   } while (0)
 #define DENSE_ISSUE2(KS)                                                          \
   do {                                                                            \
-    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = a.y[yad[(KS) < EPT ? (KS) : 0]]; \
+    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = cy[yad[(KS) < EPT ? (KS) : 0]]; \
   } while (0)
 #define DENSE_ISSUE_NONE(KS) \
   do {                       \
@@ -426,8 +472,8 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 #pragma unroll
     for (int ks = S.KE4; ks < (PREF ? 2 * EPT : 0); ++ks) {
       if (PREF && ks < 2 * EPT) {
-        if (ks % 2 == 0) unx[PREF ? ks / 2 : 0] = a.u[pad[PREF ? ks / 2 : 0]];
-        else knx[PREF ? ks / 2 : 0] = a.K[pad[PREF ? ks / 2 : 0]];
+        if (ks % 2 == 0) unx[PREF ? ks / 2 : 0] = nu[pad[PREF ? ks / 2 : 0]];
+        else knx[PREF ? ks / 2 : 0] = nK[pad[PREF ? ks / 2 : 0]];
       }
     }
     DENSE_VDOT(midv, MODE == DENSE_REDUCED);
@@ -446,7 +492,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_GEMM(acco, acce, DENSE_ISSUE2);
 #pragma unroll
     for (int q = S.KE4; q < EPT; ++q)
-      if (!FIRST) yreg[q] = a.y[yad[q]];
+      if (!FIRST) yreg[q] = cy[yad[q]];
     DENSE_VDOT(midv, false);
     __syncthreads();
     DENSE_EPI(acco, acce, midv, false, false);
@@ -489,7 +535,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         if (MODE == DENSE_TRANSPOSE) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
         if (!FIRST) x += yreg[q];
         ov[q] = in ? x : T(0);
-        op[q] = ok ? a.y + (b + j * stride) : a.sink;
+        op[q] = ok ? cy + (b + j * stride) : a.sink;
       }
 #pragma unroll
       for (int q = 0; q < EPT; ++q) *op[q] = ov[q];
@@ -513,5 +559,6 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 #undef DENSE_EPI
 #undef DENSE_COLS
 #undef DENSE_LOAD
+#undef DENSE_SYS
 
 }  // namespace cheb

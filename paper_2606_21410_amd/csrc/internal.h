@@ -90,6 +90,12 @@ int apply_t(const cheb_plan* p, const T* K, const T* u, T* y, int mode, hipStrea
 
 // ---- matrix-core route (dense_f64.hip / dense_f32.hip) ----
 int dense_setup(cheb_plan* p);
+struct DenseSys;
+// batched reduced pass over the systems act[0..nact) of the table sys (same N,
+// box and tile shape as `rep`); K, u, y are packed bases
+template <typename T>
+int launch_dense_batch(const cheb_plan* rep, int axis, int first, const T* K, const T* u, T* y,
+                       const DenseSys* sys, const int* act, int nact, hipStream_t s);
 // transpose: 0 reduced pass, 1 transposed reduced pass
 template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
@@ -150,6 +156,11 @@ int precond_setup(cheb_plan* p);
 template <typename T>
 int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, double kc, bool transpose,
                   hipStream_t s);
+// batched: members k < nmem of one group (same grid and face types as `rep`),
+// packed fields at offs[k] (device), mean conductivity kc[sys[k]] (device)
+template <typename T>
+int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long long* offs, const int* sys,
+                        const double* kc, int nmem, T* bufA, T* bufB, hipStream_t s);
 // sum of all entries (double accumulation) into out[0]
 template <typename T>
 int vsum(const T* x, size_t npts, double* partials, double* out, hipStream_t s);

@@ -328,6 +328,55 @@ __global__ void k_eig_scale(T* x, const T* lx, const T* ly, const T* lz, double 
   }
 }
 
+// batched variants: member k of a group reads / writes the packed field at
+// offs[k] and owns block k of the packed interior buffers
+template <typename T>
+__global__ void k_pack_interior_b(const T* __restrict__ in, const long long* __restrict__ offs, T* __restrict__ out,
+                                  int n0, int n1, int n2) {
+  const int m0 = n0 - 2, m1 = n1 - 2, m2 = n2 - 2;
+  const size_t tot = (size_t)m0 * m1 * m2;
+  const T* src = in + offs[blockIdx.y];
+  T* dst = out + (size_t)blockIdx.y * tot;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % m2);
+    const size_t r = t / m2;
+    const int j = (int)(r % m1), i = (int)(r / m1);
+    dst[t] = src[((size_t)(i + 1) * n1 + (j + 1)) * n2 + (k + 1)];
+  }
+}
+
+template <typename T>
+__global__ void k_unpack_interior_b(const T* __restrict__ in, const long long* __restrict__ offs, T* __restrict__ out,
+                                    int n0, int n1, int n2) {
+  const size_t tot = (size_t)n0 * n1 * n2;
+  const int m1 = n1 - 2, m2 = n2 - 2;
+  const T* src = in + (size_t)blockIdx.y * (size_t)(n0 - 2) * m1 * m2;
+  T* dst = out + offs[blockIdx.y];
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % n2);
+    const size_t r = t / n2;
+    const int j = (int)(r % n1), i = (int)(r / n1);
+    T v = T(0);
+    if (i > 0 && i < n0 - 1 && j > 0 && j < n1 - 1 && k > 0 && k < n2 - 1)
+      v = src[((size_t)(i - 1) * m1 + (j - 1)) * m2 + (k - 1)];
+    dst[t] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_eig_scale_b(T* x, const T* lx, const T* ly, const T* lz, const int* __restrict__ sys,
+                              const double* __restrict__ kc, int m0, int m1, int m2) {
+  const size_t tot = (size_t)m0 * m1 * m2;
+  T* xb = x + (size_t)blockIdx.y * tot;
+  const double inv_k = 1.0 / kc[sys[blockIdx.y]];
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % m2);
+    const size_t r = t / m2;
+    const int j = (int)(r % m1), i = (int)(r / m1);
+    xb[t] = T(double(xb[t]) * inv_k / (double(lx[i]) + double(ly[j]) + double(lz[k])));
+  }
+}
+
 inline int grid1(size_t n) {
   size_t g = (n + 1023) / 1024;
   return (int)std::max<size_t>(1, std::min<size_t>(g, 8192));
@@ -385,16 +434,18 @@ const double* pc_base<double>(const cheb_plan* p) { return p->pc64; }
 template <>
 const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
 
-// Y = M applied along `axis` of the packed block X (m0, m1, m2); trans uses M^T
+// Y = M applied along `axis` of the packed block X (m0, m1, m2); trans uses M^T.
+// nb consecutive blocks of the same shape are contracted by one launch.
 template <typename T>
-static int axis_contract(const T* M, bool trans, int axis, const int* m, const T* X, T* Y, hipStream_t s) {
+static int axis_contract(const T* M, bool trans, int axis, const int* m, const T* X, T* Y, hipStream_t s,
+                         int nb = 1) {
   GemmArgs g;
   const long long msz = m[axis];
   const long long ms_i = trans ? 1 : msz, ms_k = trans ? msz : 1;  // M(i,k) strides
   if (axis == 2) {
     // Y[r, i] = sum_k X[r, k] M[i, k]: rows r, columns i
     g.A = X; g.B = M; g.D = Y;
-    g.I = m[0] * m[1]; g.Kd = m[2]; g.C = m[2];
+    g.I = m[0] * m[1] * nb; g.Kd = m[2]; g.C = m[2];
     g.a_si = m[2]; g.a_sk = 1;
     g.b_sk = ms_k; g.b_sc = ms_i;
     g.d_si = m[2]; g.d_sc = 1;
@@ -404,7 +455,7 @@ static int axis_contract(const T* M, bool trans, int axis, const int* m, const T
   } else {
     // Y_b = M X_b with X_b (m_axis x C), C = product of the later dims
     const int C = axis == 0 ? m[1] * m[2] : m[2];
-    const int batch = axis == 0 ? 1 : m[0];
+    const int batch = (axis == 0 ? 1 : m[0]) * nb;
     g.A = M; g.B = X; g.D = Y;
     g.I = m[axis]; g.Kd = m[axis]; g.C = C;
     g.a_si = ms_i; g.a_sk = ms_k;
@@ -464,6 +515,40 @@ int mfma_gemm(const T* A, const T* B, T* D, int I, int K, int C, hipStream_t s) 
   return hip_check(hipGetLastError(), "mfma gemm");
 }
 
+template <typename T>
+int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long long* offs, const int* sys,
+                        const double* kc, int nmem, T* bufA, T* bufB, hipStream_t s) {
+  if (nmem <= 0) return CHEB_OK;
+  const int n0 = rep->g.n[0], n1 = rep->g.n[1], n2 = rep->g.n[2];
+  const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
+  const size_t tot = (size_t)m[0] * m[1] * m[2];
+  const T* base = pc_base<T>(rep);
+  hipLaunchKernelGGL(k_pack_interior_b<T>, dim3(grid1(tot), nmem), dim3(256), 0, s, in, offs, bufA, n0, n1, n2);
+  int rc = hip_check(hipGetLastError(), "batched pack");
+  T* x = bufA;
+  T* y = bufB;
+  for (int a = 0; a < 3 && !rc; ++a) {
+    rc = axis_contract<T>(base + rep->pc_ax[a].off_Vi, false, a, m, x, y, s, nmem);
+    std::swap(x, y);
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_eig_scale_b<T>, dim3(grid1(tot), nmem), dim3(256), 0, s, x, base + rep->pc_ax[0].off_lam,
+                     base + rep->pc_ax[1].off_lam, base + rep->pc_ax[2].off_lam, sys, kc, m[0], m[1], m[2]);
+  rc = hip_check(hipGetLastError(), "batched eigen scale");
+  for (int a = 2; a >= 0 && !rc; --a) {
+    rc = axis_contract<T>(base + rep->pc_ax[a].off_V, false, a, m, x, y, s, nmem);
+    std::swap(x, y);
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_unpack_interior_b<T>, dim3(grid1((size_t)n0 * n1 * n2), nmem), dim3(256), 0, s, x, offs,
+                     out, n0, n1, n2);
+  return hip_check(hipGetLastError(), "batched unpack");
+}
+
+template int precond_apply_batch<double>(const cheb_plan*, const double*, double*, const long long*, const int*,
+                                         const double*, int, double*, double*, hipStream_t);
+template int precond_apply_batch<float>(const cheb_plan*, const float*, float*, const long long*, const int*,
+                                        const double*, int, float*, float*, hipStream_t);
 template int precond_apply<double>(const cheb_plan*, const double*, double*, double*, double*, double, bool,
                                    hipStream_t);
 template int precond_apply<float>(const cheb_plan*, const float*, float*, float*, float*, double, bool,

@@ -68,3 +68,17 @@ def test_plan_validation_precision_and_nulls():
     assert lib.cheb_solve(None, None, None, None, None, None, None) == L.CHEB_ERR_INVALID_ARG
     assert lib.cheb_prolong(None, None, None, None, None, None) == L.CHEB_ERR_INVALID_ARG
     assert lib.cheb_plan_destroy(None) == L.CHEB_OK
+
+
+def test_load_case_packing_matches_generator():
+    """The binding's homogenisation load cases pack the same face data and face
+    types as the workload generator."""
+    import numpy as np
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import load_case
+    n = (5, 7, 6)
+    grid = W.Grid(n, (0, 0, 0), (1, 1, 1), W.MIXED_X_BC)
+    for a in range(3):
+        bc, g = load_case(n, a, device="cpu")
+        assert bc == W.load_case_bc(a)
+        np.testing.assert_array_equal(g.numpy(), W.load_case_faces(grid, a))
