@@ -66,6 +66,10 @@ struct cheb_batch {
   int* ch_len;
   int* sys_c0;
   int* sys_nc;
+  int* chl;       // device list of the chunks of the active systems
+  int nchl;       // its length
+  std::vector<int> hchl;
+  std::vector<int> sys_c0_h, sys_nc_h;
   double* dcoef;  // nprob x kMaxCoef per-system coefficients
   double* dscal;  // nprob x 8 per-system scalars
   double* dkc;    // nprob mean conductivities
@@ -104,10 +108,10 @@ __device__ __forceinline__ void block_sum(double (&v)[G], double* red) {
 // blockIdx.y selects the group of 8 outputs
 template <typename T>
 __global__ __launch_bounds__(kBT) void k_bdot(const T* __restrict__ V, size_t ld, int nv, const T* __restrict__ w,
-                                              const long long* __restrict__ beg, const int* __restrict__ len,
-                                              double* __restrict__ partials) {
+                                              const int* __restrict__ chl, const long long* __restrict__ beg,
+                                              const int* __restrict__ len, double* __restrict__ partials) {
   __shared__ double red[4 * 8];
-  const int ch = blockIdx.x, i0 = blockIdx.y * 8, nv1 = nv + 1;
+  const int ch = chl[blockIdx.x], i0 = blockIdx.y * 8, nv1 = nv + 1;
   const long long b = beg[ch];
   const int L = len[ch];
   double acc[8];
@@ -145,9 +149,9 @@ __global__ __launch_bounds__(kBT) void k_breduce(const double* __restrict__ part
 template <typename T>
 __global__ __launch_bounds__(kBT) void k_bupdate(const T* __restrict__ V, size_t ld, int nv, const double* h,
                                                  int hstride, const double* scale, int sstride, const T* w, T* out,
-                                                 const int* __restrict__ sysv, const long long* __restrict__ beg,
-                                                 const int* __restrict__ len) {
-  const int ch = blockIdx.x, s = sysv[ch];
+                                                 const int* __restrict__ chl, const int* __restrict__ sysv,
+                                                 const long long* __restrict__ beg, const int* __restrict__ len) {
+  const int ch = chl[blockIdx.x], s = sysv[ch];
   const long long b = beg[ch];
   const int L = len[ch];
   const double* hs = h + (size_t)s * hstride;
@@ -159,18 +163,21 @@ __global__ __launch_bounds__(kBT) void k_bupdate(const T* __restrict__ V, size_t
   }
 }
 
-// out (+)= sum_i c[s][i] V_i
+// out (+)= sum_i c[s][i] V_i; terms with a zero coefficient are skipped, so
+// basis columns a system never wrote (it stopped early) are never read
 template <typename T>
 __global__ __launch_bounds__(kBT) void k_blincomb(const T* __restrict__ V, size_t ld, int nv, const double* c,
-                                                  int cstride, T* out, int accumulate, const int* __restrict__ sysv,
-                                                  const long long* __restrict__ beg, const int* __restrict__ len) {
-  const int ch = blockIdx.x, s = sysv[ch];
+                                                  int cstride, T* out, int accumulate, const int* __restrict__ chl,
+                                                  const int* __restrict__ sysv, const long long* __restrict__ beg,
+                                                  const int* __restrict__ len) {
+  const int ch = chl[blockIdx.x], s = sysv[ch];
   const long long b = beg[ch];
   const int L = len[ch];
   const double* cs = c + (size_t)s * cstride;
   for (int e = threadIdx.x; e < L; e += kBT) {
     double x = accumulate ? double(out[b + e]) : 0.0;
-    for (int i = 0; i < nv; ++i) x += cs[i] * double(V[(size_t)i * ld + b + e]);
+    for (int i = 0; i < nv; ++i)
+      if (cs[i] != 0.0) x += cs[i] * double(V[(size_t)i * ld + b + e]);
     out[b + e] = T(x);
   }
 }
@@ -178,9 +185,10 @@ __global__ __launch_bounds__(kBT) void k_blincomb(const T* __restrict__ V, size_
 // y = alpha[s] x + beta[s] y   (alpha at scal[s*stride + ia], beta at + ib)
 template <typename TY, typename TX>
 __global__ __launch_bounds__(kBT) void k_baxpby(TY* y, const TX* __restrict__ x, const double* scal, int stride,
-                                                int ia, int ib, const int* __restrict__ sysv,
-                                                const long long* __restrict__ beg, const int* __restrict__ len) {
-  const int ch = blockIdx.x, s = sysv[ch];
+                                                int ia, int ib, const int* __restrict__ chl,
+                                                const int* __restrict__ sysv, const long long* __restrict__ beg,
+                                                const int* __restrict__ len) {
+  const int ch = chl[blockIdx.x], s = sysv[ch];
   const long long b = beg[ch];
   const int L = len[ch];
   const double al = scal[(size_t)s * stride + ia];
@@ -297,8 +305,13 @@ int upload(cheb_batch* B, double* dev, const double* host_src, size_t count, int
 template <typename T>
 int bdots(cheb_batch* B, const T* V, size_t ld, int nv, const T* w, BScratch& sc, std::vector<double>& out) {
   const int nv1 = nv + 1;
-  dim3 grid(B->nchunks, (nv1 + 7) / 8);
-  hipLaunchKernelGGL(k_bdot<T>, grid, dim3(kBT), 0, B->stream, V, ld, nv, w, B->ch_beg, B->ch_len, sc.partials);
+  if (B->nchl == 0) {
+    out.assign((size_t)B->nprob * kMaxCoef, 0.0);
+    return CHEB_OK;
+  }
+  dim3 grid(B->nchl, (nv1 + 7) / 8);
+  hipLaunchKernelGGL(k_bdot<T>, grid, dim3(kBT), 0, B->stream, V, ld, nv, w, B->chl, B->ch_beg, B->ch_len,
+                     sc.partials);
   int rc = hip_check(hipGetLastError(), "batched multi-dot");
   if (rc) return rc;
   hipLaunchKernelGGL(k_breduce, dim3(B->nprob), dim3(kBT), 0, B->stream, sc.partials, nv1, B->sys_c0, B->sys_nc,
@@ -317,27 +330,47 @@ int bdots(cheb_batch* B, const T* V, size_t ld, int nv, const T* w, BScratch& sc
 
 template <typename T>
 int bupdate(cheb_batch* B, const T* V, size_t ld, int nv, const T* w, T* out) {
-  hipLaunchKernelGGL(k_bupdate<T>, dim3(B->nchunks), dim3(kBT), 0, B->stream, V, ld, nv, B->dcoef, kMaxCoef,
-                     B->dscal, 8, w, out, B->ch_sys, B->ch_beg, B->ch_len);
+  if (B->nchl == 0) return CHEB_OK;
+  hipLaunchKernelGGL(k_bupdate<T>, dim3(B->nchl), dim3(kBT), 0, B->stream, V, ld, nv, B->dcoef, kMaxCoef,
+                     B->dscal, 8, w, out, B->chl, B->ch_sys, B->ch_beg, B->ch_len);
   return hip_check(hipGetLastError(), "batched update");
 }
 
 template <typename T>
 int blincomb(cheb_batch* B, const T* V, size_t ld, int nv, int coef_off, T* out, int acc) {
-  hipLaunchKernelGGL(k_blincomb<T>, dim3(B->nchunks), dim3(kBT), 0, B->stream, V, ld, nv, B->dcoef + coef_off,
-                     kMaxCoef, out, acc, B->ch_sys, B->ch_beg, B->ch_len);
+  if (B->nchl == 0) return CHEB_OK;
+  hipLaunchKernelGGL(k_blincomb<T>, dim3(B->nchl), dim3(kBT), 0, B->stream, V, ld, nv, B->dcoef + coef_off,
+                     kMaxCoef, out, acc, B->chl, B->ch_sys, B->ch_beg, B->ch_len);
   return hip_check(hipGetLastError(), "batched linear combination");
 }
 
 template <typename TY, typename TX>
 int baxpby(cheb_batch* B, TY* y, const TX* x, int ia, int ib) {
-  hipLaunchKernelGGL((k_baxpby<TY, TX>), dim3(B->nchunks), dim3(kBT), 0, B->stream, y, x, B->dscal, 8, ia, ib,
-                     B->ch_sys, B->ch_beg, B->ch_len);
+  if (B->nchl == 0) return CHEB_OK;
+  hipLaunchKernelGGL((k_baxpby<TY, TX>), dim3(B->nchl), dim3(kBT), 0, B->stream, y, x, B->dscal, 8, ia, ib,
+                     B->chl, B->ch_sys, B->ch_beg, B->ch_len);
   return hip_check(hipGetLastError(), "batched axpby");
 }
 
-// active lists of the apply groups for the systems flagged in `on`
+// active lists of the apply groups, preconditioner groups and vector kernels
+// for the systems flagged in `on`
 int set_active(cheb_batch* B, const std::vector<char>& on) {
+  {
+    std::vector<int> c;
+    for (int s = 0; s < B->nprob; ++s)
+      if (on[s])
+        for (int k = 0; k < B->sys_nc_h[s]; ++k) c.push_back(B->sys_c0_h[s] + k);
+    if (c != B->hchl) {
+      if (!c.empty()) {
+        int rc = hip_check(hipMemcpyAsync(B->chl, c.data(), c.size() * sizeof(int), hipMemcpyHostToDevice, B->stream),
+                           "hipMemcpyAsync(chunk list)");
+        if (!rc) rc = bsync(B);
+        if (rc) return rc;
+      }
+      B->hchl = c;
+      B->nchl = (int)c.size();
+    }
+  }
   for (auto& g : B->groups) {
     std::vector<int> a;
     for (int k = 0; k < (int)g.members.size(); ++k)
@@ -462,7 +495,8 @@ int blgmres(cheb_batch* B, const T* K, const T* b, T* x, bool x_zero, const std:
       const double bb = dots[(size_t)s * kMaxCoef];
       beta[s] = std::sqrt(bb > 0 ? bb : 0.0);
       resid[s] = beta[s];
-      if (!(beta[s] > tol[s])) state[s] = std::isfinite(beta[s]) ? CHEB_OK : CHEB_NOT_CONVERGED;
+      if (!std::isfinite(beta[s])) state[s] = CHEB_NOT_CONVERGED;
+      else if (!(beta[s] > tol[s])) state[s] = CHEB_OK;
       else if (mv[s] >= maxmv) state[s] = CHEB_NOT_CONVERGED;
       else if (stall > 0.0 && beta[s] > stall * beta_prev[s]) state[s] = CHEB_STAGNATED;
       beta_prev[s] = beta[s];
@@ -591,12 +625,13 @@ int blgmres(cheb_batch* B, const T* K, const T* b, T* x, bool x_zero, const std:
       nvmax = std::max(nvmax, std::min(jend[s], m));
       jmaxend = std::max(jmaxend, jend[s]);
     }
-    rc = upload(B, B->dcoef, coef.data(), coef.size(), 0);
+    // every system of the cycle forms its correction, including those that
+    // stopped extending the space early
+    rc = set_active(B, on);
+    if (!rc) rc = upload(B, B->dcoef, coef.data(), coef.size(), 0);
     if (!rc) rc = blincomb<T>(B, kw.V, kw.ld, nvmax, 0, kw.w, 0);
     for (int i = m; i < jmaxend && !rc; ++i)
       rc = blincomb<T>(B, kw.Z + (size_t)zslot[i - m] * kw.ld, kw.ld, 1, i, kw.w, 1);
-    if (rc) return rc;
-    rc = set_active(B, on);
     if (rc) return rc;
     std::fill(scal.begin(), scal.end(), 0.0);
     for (int s = 0; s < ns; ++s) {
@@ -746,12 +781,17 @@ int cheb_batch_create(const cheb_grid* grids, int32_t nprob, int32_t precision, 
   B->ch_beg = nullptr;
   B->ch_len = nullptr;
   B->sys_c0 = B->sys_nc = nullptr;
+  B->chl = nullptr;
+  B->nchl = 0;
+  B->sys_c0_h = c0;
+  B->sys_nc_h = nc;
   B->dcoef = B->dscal = B->dkc = nullptr;
   B->dflag = nullptr;
   B->hpin = nullptr;
   if (!rc) rc = hip_check(hipMalloc((void**)&B->ch_sys, chs.size() * sizeof(int)), "hipMalloc(chunks)");
   if (!rc) rc = hip_check(hipMalloc((void**)&B->ch_beg, chb.size() * sizeof(long long)), "hipMalloc(chunks)");
   if (!rc) rc = hip_check(hipMalloc((void**)&B->ch_len, chl.size() * sizeof(int)), "hipMalloc(chunks)");
+  if (!rc) rc = hip_check(hipMalloc((void**)&B->chl, chs.size() * sizeof(int)), "hipMalloc(chunks)");
   if (!rc) rc = hip_check(hipMalloc((void**)&B->sys_c0, nprob * sizeof(int)), "hipMalloc(chunks)");
   if (!rc) rc = hip_check(hipMalloc((void**)&B->sys_nc, nprob * sizeof(int)), "hipMalloc(chunks)");
   if (!rc) rc = hip_check(hipMalloc((void**)&B->dcoef, (size_t)nprob * kMaxCoef * sizeof(double)), "hipMalloc");
@@ -882,7 +922,8 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
   std::vector<int> state(ns, RUN), mv(ns, 0), mv32(ns, 0), restarts(ns, 0), irs(ns, 0);
   std::vector<double> resid(ns, 0.0), bnorm(ns, 0.0), tol(ns, 0.0);
   std::vector<double> dots;
-  rc = bdots<double>(B, nullptr, 0, 0, w.bt, w.sc, dots);
+  rc = set_active(B, std::vector<char>(ns, 1));
+  if (!rc) rc = bdots<double>(B, nullptr, 0, 0, w.bt, w.sc, dots);
   if (rc) return rc;
   for (int s = 0; s < ns; ++s) {
     bnorm[s] = std::sqrt(std::max(0.0, dots[(size_t)s * kMaxCoef]));
@@ -917,7 +958,9 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
         if (!on[s]) continue;
         rho[s] = std::sqrt(std::max(0.0, dots[(size_t)s * kMaxCoef]));
         resid[s] = rho[s];
-        if (!(rho[s] > tol[s])) {
+        if (!std::isfinite(rho[s])) {
+          state[s] = CHEB_NOT_CONVERGED;
+        } else if (!(rho[s] > tol[s])) {
           state[s] = CHEB_OK;
         } else if (irs[s] >= bp.ir_max || mv[s] >= bp.maxiter) {
           state[s] = CHEB_NOT_CONVERGED;
@@ -951,7 +994,7 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
       const int cap = 40 * (bp.m + bp.k + 1);
       budget = std::max(1, std::min(budget, cap));
       rc = blgmres<float>(B, w.K32, w.b32, w.d32, true, itol, budget, w.kw32, w.sc, istate, ires, imv, restarts,
-                          bp.precond ? 0.0 : 0.9, bp.precond);
+                          0.9, bp.precond);
       if (rc) break;
       std::fill(scal.begin(), scal.end(), 0.0);
       for (int s = 0; s < ns; ++s) {
@@ -960,7 +1003,10 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
         scal[(size_t)s * 8] = state[s] == RUN ? rho[s] : 0.0;
         scal[(size_t)s * 8 + 1] = 1.0;
       }
-      rc = upload(B, B->dscal, scal.data(), scal.size(), 0);
+      // the inner solve leaves its own last active set behind: restore this step's
+      for (int s2 = 0; s2 < ns; ++s2) on[s2] = state[s2] == RUN;
+      rc = set_active(B, on);
+      if (!rc) rc = upload(B, B->dscal, scal.data(), scal.size(), 0);
       if (!rc) rc = baxpby<double, float>(B, w.x, w.d32, 0, 1);
       if (!rc) rc = bsync(B);
     }
@@ -1007,6 +1053,7 @@ int cheb_batch_destroy(cheb_batch* batch) {
   if (batch->ch_sys) (void)hipFree(batch->ch_sys);
   if (batch->ch_beg) (void)hipFree(batch->ch_beg);
   if (batch->ch_len) (void)hipFree(batch->ch_len);
+  if (batch->chl) (void)hipFree(batch->chl);
   if (batch->sys_c0) (void)hipFree(batch->sys_c0);
   if (batch->sys_nc) (void)hipFree(batch->sys_nc);
   if (batch->dcoef) (void)hipFree(batch->dcoef);

@@ -601,7 +601,7 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
       const int cap = 40 * (sp.m + sp.k + 1);
       if (budget > cap) budget = cap;
       const int r2 = lgmres<float>(p, A32, w.b32, w.d32, true, sp.ir_rtol, budget > 1 ? budget : 1, w.kw,
-                                   w.sc, si, &res32, 1.0, nullptr, 0, sp.precond ? 0.0 : 0.9, sp.precond, M32);
+                                   w.sc, si, &res32, 1.0, nullptr, 0, 0.9, sp.precond, M32);
       if (r2 < 0) {
         rc = r2;
         break;

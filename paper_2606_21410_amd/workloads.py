@@ -273,8 +273,9 @@ def gaussian_field_rff(grid: Grid, seed: int, corr_len: float, n_features: int =
                        chunk: int = 16) -> np.ndarray:
     """Zero-mean unit-variance Gaussian field with covariance exp(-r^2/(2 l^2)),
     by random Fourier features: g(x) = sqrt(2/M) sum_m cos(w_m . x + phi_m),
-    w ~ N(0, I/l^2), phi ~ U(0, 2 pi).  Grid-independent for a given seed."""
-    r = rng(seed)
+    w ~ N(0, I/l^2), phi ~ U(0, 2 pi).  Grid-independent for a given seed (an
+    int, or a tuple such as (1004, s) for structure s of a family)."""
+    r = rng(*seed) if isinstance(seed, tuple) else rng(seed)
     w = r.normal(size=(n_features, 3)) / corr_len
     phi = r.uniform(0.0, 2.0 * math.pi, size=n_features)
     x, y, z = grid.coords()
