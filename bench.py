@@ -226,6 +226,42 @@ def homogenisation_section(dev, n_struct=32, rtol=1e-10):
     return out
 
 
+def picard_chain_section(dev, levels=(33, 65, 129, 257)):
+    """Nonlinear two-phase workload: spheres at volume fraction 0.3 (seed 1003),
+    contrast 100, tanh width 2/256, K = K0 (1 + u^2/2), u = -1/+1 on the x faces;
+    Picard iterations of mixed FP32 / FP64 solves with the preconditioner,
+    hierarchical 33 -> 65 -> 129 -> 257 with modal prolongation as warm start.
+    Per level: time, Picard steps, matvecs and the refinement indicator e_ref."""
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan, SolveOptions, prolong
+    opts = SolveOptions(rtol=1e-10, maxiter=20000, precond=True)
+    out = []
+    prev = None
+    for n in levels:
+        P = W.two_phase_problem(n, seed=1003, volume_fraction=0.3, contrast=100.0, n_finest=levels[-1])
+        K0 = torch.from_numpy(P.K).to(dev)
+        f = torch.from_numpy(P.f).to(dev)
+        g = torch.from_numpy(P.g).to(dev)
+        plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "mixed", dev)
+        plan.ensure_workspace(opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u0 = prolong(prev[0], plan, prev[1])[0] if prev else None
+        u, info = plan.picard(K0, f, g, u0=u0, tol=1e-10, max_steps=60, opts=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rec = {"n": n, "seconds": round(el, 3), "picard_steps": info["picard_steps"], "matvecs": info["matvecs"],
+               "status": info["rc"]}
+        if prev:
+            _, e = prolong(prev[0], plan, prev[1], uf_solved=u)
+            rec["e_ref"] = e
+        _log(f"picard chain {rec}")
+        out.append(rec)
+        prev = (plan, u)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +378,11 @@ def main():
     if not args.no_solve and n == 129:
         solve = solve_section(P, d, dev, shape)
 
+    chain = None
+    if not args.no_solve and n == 129:
+        _log("hierarchical Picard chain 33 -> 65 -> 129 -> 257")
+        chain = picard_chain_section(dev)
+
     batch = None
     if not args.no_batch and not args.profile_apply:
         _log("batched homogenisation (32 microstructures x 3 load cases)")
@@ -375,6 +416,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_1e-8_129": solve,
         "homogenisation_batch": batch,
+        "picard_chain": chain,
     }
     print(json.dumps(out), flush=True)
 

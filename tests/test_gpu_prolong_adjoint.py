@@ -200,3 +200,33 @@ def test_flux_average_vs_oracle():
     out = plan.flux_average(to_dev(K, torch.float64), to_dev(u, torch.float64))
     ref = O.flux_average(G, K, u)
     np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+
+
+def test_hierarchical_picard_chain_vs_oracle():
+    """Nonlinear two-phase workload (vf 0.3, contrast 100, K = K0 (1 + u^2/2)):
+    Picard with FP32 inner / FP64 refinement and the preconditioner, level 17^3
+    prolonged into 33^3 as the warm start; the 33^3 result against the oracle's
+    Picard iteration, and e_ref from the prolongation."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions, prolong
+    d = lambda a: to_dev(a, torch.float64)
+    opts = SolveOptions(rtol=1e-11, maxiter=4000, precond=True)
+    prev = None
+    for n in (17, 33):
+        P = W.two_phase_problem(n, seed=1003, volume_fraction=0.3, contrast=100.0, n_finest=33)
+        plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "mixed")
+        u0 = prolong(prev[0], plan, prev[1])[0] if prev else None
+        u, info = plan.picard(d(P.K), d(P.f), d(P.g), u0=u0, tol=1e-10, max_steps=60, opts=opts)
+        log(f"picard chain n={n}: {info['picard_steps']} steps, {info['matvecs']} matvecs, rc {info['rc']}")
+        assert info["rc"] == 0
+        if prev:
+            _, e = prolong(prev[0], plan, prev[1], uf_solved=u)
+            log(f"  e_ref {e:.3e}")
+            assert 0 < e < 1e-1
+        prev = (plan, u)
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+    Uo, so = O.picard(G, P.K, P.f, P.g, tol=1e-10)
+    e = rel_l2(to_host(prev[1]), Uo)
+    log(f"  vs oracle ({so} steps): {e:.2e}")
+    assert e <= 1e-8
