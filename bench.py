@@ -335,6 +335,23 @@ def main():
         res[prec] = {"ms_per_apply": ms, "gdofs": npts / (ms * 1e-3) / 1e9, "wall_s": wall,
                      "autotune_us": tune, "route": tune["chosen"]}
         _log(f"apply {prec} ({tune['chosen']}): {ms * 1e3:.1f} us/apply, {res[prec]['gdofs']:.2f} GDOF/s")
+        # the same applies replayed from a HIP graph (16 applies per replay)
+        graph = plan.capture_applies(K, us, ys, "reduced")
+        reps = max(args.steps // N_ROT, 1)
+        graph.replay()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            graph.replay()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_g = ev0.elapsed_time(ev1) / (reps * N_ROT)
+        res[prec]["graph_ms_per_apply"] = ms_g
+        res[prec]["graph_gdofs"] = npts / (ms_g * 1e-3) / 1e9
+        _log(f"apply {prec} (graph replay): {ms_g * 1e3:.1f} us/apply")
+        del graph
         plan.set_route("fft")
         ms_fft, _ = time_applies(plan, K, us, ys, max(args.steps // 4, 10), 5)
         res[prec]["fft_route_gdofs"] = npts / (ms_fft * 1e-3) / 1e9

@@ -82,6 +82,23 @@ class Plan:
         L.check(self.lib.cheb_plan_set_route(self._h, _ROUTE[route]))
         self.route = route
 
+    def capture_applies(self, K, us, ys, mode: str = "reduced"):
+        """Record one operator application per (u, y) pair into a HIP graph
+        (torch.cuda.CUDAGraph; the applies launch only kernels, no memsets or
+        allocations).  Returns the graph; ``graph.replay()`` runs all of them."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            for u, y in zip(us, ys):
+                self.apply(K, u, y, mode)  # first launches set up per-kernel state outside the capture
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        torch.cuda.synchronize(self.device)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for u, y in zip(us, ys):
+                self.apply(K, u, y, mode)
+        return graph
+
     def autotune(self, K=None, u=None):
         """Time the FFT route and the matrix-core tile shapes of the reduced
         operator (per precision the plan computes in) and keep the fastest for
