@@ -8,7 +8,7 @@ namespace cheb {
 
 // Persistent launch: as many workgroups as the device holds at once (resident
 // workgroups per CU x CUs, queried once per kernel), at most one per tile.
-template <typename T, int NC, int MODE, bool FIRST, int V>
+template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int lds = dense_lds_bytes<T>(NC, V);
@@ -18,12 +18,12 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
     int dev = 0, cus = 0, per_cu = 0;
     int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (!rc && lds > 64 * 1024)
-      rc = hip_check(hipFuncSetAttribute((const void*)k_dense_pass<T, NC, MODE, FIRST, V>,
+      rc = hip_check(hipFuncSetAttribute((const void*)k_dense_pass<T, NC, MODE, FIRST, V, CG>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, lds),
                      "matrix-core pass LDS attribute");
     if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     if (!rc)
-      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_dense_pass<T, NC, MODE, FIRST, V>,
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_dense_pass<T, NC, MODE, FIRST, V, CG>,
                                                                   64 * S.NW, lds),
                      "occupancy query");
     if (rc) return rc;
@@ -32,17 +32,22 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
   const int ta = a.axis == 0 ? a.n[1] : a.n[0], tb = a.axis == 2 ? a.n[1] : a.n[2];
   const int tiles = ((ta - 2) * (tb - 2) + S.C - 1) / S.C * (a.sys ? a.nact : 1);
   const int grid = tiles < resident ? (tiles > 0 ? tiles : 1) : resident;
-  hipLaunchKernelGGL((k_dense_pass<T, NC, MODE, FIRST, V>), dim3(grid), dim3(64 * S.NW), lds, s, a);
+  hipLaunchKernelGGL((k_dense_pass<T, NC, MODE, FIRST, V, CG>), dim3(grid), dim3(64 * S.NW), lds, s, a);
   return hip_check(hipGetLastError(), "matrix-core pass launch");
+}
+
+template <typename T, int NC, int V, bool CG>
+static int launch_dense_c(const DenseArgs<T>& a, int transpose, hipStream_t s) {
+  if (a.first)
+    return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, true, V, CG>(a, s)
+                     : launch_dense_inst<T, NC, DENSE_REDUCED, true, V, CG>(a, s);
+  return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, false, V, CG>(a, s)
+                   : launch_dense_inst<T, NC, DENSE_REDUCED, false, V, CG>(a, s);
 }
 
 template <typename T, int NC, int V>
 static int launch_dense_v(const DenseArgs<T>& a, int transpose, hipStream_t s) {
-  if (a.first)
-    return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, true, V>(a, s)
-                     : launch_dense_inst<T, NC, DENSE_REDUCED, true, V>(a, s);
-  return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, false, V>(a, s)
-                   : launch_dense_inst<T, NC, DENSE_REDUCED, false, V>(a, s);
+  return a.axis == 2 ? launch_dense_c<T, NC, V, true>(a, transpose, s) : launch_dense_c<T, NC, V, false>(a, transpose, s);
 }
 
 template <typename T, int NC>

@@ -74,8 +74,9 @@ __host__ __device__ constexpr int pow2_floor(int x) {
   return p;
 }
 
-// LDS carve of one workgroup (bytes): fragment table, tile, K tile, face rows,
-// the per-column lift values / transposed-lift multipliers, column bookkeeping
+// LDS carve of one workgroup (bytes): fragment table, u tile, K tile, face
+// rows, the per-column lift values / transposed-lift multipliers, column
+// bookkeeping
 template <typename T>
 __host__ __device__ constexpr int dense_lds_bytes(int N, int V) {
   const DenseDims d = dense_dims(N, V);
@@ -138,52 +139,53 @@ struct DenseArgs {
     }                                                                          \
   } while (0)
 
-// vector-ALU dot products of each tile column with the LDS tile: the middle row
-// N/2 of the odd part (when it does not fill a 16-row block) and, with LIFT, the
-// two face rows that give the homogeneous lift of the end values (Section
-// 2.3.1); lane lg == 0 of each column's group holds the sums.
-#define DENSE_VDOT(MIDOUT, LIFT)                                                   \
+// vector-ALU dot products of each tile column with the LDS tile for the middle
+// row N/2 of the odd part (when it does not fill a 16-row block); lane lg == 0
+// of each column's group holds the sum.
+#define DENSE_VDOT(MIDOUT)                                                         \
   do {                                                                             \
     MIDOUT = T(0);                                                                 \
-    T s0_ = T(0), sN_ = T(0);                                                      \
-    if (S.MIDV || (LIFT)) {                                                        \
+    if (S.MIDV) {                                                                  \
       if (lc < C)                                                                  \
-        for (int j = lg; j < n; j += LPC) {                                        \
-          const T v = U[j * SC + lc];                                              \
-          if (S.MIDV && j < S.KO) MIDOUT += amid[j] * (v - U[(N - j) * SC + lc]); \
-          if (LIFT) {                                                              \
-            s0_ += drw[j] * v;                                                     \
-            sN_ += drw[n + j] * v;                                                 \
-          }                                                                        \
-        }                                                                          \
-      if (S.MIDV) MIDOUT = group_sum<LPC>(MIDOUT);                                 \
-      if (LIFT) {                                                                  \
-        s0_ = group_sum<LPC>(s0_);                                                 \
-        sN_ = group_sum<LPC>(sN_);                                                 \
-        if (lc < C && lg == 0) {                                                   \
-          T u0 = T(0), uN = T(0);                                                  \
-          if (nlo && nhi) {                                                        \
-            const T det = a.m00 * a.mNN - a.m0N * a.mN0;                           \
-            u0 = (-s0_ * a.mNN + sN_ * a.m0N) / det;                               \
-            uN = (-sN_ * a.m00 + s0_ * a.mN0) / det;                               \
-          } else if (nlo) {                                                        \
-            u0 = -s0_ / a.m00;                                                     \
-          } else if (nhi) {                                                        \
-            uN = -sN_ / a.mNN;                                                     \
-          }                                                                        \
-          cend[2 * lc] = u0;                                                       \
-          cend[2 * lc + 1] = uN;                                                   \
-        }                                                                          \
-      }                                                                            \
+        for (int j = lg; j < S.KO; j += LPC)                                       \
+          MIDOUT += amid[j] * (U[j * SC + lc] - U[(N - j) * SC + lc]);             \
+      MIDOUT = group_sum<LPC>(MIDOUT);                                             \
     }                                                                              \
   } while (0)
 
+// end values of the homogeneous lift (Section 2.3.1) of each column: the
+// first product's rows 0 and N are the face-row dot products s0 = D[0][:] u and
+// sN = D[N][:] u of the interior values, and [u0, uN] solves the face rows'
+// 2 x 2 system M [u0, uN] = -[s0, sN] on the Neumann ends.  Row 0 sits in
+// register r = 0 of the lanes lk == 0 of the waves with mt == 0.
+#define DENSE_LIFTVALS(ACCO, ACCE)                                          \
+  do {                                                                      \
+    if (mt == 0 && lk == 0) {                                               \
+      const T s0_ = ACCO[0] + ACCE[0], sN_ = ACCO[0] - ACCE[0];             \
+      T u0 = T(0), uN = T(0);                                               \
+      if (nlo && nhi) {                                                     \
+        const T det = a.m00 * a.mNN - a.m0N * a.mN0;                        \
+        u0 = (-s0_ * a.mNN + sN_ * a.m0N) / det;                            \
+        uN = (-sN_ * a.m00 + s0_ * a.mN0) / det;                            \
+      } else if (nlo) {                                                     \
+        u0 = -s0_ / a.m00;                                                  \
+      } else if (nhi) {                                                     \
+        uN = -sN_ / a.mNN;                                                  \
+      }                                                                     \
+      cend[2 * col] = u0;                                                   \
+      cend[2 * col + 1] = uN;                                               \
+    }                                                                       \
+  } while (0)
+
 // accumulators -> LDS tile rows i and N-i.  FLUX (first product): add the
-// lift's rank-2 correction u0 M[:][0] + uN M[:][N] (LIFT) and multiply by K.
+// lift's rank-2 correction u0 M[:][0] + uN M[:][N] (LIFT, on axes with a
+// Neumann end) and multiply by K.  M is centro-antisymmetric, so row N-i of the
+// correction is -(u0 M[i][N] + uN M[i][0]).
 #define DENSE_EPI(ACCO, ACCE, MIDVAL, FLUX, LIFT)                            \
   do {                                                                       \
     T u0_ = T(0), uN_ = T(0);                                                \
-    if (LIFT) {                                                              \
+    const bool lift_ = (LIFT) && (nlo || nhi);                               \
+    if (lift_) {                                                             \
       u0_ = cend[2 * col];                                                   \
       uN_ = cend[2 * col + 1];                                               \
     }                                                                        \
@@ -192,9 +194,10 @@ struct DenseArgs {
       if (i < S.RM) {                                                        \
         const T o = ACCO[r], e = ACCE[r];                                    \
         T lo = o + e, hi = o - e;                                            \
-        if (LIFT) {                                                          \
-          lo += u0_ * dc0[i] + uN_ * dcN[i];                                 \
-          hi += u0_ * dc0[N - i] + uN_ * dcN[N - i];                         \
+        if (lift_) {                                                         \
+          const T c0_ = dc0[i], cN_ = dcN[i];                                \
+          lo += u0_ * c0_ + uN_ * cN_;                                       \
+          hi -= u0_ * cN_ + uN_ * c0_;                                       \
         }                                                                    \
         if (FLUX) {                                                          \
           lo *= Kt[i * SC + col];                                            \
@@ -210,7 +213,7 @@ struct DenseArgs {
     }                                                                        \
     if (S.MIDV && lc < C && lg == 0) {                                       \
       T m_ = MIDVAL;                                                         \
-      if (LIFT) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
+      if (lift_) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
       if (FLUX) m_ *= Kt[S.HALF * SC + lc];                                  \
       U[S.HALF * SC + lc] = m_;                                              \
     }                                                                        \
@@ -231,29 +234,24 @@ struct DenseArgs {
     }                                                                      \
   } while (0)
 
-// global -> registers: u (interior nodes) and K of the tile in slot SLOT.
-// Every load is issued (off-tile elements read node 0 and are discarded), so
-// the number of outstanding loads is static and the compiler's waits stay exact.
+// global -> registers: u and K of the tile in slot SLOT (u's end nodes are
+// cleared when the tile is written to LDS).  Every load is issued (off-tile
+// elements read node 0 and their columns are discarded), so the number of
+// outstanding loads is static and the compiler's waits stay exact; nothing here
+// waits for the loads.
 #define DENSE_LOAD(SLOT, UR, KR, PU, PK)                              \
   do {                                                                \
     int ad_[EPT];                                                     \
-    bool ok_[EPT], in_[EPT];                                          \
     _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
       const int e = tid + q * NT < TOT ? tid + q * NT : TOT - 1;      \
       int j, c;                                                       \
       DENSE_MAP(e, j, c);                                             \
       const int b = cbase[SLOT][c];                                   \
-      ok_[q] = b >= 0 && tid + q * NT < TOT;                          \
-      in_[q] = ok_[q] && j != 0 && j != N;                            \
-      ad_[q] = ok_[q] ? b + j * stride : 0;                           \
+      ad_[q] = b >= 0 ? b + j * stride : 0;                           \
     }                                                                 \
     _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
       UR[q] = (PU)[ad_[q]];                                           \
       KR[q] = (PK)[ad_[q]];                                           \
-    }                                                                 \
-    _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
-      UR[q] = in_[q] ? UR[q] : T(0);                                  \
-      KR[q] = ok_[q] ? KR[q] : T(0);                                  \
     }                                                                 \
   } while (0)
 
@@ -278,7 +276,7 @@ struct DenseArgs {
 // interior-transverse pencils and keeps the next tile's u and K loads in flight
 // in registers while it computes the current one.  In the first pass it also
 // clears the pencils that lie in a face (all their nodes are boundary nodes).
-template <typename T, int NC, int MODE, bool FIRST, int V>
+template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(DenseArgs<T> a) {
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int N = NC, n = NC + 1;
@@ -310,8 +308,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   const int lc = tid / LPC, lg = tid - lc * LPC;
   const int axis = a.axis;
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const int stride = axis == 2 ? 1 : axis == 1 ? n2 : n1 * n2;
-  const bool contig = axis == 2;
+  // CG: the pass runs along the unit-stride axis (axis 2)
+  const int stride = CG ? 1 : axis == 1 ? n2 : n1 * n2;
+  constexpr bool contig = CG;
   const int nai = (axis == 0 ? n1 : n0) - 2, nbi = (axis == 2 ? n1 : n2) - 2;
   const int npen = nai * nbi;
   const int tps = (npen + C - 1) / C;  // tiles per system
@@ -377,8 +376,11 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   nu = cu;
   nK = cK;
   __syncthreads();
-  // V = 0 prefetches the next tile into registers; V = 1 loads each tile when
-  // it starts and relies on the second workgroup of the CU for overlap
+  // V = 0 loads the next tile's u and K into registers between the first
+  // product's matrix instructions and writes them to LDS at the top of the next
+  // tile.  V = 1, whose registers hold the fragments, loads each tile at its
+  // top and relies on the second workgroup of the CU for overlap (prefetch
+  // registers would spill, and spill reloads wait for every load in flight).
   constexpr bool PREF = V == 0;
   T ureg[EPT], kreg[EPT];
   if (PREF) DENSE_LOAD(0, ureg, kreg, cu, cK);
@@ -393,6 +395,19 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     drw[j] = a.drow0[j];
     drw[n + j] = a.drowN[j];
   }
+  // u tile -> LDS with its end nodes cleared (the interior values of the lift)
+#define DENSE_PUT(DU, UR, KR)                       \
+  do {                                              \
+    _Pragma("unroll") for (int q = 0; q < EPT; ++q) { \
+      const int e = tid + q * NT;                   \
+      if (e < TOT) {                                \
+        int j, c;                                   \
+        DENSE_MAP(e, j, c);                         \
+        (DU)[j * SC + c] = j != 0 && j != N ? UR[q] : T(0); \
+        Kt[j * SC + c] = KR[q];                     \
+      }                                             \
+    }                                               \
+  } while (0)
 
   for (; tile < t_end; tile += t_step, slot ^= 1) {
     const int nxt = tile + t_step < t_end ? tile + t_step : ntiles;
@@ -401,67 +416,45 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     nlo = (cbm >> (2 * axis)) & 1;
     nhi = (cbm >> (2 * axis + 1)) & 1;
     if (!PREF) DENSE_LOAD(slot, ureg, kreg, cu, cK);
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      if (e < TOT) {
-        int j, c;
-        DENSE_MAP(e, j, c);
-        U[j * SC + c] = ureg[q];
-        Kt[j * SC + c] = kreg[q];
-      }
-    }
+    DENSE_PUT(U, ureg, kreg);
     if (nxt < ntiles) DENSE_COLS(slot ^ 1, nxt);
+    else if (tid < C) cbase[slot ^ 1][tid] = -1;  // loads of the next tile all read node 0
     __syncthreads();
 
-    // in flight during this tile: next tile's u and K (the last tile reloads
-    // its own columns), this tile's y
-    // Their addresses are formed here and the loads are issued a few at a time
-    // between the first product's matrix instructions, so the matrix cores keep
+    // in flight during this tile: next tile's u and K (V = 0), this tile's y.  Their
+    // addresses are formed here and the loads are issued a few at a time
+    // between the products' matrix instructions, so the matrix cores keep
     // working while load issue waits for queue space.
     T unx[PREF ? EPT : 1], knx[PREF ? EPT : 1], yreg[EPT];
-    int pad[PREF ? EPT : 1], yad[EPT];
-    bool pok[PREF ? EPT : 1], pin[PREF ? EPT : 1];
     {
       T* ny_;
       int nbm_;
       DENSE_SYS(nxt < ntiles ? nxt : tile, nu, nK, ny_, nbm_);
       (void)ny_;
       (void)nbm_;
-      const int ps = slot ^ 1;
-      const bool more = nxt < ntiles;
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * NT < TOT ? tid + q * NT : TOT - 1;
-        int j, c;
-        DENSE_MAP(e, j, c);
-        const int b = cbase[slot][c];
-        yad[q] = b >= 0 ? b + j * stride : 0;
-        if (PREF) {
-          const int bn = more ? cbase[ps][c] : -1;
-          const bool ok = bn >= 0 && tid + q * NT < TOT;
-          pok[PREF ? q : 0] = ok;
-          pin[PREF ? q : 0] = ok && j != 0 && j != N;
-          pad[PREF ? q : 0] = ok ? bn + j * stride : 0;
-        }
-      }
     }
+    // global offset of element q of the tile in slot SL (node 0 off the tile)
+#define DENSE_AD(SL, q)                                                      \
+  ([&]() {                                                                   \
+    const int e_ = tid + (q) * NT < TOT ? tid + (q) * NT : TOT - 1;          \
+    int j_, c_;                                                              \
+    DENSE_MAP(e_, j_, c_);                                                   \
+    const int b_ = cbase[SL][c_];                                            \
+    return b_ >= 0 ? b_ + j_ * stride : 0;                                   \
+  }())
     // loads issued at k-step KS of the first product: prefetch element KS/2 (u
     // at even steps, K at odd ones); y loads go between the second product's
     // k-steps
-#define DENSE_ISSUE1(KS)                                                          \
-  do {                                                                            \
-    if (PREF && (KS) < 2 * EPT) {                                                 \
-      if ((KS) % 2 == 0) unx[PREF ? (KS) / 2 : 0] = nu[pad[PREF ? (KS) / 2 : 0]];  \
-      else knx[PREF ? (KS) / 2 : 0] = nK[pad[PREF ? (KS) / 2 : 0]];               \
-    }                                                                             \
+#define DENSE_ISSUE1(KS)                                   \
+  do {                                                     \
+    if (PREF && (KS) < 2 * EPT) {                          \
+      if ((KS) % 2 == 0) unx[PREF ? (KS) / 2 : 0] = nu[DENSE_AD(slot ^ 1, (KS) / 2)]; \
+      else knx[PREF ? (KS) / 2 : 0] = nK[DENSE_AD(slot ^ 1, (KS) / 2)];              \
+    }                                                      \
   } while (0)
-#define DENSE_ISSUE2(KS)                                                          \
-  do {                                                                            \
-    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = cy[yad[(KS) < EPT ? (KS) : 0]]; \
-  } while (0)
-#define DENSE_ISSUE_NONE(KS) \
-  do {                       \
+#define DENSE_ISSUE2(KS)                                                           \
+  do {                                                                             \
+    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = cy[DENSE_AD(slot, (KS) < EPT ? (KS) : 0)]; \
   } while (0)
 
     V4 acco, acce;
@@ -471,29 +464,21 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     // whatever did not fit between the k-steps
 #pragma unroll
     for (int ks = S.KE4; ks < (PREF ? 2 * EPT : 0); ++ks) {
-      if (PREF && ks < 2 * EPT) {
-        if (ks % 2 == 0) unx[PREF ? ks / 2 : 0] = nu[pad[PREF ? ks / 2 : 0]];
-        else knx[PREF ? ks / 2 : 0] = nK[pad[PREF ? ks / 2 : 0]];
-      }
+      if (ks % 2 == 0) unx[PREF ? ks / 2 : 0] = nu[DENSE_AD(slot ^ 1, ks / 2)];
+      else knx[PREF ? ks / 2 : 0] = nK[DENSE_AD(slot ^ 1, ks / 2)];
     }
-    DENSE_VDOT(midv, MODE == DENSE_REDUCED);
+    DENSE_VDOT(midv);
+    if (MODE == DENSE_REDUCED) DENSE_LIFTVALS(acco, acce);
     __syncthreads();
     DENSE_EPI(acco, acce, midv, true, MODE == DENSE_REDUCED);
     __syncthreads();
 
     // divergence part
-    if (PREF) {
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        unx[PREF ? q : 0] = pin[PREF ? q : 0] ? unx[PREF ? q : 0] : T(0);
-        knx[PREF ? q : 0] = pok[PREF ? q : 0] ? knx[PREF ? q : 0] : T(0);
-      }
-    }
     DENSE_GEMM(acco, acce, DENSE_ISSUE2);
 #pragma unroll
     for (int q = S.KE4; q < EPT; ++q)
-      if (!FIRST) yreg[q] = cy[yad[q]];
-    DENSE_VDOT(midv, false);
+      if (!FIRST) yreg[q] = cy[DENSE_AD(slot, q)];
+    DENSE_VDOT(midv);
     __syncthreads();
     DENSE_EPI(acco, acce, midv, false, false);
     __syncthreads();
@@ -532,7 +517,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         const bool ok = b >= 0 && tid + q * NT < TOT;
         const bool in = j != 0 && j != N;
         T x = U[j * SC + c];
-        if (MODE == DENSE_TRANSPOSE) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
+        if (MODE == DENSE_TRANSPOSE && (nlo || nhi)) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
         if (!FIRST) x += yreg[q];
         ov[q] = in ? x : T(0);
         op[q] = ok ? cy + (b + j * stride) : a.sink;
@@ -553,9 +538,11 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 #undef DENSE_MAP
 #undef DENSE_GEMM
 #undef DENSE_ISSUE1
-#undef DENSE_ISSUE_NONE
+#undef DENSE_PUT
+#undef DENSE_AD
 #undef DENSE_ISSUE2
 #undef DENSE_VDOT
+#undef DENSE_LIFTVALS
 #undef DENSE_EPI
 #undef DENSE_COLS
 #undef DENSE_LOAD
