@@ -43,7 +43,7 @@ def _traffic_record(route):
         cur = hashlib.sha1(open(os.path.join(ROOT, "paper_2606_21410_amd", "csrc", f), "rb").read()).hexdigest()[:12]
         if cur != h:
             return None
-    if not rec["kernel"].endswith(f"{route[-1]}>(cheb::DenseArgs<double>)"):
+    if rec.get("variant") != int(route[-1]):
         return None
     return rec
 
@@ -372,7 +372,7 @@ def main():
     bytes_per_launch = (24.0 + 32.0 + 32.0) / 3.0 * npts
     achieved = bytes_per_launch / launch_s / 1e9
     route = res["f64"]["route"]
-    kname = (f"k_dense_pass<double,128,REDUCED,*,{route[-1]}> (matrix-core route" if route != "fft"
+    kname = (f"k_dense_pass<double,128,REDUCED,*,{route[-1]},*> (matrix-core route" if route != "fft"
              else "k_axis_pass<double,128,REDUCED> (FFT route")
     rec = _traffic_record(route)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
