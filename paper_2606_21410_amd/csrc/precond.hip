@@ -16,9 +16,11 @@
 // back-substitution for the eigenvectors), and the inverse by Gauss-Jordan.
 // Apply (device): pack interior -> three dense axis contractions with V^{-1}
 // -> divide by the eigenvalue sums -> three contractions with V -> unpack.
-// The contractions are batched GEMMs on the matrix cores (MFMA 16x16x4).
+// The contractions run on the matrix cores (MFMA 16x16x4): a pencil-tile kernel
+// for m <= 128, a generic strided batched GEMM beyond.
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "cheb_host.h"
@@ -290,6 +292,117 @@ __global__ __launch_bounds__(256) void k_axis_gemm(GemmArgs g) {
   }
 }
 
+// Contraction of packed blocks along one axis with a dense m x m matrix,
+// y_i = sum_k M[i][k] x_k per pencil (M^T with trans), for m <= MP <= 128.
+// A tile of 16 pencils is staged in LDS by coalesced loads, multiplied on the
+// matrix cores by register-resident 16-row fragments of M (one wave per 16
+// output rows, the whole K range per wave, rows and columns past m zero), and
+// written back through LDS so that the stores coalesce as well.  Workgroups
+// walk the tiles of all nb blocks.
+struct FdmArgs {
+  const void* M;
+  const void* X;
+  void* Y;
+  int m, axis, trans, nb;
+  int m0, m1, m2;  // dims of one packed block; nb blocks follow each other
+};
+
+template <typename T, int MP>
+__global__ __launch_bounds__(4 * MP, 2) void k_fdm_contract(FdmArgs g) {
+  constexpr int NW = MP / 16, NT = 64 * NW, C = 16, SC = C + 1, KS = MP / 4;
+  constexpr int EPT = MP * C / NT;  // = 4
+  typedef typename Mfma<T>::v4 V4;
+  __shared__ T Xs[MP * SC];
+  __shared__ long long pb[2][C];  // first element of each pencil of a tile (-1 past the last)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m = g.m, axis = g.axis;
+  const T* M = (const T*)g.M;
+  const T* X = (const T*)g.X;
+  T* Y = (T*)g.Y;
+  const long long plane = (long long)g.m1 * g.m2, bsz = plane * g.m0;
+  const long long stride = axis == 2 ? 1 : axis == 1 ? g.m2 : plane;
+  const long long ppb = bsz / m;  // pencils per block
+  const long long npen = ppb * g.nb;
+  const long long ntiles = (npen + C - 1) / C;
+  const bool contig = axis == 2;
+  const int tot = m * C;  // tile elements
+  // pencil bases of tile TL into slot SL
+  auto cols = [&](long long tl, int sl) {
+    if (tid < C) {
+      const long long q = tl * C + tid;
+      long long b = -1;
+      if (tl < ntiles && q < npen) {
+        const long long bi = q / ppb, qq = q - bi * ppb;
+        const long long off = axis == 0 ? qq : axis == 1 ? (qq / g.m2) * plane + qq % g.m2 : qq * g.m2;
+        b = bi * bsz + off;
+      }
+      pb[sl][tid] = b;
+    }
+  };
+  // element e of a tile -> (node k, pencil c): pencil-contiguous along the
+  // unit-stride axis, pencil-fastest otherwise.  Loads of element q of the tile
+  // in slot SL (0 off the tile; every load is issued).
+  auto load = [&](int sl, T* v) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT < tot ? tid + q * NT : tot - 1;
+      const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
+      const long long b = pb[sl][c];
+      v[q] = X[b >= 0 ? b + k * stride : 0];
+    }
+  };
+  long long tile = blockIdx.x;
+  int slot = 0;
+  cols(tile, 0);
+  __syncthreads();
+  T v[EPT];
+  load(0, v);
+  // fragments of M: rows 16 wave + li, the whole K range (zero past m)
+  T a[KS];
+  const int row = 16 * wave + li;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 4 * ks + lk;
+    const size_t at = g.trans ? (size_t)k * m + row : (size_t)row * m + k;
+    a[ks] = (row < m && k < m) ? M[at] : T(0);
+  }
+  for (int e = tid; e < (MP - m) * SC; e += NT) Xs[m * SC + e] = T(0);
+  for (; tile < ntiles; tile += gridDim.x, slot ^= 1) {
+    __syncthreads();  // the previous tile's readers of Xs are done
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      if (e < tot) {
+        const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
+        Xs[k * SC + c] = v[q];
+      }
+    }
+    cols(tile + gridDim.x, slot ^ 1);
+    __syncthreads();
+    load(slot ^ 1, v);  // the next tile, in flight during this one
+    V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acc = Mfma<T>::mac(a[ks], Xs[(4 * ks + lk) * SC + li], acc);
+    __syncthreads();  // every wave has read the tile
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wave + Mfma<T>::row(lk, r);
+      if (i < m) Xs[i * SC + li] = acc[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      if (e < tot) {
+        const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
+        const long long b = pb[slot][c];
+        if (b >= 0) Y[b + k * stride] = Xs[k * SC + c];
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_pack_interior(const T* __restrict__ in, T* __restrict__ out, int n0, int n1, int n2) {
   const int m0 = n0 - 2, m1 = n1 - 2, m2 = n2 - 2;
@@ -392,14 +505,42 @@ int precond_setup(cheb_plan* p) {
   size_t off64 = 0;
   std::vector<double> host;
   PrecondAxis ax[3];
+  // axes with the same 1-D problem (N, L, face pair) share one decomposition;
+  // the distinct ones are decomposed on host threads of their own
+  int src[3];
+  for (int a = 0; a < 3; ++a) {
+    src[a] = a;
+    for (int b = 0; b < a; ++b)
+      if (src[b] == b && p->ax[b].N == p->ax[a].N && p->ax[b].L == p->ax[a].L &&
+          p->g.bc[2 * b] == p->g.bc[2 * a] && p->g.bc[2 * b + 1] == p->g.bc[2 * a + 1]) {
+        src[a] = b;
+        break;
+      }
+  }
+  std::vector<double> lamv[3], Vv[3], Viv[3];
+  bool okv[3] = {true, true, true};
+  {
+    std::vector<std::thread> th;
+    for (int a = 0; a < 3; ++a) {
+      if (src[a] != a) continue;
+      th.emplace_back([&, a]() {
+        const int m = p->ax[a].N - 1;
+        std::vector<double> A;
+        reduced_1d(p->ax[a].N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], A);
+        okv[a] = eig_real(m, A, lamv[a], Vv[a]) && invert(m, Vv[a], Viv[a]);
+      });
+    }
+    for (auto& t : th) t.join();
+  }
   for (int a = 0; a < 3; ++a) {
     const int N = p->ax[a].N, m = N - 1;
-    std::vector<double> A, lam, V, Vi;
-    reduced_1d(N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], A);
-    if (!eig_real(m, A, lam, V) || !invert(m, V, Vi)) {
+    if (!okv[src[a]]) {
       set_error("preconditioner setup: eigen-decomposition failed");
       return CHEB_ERR_UNSUPPORTED;
     }
+    const std::vector<double>& lam = lamv[src[a]];
+    const std::vector<double>& V = Vv[src[a]];
+    const std::vector<double>& Vi = Viv[src[a]];
     ax[a].m = m;
     ax[a].off_V = off64;
     host.insert(host.end(), V.begin(), V.end());
@@ -434,11 +575,56 @@ const double* pc_base<double>(const cheb_plan* p) { return p->pc64; }
 template <>
 const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
 
+// persistent launch: as many workgroups as the device holds at once (queried
+// once per instantiation), at most one per tile
+template <typename T, int MP>
+static int launch_fdm(const FdmArgs& f, hipStream_t s) {
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (!rc)
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fdm_contract<T, MP>, 4 * MP, 0),
+                     "occupancy query");
+    if (rc) return rc;
+    resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const long long npen = (long long)f.m0 * f.m1 * f.m2 / f.m * f.nb;
+  const long long tiles = (npen + 15) / 16;
+  const int grid = (int)(tiles < resident ? (tiles > 0 ? tiles : 1) : resident);
+  hipLaunchKernelGGL((k_fdm_contract<T, MP>), dim3(grid), dim3(4 * MP), 0, s, f);
+  return hip_check(hipGetLastError(), "axis contraction");
+}
+
 // Y = M applied along `axis` of the packed block X (m0, m1, m2); trans uses M^T.
 // nb consecutive blocks of the same shape are contracted by one launch.
 template <typename T>
 static int axis_contract(const T* M, bool trans, int axis, const int* m, const T* X, T* Y, hipStream_t s,
                          int nb = 1) {
+  if (m[axis] <= 128) {
+    FdmArgs f;
+    f.M = M;
+    f.X = X;
+    f.Y = Y;
+    f.m = m[axis];
+    f.axis = axis;
+    f.trans = trans ? 1 : 0;
+    f.nb = nb;
+    f.m0 = m[0];
+    f.m1 = m[1];
+    f.m2 = m[2];
+    switch ((m[axis] + 15) / 16) {
+      case 1: return launch_fdm<T, 16>(f, s);
+      case 2: return launch_fdm<T, 32>(f, s);
+      case 3: return launch_fdm<T, 48>(f, s);
+      case 4: return launch_fdm<T, 64>(f, s);
+      case 5: return launch_fdm<T, 80>(f, s);
+      case 6: return launch_fdm<T, 96>(f, s);
+      case 7: return launch_fdm<T, 112>(f, s);
+      default: return launch_fdm<T, 128>(f, s);
+    }
+  }
   GemmArgs g;
   const long long msz = m[axis];
   const long long ms_i = trans ? 1 : msz, ms_k = trans ? msz : 1;  // M(i,k) strides
