@@ -26,6 +26,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Basis vectors are taken kGroup at a time: their loads are all issued before
+// the first product, so a block keeps kGroup * kEPT loads per thread in flight.
+// The per-vector accumulation order is that of one vector at a time.  Slots of
+// a group past the last vector load w (V may be null when nv is 0), and every
+// index is clamped into [0, npts), so all loads stay inside w and the basis.
+constexpr int kGroup = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, size_t ld, int nv,
                                                        const T* __restrict__ w, size_t npts,
@@ -34,26 +41,38 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, 
   const size_t b0 = (size_t)blockIdx.x * kChunk;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double wv[kEPT];
+  size_t ix[kEPT];  // element index, clamped into range (its w value is 0 past the end)
 #pragma unroll
   for (int e = 0; e < kEPT; ++e) {
     const size_t i = b0 + tid + (size_t)e * kThreads;
+    ix[e] = i < npts ? i : npts - 1;
     wv[e] = i < npts ? double(w[i]) : 0.0;
   }
-  for (int v = 0; v <= nv; ++v) {
-    double acc = 0.0;
-    if (v < nv) {
-      const T* Vi = V + (size_t)v * ld;
+  for (int v0 = 0; v0 <= nv; v0 += kGroup) {
+    T x[kGroup][kEPT];
 #pragma unroll
-      for (int e = 0; e < kEPT; ++e) {
-        const size_t i = b0 + tid + (size_t)e * kThreads;
-        if (i < npts) acc = fma(wv[e], double(Vi[i]), acc);
-      }
-    } else {
+    for (int g = 0; g < kGroup; ++g) {
+      const T* Vi = v0 + g < nv ? V + (size_t)(v0 + g) * ld : w;
 #pragma unroll
-      for (int e = 0; e < kEPT; ++e) acc = fma(wv[e], wv[e], acc);
+      for (int e = 0; e < kEPT; ++e) x[g][e] = Vi[ix[e]];
     }
-    acc = wave_sum(acc);
-    if (lane == 0) red[wave][v] = acc;
+    double acc[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      acc[g] = 0.0;
+      if (v0 + g < nv) {
+#pragma unroll
+        for (int e = 0; e < kEPT; ++e) acc[g] = fma(wv[e], double(x[g][e]), acc[g]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < kEPT; ++e) acc[g] = fma(wv[e], wv[e], acc[g]);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      const double t = wave_sum(acc[g]);
+      if (lane == 0 && v0 + g <= nv) red[wave][v0 + g] = t;
+    }
   }
   __syncthreads();
   for (int v = tid; v <= nv; v += kThreads) {
@@ -80,6 +99,10 @@ __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restri
   }
 }
 
+// out = (w - sum_v h_v V_v) * scale; kUE elements per thread per step, with
+// the basis loads of kGroup vectors issued together
+constexpr int kUE = 4;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update_scale(const T* __restrict__ V, size_t ld, int nv,
                                                            const double* __restrict__ h, const T* w, T* out,
@@ -87,10 +110,34 @@ __global__ __launch_bounds__(kThreads) void k_update_scale(const T* __restrict__
   __shared__ double hs[kMaxDots];
   for (int v = threadIdx.x; v < nv; v += kThreads) hs[v] = h[v];
   __syncthreads();
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < npts; i += (size_t)gridDim.x * kThreads) {
-    double acc = double(w[i]);
-    for (int v = 0; v < nv; ++v) acc = fma(-hs[v], double(V[(size_t)v * ld + i]), acc);
-    out[i] = T(acc * scale);
+  const size_t step = (size_t)gridDim.x * kThreads * kUE;
+  for (size_t i0 = (size_t)blockIdx.x * kThreads * kUE + threadIdx.x; i0 < npts; i0 += step) {
+    size_t ix[kUE];
+    double acc[kUE];
+#pragma unroll
+    for (int q = 0; q < kUE; ++q) {
+      const size_t i = i0 + (size_t)q * kThreads;
+      ix[q] = i < npts ? i : npts - 1;
+      acc[q] = double(w[ix[q]]);
+    }
+    int v = 0;
+    for (; v + kGroup <= nv; v += kGroup) {
+      T x[kGroup][kUE];
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+        for (int q = 0; q < kUE; ++q) x[g][q] = V[(size_t)(v + g) * ld + ix[q]];
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+        for (int q = 0; q < kUE; ++q) acc[q] = fma(-hs[v + g], double(x[g][q]), acc[q]);
+    }
+    for (; v < nv; ++v)
+#pragma unroll
+      for (int q = 0; q < kUE; ++q) acc[q] = fma(-hs[v], double(V[(size_t)v * ld + ix[q]]), acc[q]);
+#pragma unroll
+    for (int q = 0; q < kUE; ++q)
+      if (i0 + (size_t)q * kThreads < npts) out[i0 + (size_t)q * kThreads] = T(acc[q] * scale);
   }
 }
 
@@ -248,8 +295,11 @@ int multidot(const T* V, size_t ld, int nv, const T* w, size_t npts, double* par
     set_error("too many vectors in multi-dot");
     return CHEB_ERR_INVALID_ARG;
   }
-  int blocks = (int)((npts + kChunk - 1) / kChunk);
-  if (blocks < 1) blocks = 1;
+  if (npts == 0) {  // every dot product is empty: zero rows reduce to 0
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nv + 1), dim3(kThreads), 0, s, partials, 0, nv + 1, out);
+    return hip_check(hipGetLastError(), "multidot");
+  }
+  const int blocks = (int)((npts + kChunk - 1) / kChunk);
   hipLaunchKernelGGL(k_multidot<T>, dim3(blocks), dim3(kThreads), 0, s, V, ld, nv, w, npts, partials);
   hipLaunchKernelGGL(k_reduce_cols, dim3(nv + 1), dim3(kThreads), 0, s, partials, blocks, nv + 1, out);
   return hip_check(hipGetLastError(), "multidot");
