@@ -85,3 +85,37 @@ def test_precond_adjoint_vs_dense():
     _, grad, info = plan.adjoint(d(K), d(U), d(U - t), SolveOptions(rtol=1e-13, precond=True))
     assert info["status"] == 0
     assert rel_l2(to_host(grad), g_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("shape,bcname", [
+    ((33, 49, 65), "DDNNNN"),   # interior sizes 31, 47, 63: contraction widths 32, 48, 64
+    ((97, 20, 129), "NDNNDN"),  # 95, 18, 127: widths 96, 32, 128; faces not mirror-symmetric
+    ((81, 113, 9), "NNNDNN"),   # 79, 111, 7: widths 80, 112, 16
+])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_precond_exact_for_constant_K_shapes(shape, bcname, prec):
+    """Constant K on grids whose interior sizes cover every padded width of the
+    preconditioner's contraction kernel: the preconditioner is the exact inverse,
+    so LGMRES stops after a few applications -- for the forward solve and (FP64)
+    for the adjoint solve, which applies the transposed contractions."""
+    require_gpu()
+    import torch
+    from tests.gpu_util import BC_SETS
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    bc = BC_SETS[bcname]
+    LO, HI = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+    K = np.full(shape, 1.7)
+    f = W.random_field(shape, 71)
+    g = W.random_faces(W.Grid(shape, LO, HI, bc), 72)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    d = lambda a: to_dev(a, dt)
+    plan = Plan(shape, LO, HI, bc, prec)
+    rtol = 1e-5 if prec == "f32" else 1e-11
+    u, info = plan.solve(d(K), d(f), d(g), opts=SolveOptions(rtol=rtol, precond=True))
+    log(f"const K {shape} {bcname} {prec}: {info}")
+    assert info["status"] == 0 and info["matvecs"] <= 4
+    if prec == "f64":
+        r = W.random_field(shape, 73)
+        _, _, ainfo = plan.adjoint(d(K), u, d(r), SolveOptions(rtol=1e-11, precond=True))
+        log(f"adjoint const K {shape} {bcname}: {ainfo}")
+        assert ainfo["status"] == 0 and ainfo["matvecs"] <= 4
