@@ -274,6 +274,9 @@ def main():
     ap.add_argument("--profile-apply", action="store_true",
                     help="for profiler runs: 4 plain device copies of one FP64 field (the byte-counter "
                          "calibration), then the FP64 applies only")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="for profiler runs: the preconditioned FP64 and mixed solves only, each twice on "
+                         "one plan (the first with plan and preconditioner set-up)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
@@ -299,6 +302,27 @@ def main():
 
     res = {}
     stream = torch.cuda.current_stream(dev)
+
+    if args.profile_solve:
+        K, f, g = d(P.K), d(P.f), d(P.g)
+        out = {}
+        for prec, rt in (("f64", 1e-9), ("mixed", 1e-8)):
+            opts = SolveOptions(rtol=rt, maxiter=5000, precond=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl = Plan(shape, P.grid.lo, P.grid.hi, P.grid.bc, prec, device=dev)
+            pl.ensure_workspace(opts)
+            _, info = pl.solve(K, f, g, opts=opts)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = pl.solve(K, f, g, opts=opts)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out[prec] = {"cold_s": round(t1 - t0, 4), "warm_s": round(t2 - t1, 4), "matvecs": info["matvecs"],
+                         "matvecs_f32": info["matvecs_f32"], "status": info["status"]}
+            _log(f"profile solve {prec}: {out[prec]}")
+        print(json.dumps({"profile_solve": out}), flush=True)
+        return
 
     def time_applies(plan, K, us, ys, steps, warmup):
         for i in range(warmup):
