@@ -434,8 +434,8 @@ template <typename T>
 int bprec(cheb_batch* B, const T* in, T* out, T* pa, T* pb) {
   for (auto& g : B->pgroups) {
     if (g.hact.empty()) continue;
-    int rc = precond_apply_batch<T>(B->plans[g.rep], in, out, g.doffs, g.dsys, B->dkc, (int)g.hact.size(), pa, pb,
-                                    B->stream);
+    int rc = precond_apply_batch<T>(B->plans[g.rep], in, out, g.doffs, g.dsys, B->dkc, (int)g.hact.size(), B->P,
+                                    pa, pb, B->stream);
     if (rc) return rc;
   }
   return CHEB_OK;

@@ -157,10 +157,11 @@ template <typename T>
 int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, double kc, bool transpose,
                   hipStream_t s);
 // batched: members k < nmem of one group (same grid and face types as `rep`),
-// packed fields at offs[k] (device), mean conductivity kc[sys[k]] (device)
+// packed fields at offs[k] (device), mean conductivity kc[sys[k]] (device);
+// span = elements of the packed batch (every offs[k] + field size is within it)
 template <typename T>
 int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long long* offs, const int* sys,
-                        const double* kc, int nmem, T* bufA, T* bufB, hipStream_t s);
+                        const double* kc, int nmem, size_t span, T* bufA, T* bufB, hipStream_t s);
 // sum of all entries (double accumulation) into out[0]
 template <typename T>
 int vsum(const T* x, size_t npts, double* partials, double* out, hipStream_t s);

@@ -15,7 +15,8 @@
 // to the real Schur form -- the eigenvalues of these operators are real -- and
 // back-substitution for the eigenvectors), and the inverse by Gauss-Jordan.
 // Apply (device): pack interior -> three dense axis contractions with V^{-1}
-// -> divide by the eigenvalue sums -> three contractions with V -> unpack.
+// -> divide by the eigenvalue sums -> three contractions with V -> unpack (for
+// m <= 128 the packing, scaling and unpacking run inside the contractions).
 // The contractions run on the matrix cores (MFMA 16x16x4): a pencil-tile kernel
 // for m <= 128, a generic strided batched GEMM beyond.
 #include <algorithm>
@@ -299,60 +300,127 @@ __global__ __launch_bounds__(256) void k_axis_gemm(GemmArgs g) {
 // output rows, the whole K range per wave, rows and columns past m zero), and
 // written back through LDS so that the stores coalesce as well.  Workgroups
 // walk the tiles of all nb blocks.
+//
+// Input and output are each either packed interior blocks (nb blocks of
+// m0 x m1 x m2 back to back) or full fields (n_a = m_a + 2 nodes per axis, the
+// interior block at node offset (1,1,1), field b at offs[b]), so the packing
+// of the first contraction and the unpacking of the last one are part of
+// them.  With lam set, the output is divided by Kc (lam0[i0] + lam1[i1] +
+// lam2[i2]): the eigenvalue scaling between the two halves of the
+// preconditioner.
 struct FdmArgs {
   const void* M;
   const void* X;
   void* Y;
   int m, axis, trans, nb;
-  int m0, m1, m2;  // dims of one packed block; nb blocks follow each other
+  int m0, m1, m2;             // dims of one packed block
+  const long long* offs;      // full layouts: field b starts at offs[b] (null: b * n0 n1 n2)
+  const void* lam0;           // eigenvalues per axis (scaling)
+  const void* lam1;
+  const void* lam2;
+  double inv_k;               // 1 / Kc of a single system (sys == null)
+  const int* sys;             // batch: Kc of block b is kc[sys[b]]
+  const double* kc;
 };
 
-template <typename T, int MP>
-__global__ __launch_bounds__(4 * MP, 2) void k_fdm_contract(FdmArgs g) {
+// fusion modes: X is a full field / Y is a full field / Y is scaled
+enum { FDM_XFULL = 1, FDM_YFULL = 2, FDM_SCALE = 4 };
+constexpr int kFdmMaxNb = 256;  // blocks whose offsets and Kc a workgroup keeps in LDS
+
+template <typename T, int MP, int MODE>
+__global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
   constexpr int NW = MP / 16, NT = 64 * NW, C = 16, SC = C + 1, KS = MP / 4;
   constexpr int EPT = MP * C / NT;  // = 4
+  constexpr bool XF = MODE & FDM_XFULL, YF = MODE & FDM_YFULL, SCL = MODE & FDM_SCALE;
+  constexpr bool FULL = XF || YF;
   typedef typename Mfma<T>::v4 V4;
   __shared__ T Xs[MP * SC];
-  __shared__ long long pb[2][C];  // first element of each pencil of a tile (-1 past the last)
+  __shared__ int pbx[2][C], pby[2][C];    // first element of each pencil in X and Y (-1 past the last)
+  __shared__ double psc[SCL ? 2 : 1][C];  // the pencil's transverse eigenvalues and 1 / Kc (scaling)
+  __shared__ double pik[SCL ? 2 : 1][C];
+  __shared__ T lam_s[SCL ? 3 : 1][MP];
+  __shared__ int boff[FULL ? kFdmMaxNb : 1];
+  __shared__ double bik[SCL ? kFdmMaxNb : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m = g.m, axis = g.axis;
   const T* M = (const T*)g.M;
   const T* X = (const T*)g.X;
   T* Y = (T*)g.Y;
-  const long long plane = (long long)g.m1 * g.m2, bsz = plane * g.m0;
-  const long long stride = axis == 2 ? 1 : axis == 1 ? g.m2 : plane;
-  const long long ppb = bsz / m;  // pencils per block
-  const long long npen = ppb * g.nb;
-  const long long ntiles = (npen + C - 1) / C;
+  const int n1 = g.m1 + 2, n2 = g.m2 + 2;
+  const int plane = g.m1 * g.m2, bsz = plane * g.m0;
+  const int fplane = n1 * n2, fsz = fplane * (g.m0 + 2);
+  const int pstride = axis == 2 ? 1 : axis == 1 ? g.m2 : plane;  // packed
+  const int fstride = axis == 2 ? 1 : axis == 1 ? n2 : fplane;   // full
+  const int sxa = XF ? fstride : pstride, sya = YF ? fstride : pstride;
+  const int ppb = bsz / m;  // pencils per block
+  const int npen = ppb * g.nb;
+  const int ntiles = (npen + C - 1) / C;
   const bool contig = axis == 2;
   const int tot = m * C;  // tile elements
-  // pencil bases of tile TL into slot SL
-  auto cols = [&](long long tl, int sl) {
+  // per-workgroup tables: eigenvalues, field offsets and 1 / Kc of the blocks
+  if (SCL) {
+    const T* lp[3] = {(const T*)g.lam0, (const T*)g.lam1, (const T*)g.lam2};
+    const int md[3] = {g.m0, g.m1, g.m2};
+    for (int a = 0; a < 3; ++a)
+      for (int i = tid; i < MP; i += NT) lam_s[SCL ? a : 0][i] = i < md[a] ? lp[a][i] : T(0);
+    for (int b = tid; b < g.nb; b += NT) bik[SCL ? b : 0] = g.sys ? 1.0 / g.kc[g.sys[b]] : g.inv_k;
+  }
+  if (FULL)
+    for (int b = tid; b < g.nb; b += NT) boff[FULL ? b : 0] = g.offs ? (int)g.offs[b] : b * fsz;
+  __syncthreads();
+  // pencil bookkeeping of tile TL into slot SL
+  auto cols = [&](int tl, int sl) {
     if (tid < C) {
-      const long long q = tl * C + tid;
-      long long b = -1;
+      const int q = tl * C + tid;
+      int bx = -1, by = -1;
+      double sc = 0.0, ik = 0.0;
       if (tl < ntiles && q < npen) {
-        const long long bi = q / ppb, qq = q - bi * ppb;
-        const long long off = axis == 0 ? qq : axis == 1 ? (qq / g.m2) * plane + qq % g.m2 : qq * g.m2;
-        b = bi * bsz + off;
+        const int bi = q / ppb, qq = q - bi * ppb;
+        // the pencil's interior indices (axis index 0)
+        int i0 = 0, i1 = 0, i2 = 0;
+        if (axis == 0) {
+          i1 = qq / g.m2;
+          i2 = qq - i1 * g.m2;
+        } else if (axis == 1) {
+          i0 = qq / g.m2;
+          i2 = qq - i0 * g.m2;
+        } else {
+          i0 = qq / g.m1;
+          i1 = qq - i0 * g.m1;
+        }
+        const int pk = bi * bsz + (i0 * g.m1 + i1) * g.m2 + i2;
+        const int fk = FULL ? boff[FULL ? bi : 0] + ((i0 + 1) * n1 + (i1 + 1)) * n2 + (i2 + 1) : 0;
+        bx = XF ? fk : pk;
+        by = YF ? fk : pk;
+        if (SCL) {
+          const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;
+          const int ia = a0 == 0 ? i0 : i1, ib = a1 == 1 ? i1 : i2;
+          sc = double(lam_s[SCL ? a0 : 0][ia]) + double(lam_s[SCL ? a1 : 0][ib]);
+          ik = bik[SCL ? bi : 0];
+        }
       }
-      pb[sl][tid] = b;
+      pbx[sl][tid] = bx;
+      pby[sl][tid] = by;
+      if (SCL) {
+        psc[SCL ? sl : 0][tid] = sc;
+        pik[SCL ? sl : 0][tid] = ik;
+      }
     }
   };
   // element e of a tile -> (node k, pencil c): pencil-contiguous along the
-  // unit-stride axis, pencil-fastest otherwise.  Loads of element q of the tile
-  // in slot SL (0 off the tile; every load is issued).
+  // unit-stride axis, pencil-fastest otherwise.  Loads of the tile in slot SL
+  // (element 0 off the tile; every load is issued).
   auto load = [&](int sl, T* v) {
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT < tot ? tid + q * NT : tot - 1;
       const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
-      const long long b = pb[sl][c];
-      v[q] = X[b >= 0 ? b + k * stride : 0];
+      const int b = pbx[sl][c];
+      v[q] = X[b >= 0 ? b + k * sxa : 0];
     }
   };
-  long long tile = blockIdx.x;
+  int tile = blockIdx.x;
   int slot = 0;
   cols(tile, 0);
   __syncthreads();
@@ -396,10 +464,45 @@ __global__ __launch_bounds__(4 * MP, 2) void k_fdm_contract(FdmArgs g) {
       const int e = tid + q * NT;
       if (e < tot) {
         const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
-        const long long b = pb[slot][c];
-        if (b >= 0) Y[b + k * stride] = Xs[k * SC + c];
+        const int b = pby[slot][c];
+        if (b >= 0) {
+          T val = Xs[k * SC + c];
+          if (SCL)
+            val = T(double(val) * pik[SCL ? slot : 0][c] / (psc[SCL ? slot : 0][c] + double(lam_s[SCL ? axis : 0][k])));
+          Y[b + k * sya] = val;
+        }
       }
     }
+  }
+}
+
+// zero the boundary nodes of field blockIdx.y (at offs[y], or y * n0*n1*n2)
+template <typename T>
+__global__ void k_zero_faces(T* __restrict__ out, const long long* __restrict__ offs, int n0, int n1, int n2) {
+  T* o = out + (offs ? offs[blockIdx.y] : (long long)blockIdx.y * n0 * n1 * n2);
+  const long long fxy = (long long)n1 * n2, fxz = (long long)n0 * n2, fyz = (long long)n0 * n1;
+  const long long tot = 2 * (fxy + fxz + fyz);
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    long long u = t;
+    int i, j, k;
+    if (u < 2 * fxy) {  // x faces
+      i = u < fxy ? 0 : n0 - 1;
+      u %= fxy;
+      j = (int)(u / n2);
+      k = (int)(u % n2);
+    } else if ((u -= 2 * fxy) < 2 * fxz) {  // y faces
+      j = u < fxz ? 0 : n1 - 1;
+      u %= fxz;
+      i = (int)(u / n2);
+      k = (int)(u % n2);
+    } else {  // z faces
+      u -= 2 * fxz;
+      k = u < fyz ? 0 : n2 - 1;
+      u %= fyz;
+      i = (int)(u / n1);
+      j = (int)(u % n1);
+    }
+    o[((long long)i * n1 + j) * n2 + k] = T(0);
   }
 }
 
@@ -577,7 +680,7 @@ const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
 
 // persistent launch: as many workgroups as the device holds at once (queried
 // once per instantiation), at most one per tile
-template <typename T, int MP>
+template <typename T, int MP, int MODE>
 static int launch_fdm(const FdmArgs& f, hipStream_t s) {
   static int resident = 0;
   if (resident == 0) {
@@ -585,7 +688,8 @@ static int launch_fdm(const FdmArgs& f, hipStream_t s) {
     int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     if (!rc)
-      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fdm_contract<T, MP>, 4 * MP, 0),
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fdm_contract<T, MP, MODE>,
+                                                                  4 * MP, 0),
                      "occupancy query");
     if (rc) return rc;
     resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
@@ -593,8 +697,32 @@ static int launch_fdm(const FdmArgs& f, hipStream_t s) {
   const long long npen = (long long)f.m0 * f.m1 * f.m2 / f.m * f.nb;
   const long long tiles = (npen + 15) / 16;
   const int grid = (int)(tiles < resident ? (tiles > 0 ? tiles : 1) : resident);
-  hipLaunchKernelGGL((k_fdm_contract<T, MP>), dim3(grid), dim3(4 * MP), 0, s, f);
+  hipLaunchKernelGGL((k_fdm_contract<T, MP, MODE>), dim3(grid), dim3(4 * MP), 0, s, f);
   return hip_check(hipGetLastError(), "axis contraction");
+}
+
+template <typename T, int MODE>
+static int launch_fdm_mode(const FdmArgs& f, hipStream_t s) {
+  switch ((f.m + 15) / 16) {
+    case 1: return launch_fdm<T, 16, MODE>(f, s);
+    case 2: return launch_fdm<T, 32, MODE>(f, s);
+    case 3: return launch_fdm<T, 48, MODE>(f, s);
+    case 4: return launch_fdm<T, 64, MODE>(f, s);
+    case 5: return launch_fdm<T, 80, MODE>(f, s);
+    case 6: return launch_fdm<T, 96, MODE>(f, s);
+    case 7: return launch_fdm<T, 112, MODE>(f, s);
+    default: return launch_fdm<T, 128, MODE>(f, s);
+  }
+}
+
+template <typename T>
+static int launch_fdm_m(const FdmArgs& f, int mode, hipStream_t s) {
+  switch (mode) {
+    case FDM_XFULL: return launch_fdm_mode<T, FDM_XFULL>(f, s);
+    case FDM_YFULL: return launch_fdm_mode<T, FDM_YFULL>(f, s);
+    case FDM_SCALE: return launch_fdm_mode<T, FDM_SCALE>(f, s);
+    default: return launch_fdm_mode<T, 0>(f, s);
+  }
 }
 
 // Y = M applied along `axis` of the packed block X (m0, m1, m2); trans uses M^T.
@@ -603,7 +731,7 @@ template <typename T>
 static int axis_contract(const T* M, bool trans, int axis, const int* m, const T* X, T* Y, hipStream_t s,
                          int nb = 1) {
   if (m[axis] <= 128) {
-    FdmArgs f;
+    FdmArgs f{};
     f.M = M;
     f.X = X;
     f.Y = Y;
@@ -614,16 +742,7 @@ static int axis_contract(const T* M, bool trans, int axis, const int* m, const T
     f.m0 = m[0];
     f.m1 = m[1];
     f.m2 = m[2];
-    switch ((m[axis] + 15) / 16) {
-      case 1: return launch_fdm<T, 16>(f, s);
-      case 2: return launch_fdm<T, 32>(f, s);
-      case 3: return launch_fdm<T, 48>(f, s);
-      case 4: return launch_fdm<T, 64>(f, s);
-      case 5: return launch_fdm<T, 80>(f, s);
-      case 6: return launch_fdm<T, 96>(f, s);
-      case 7: return launch_fdm<T, 112>(f, s);
-      default: return launch_fdm<T, 128>(f, s);
-    }
+    return launch_fdm_m<T>(f, 0, s);
   }
   GemmArgs g;
   const long long msz = m[axis];
@@ -655,11 +774,69 @@ static int axis_contract(const T* M, bool trans, int axis, const int* m, const T
   return hip_check(hipGetLastError(), "axis contraction");
 }
 
+// the fused path: every axis on the pencil-tile kernel, 32-bit element offsets
+// in the packed blocks and the fields, the block tables in LDS
+static bool fused_ok(const int* m, int nb, size_t span) {
+  const size_t lim = (size_t)1 << 31;
+  return m[0] <= 128 && m[1] <= 128 && m[2] <= 128 && nb <= kFdmMaxNb && span < lim &&
+         (size_t)m[0] * m[1] * m[2] * (size_t)nb < lim;
+}
+
+// The six contractions on the matrix cores with the packing, the eigenvalue
+// scaling and the unpacking folded into the first, third and last (every axis
+// with m <= 128); nb fields at offs (null: one field), the boundary nodes of
+// the output set to zero by a small kernel.
+template <typename T>
+static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, bool transpose, int nb,
+                         const long long* offs, double inv_k, const int* sys, const double* kc, hipStream_t s) {
+  const int n0 = p->g.n[0], n1 = p->g.n[1], n2 = p->g.n[2];
+  const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
+  const T* base = pc_base<T>(p);
+  auto V = [&](int a) { return base + p->pc_ax[a].off_V; };
+  auto Vi = [&](int a) { return base + p->pc_ax[a].off_Vi; };
+  auto run = [&](int a, bool fwd, const T* X, T* Y, int mode) {
+    FdmArgs f{};
+    f.M = fwd ? (transpose ? V(a) : Vi(a)) : (transpose ? Vi(a) : V(a));
+    f.trans = transpose ? 1 : 0;
+    f.X = X;
+    f.Y = Y;
+    f.m = m[a];
+    f.axis = a;
+    f.nb = nb;
+    f.m0 = m[0];
+    f.m1 = m[1];
+    f.m2 = m[2];
+    f.offs = offs;
+    if (mode == FDM_SCALE) {
+      f.lam0 = base + p->pc_ax[0].off_lam;
+      f.lam1 = base + p->pc_ax[1].off_lam;
+      f.lam2 = base + p->pc_ax[2].off_lam;
+      f.inv_k = inv_k;
+      f.sys = sys;
+      f.kc = kc;
+    }
+    return launch_fdm_m<T>(f, mode, s);
+  };
+  int rc = run(0, true, in, bufA, FDM_XFULL);
+  if (!rc) rc = run(1, true, bufA, bufB, 0);
+  if (!rc) rc = run(2, true, bufB, bufA, FDM_SCALE);
+  if (!rc) rc = run(2, false, bufA, bufB, 0);
+  if (!rc) rc = run(1, false, bufB, bufA, 0);
+  if (!rc) rc = run(0, false, bufA, out, FDM_YFULL);
+  if (rc) return rc;
+  const long long faces = 2LL * ((long long)n1 * n2 + (long long)n0 * n2 + (long long)n0 * n1);
+  const int fb = (int)std::min<long long>((faces + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero_faces<T>, dim3(fb, nb), dim3(256), 0, s, out, offs, n0, n1, n2);
+  return hip_check(hipGetLastError(), "boundary zero");
+}
+
 template <typename T>
 int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, double kc, bool transpose,
                   hipStream_t s) {
   const int n0 = p->g.n[0], n1 = p->g.n[1], n2 = p->g.n[2];
   const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
+  if (fused_ok(m, 1, (size_t)n0 * n1 * n2))
+    return precond_fused<T>(p, in, out, bufA, bufB, transpose, 1, nullptr, 1.0 / kc, nullptr, nullptr, s);
   const size_t tot = (size_t)m[0] * m[1] * m[2];
   const T* base = pc_base<T>(p);
   auto V = [&](int a) { return base + p->pc_ax[a].off_V; };
@@ -703,10 +880,12 @@ int mfma_gemm(const T* A, const T* B, T* D, int I, int K, int C, hipStream_t s) 
 
 template <typename T>
 int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long long* offs, const int* sys,
-                        const double* kc, int nmem, T* bufA, T* bufB, hipStream_t s) {
+                        const double* kc, int nmem, size_t span, T* bufA, T* bufB, hipStream_t s) {
   if (nmem <= 0) return CHEB_OK;
   const int n0 = rep->g.n[0], n1 = rep->g.n[1], n2 = rep->g.n[2];
   const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
+  if (fused_ok(m, nmem, span))
+    return precond_fused<T>(rep, in, out, bufA, bufB, false, nmem, offs, 0.0, sys, kc, s);
   const size_t tot = (size_t)m[0] * m[1] * m[2];
   const T* base = pc_base<T>(rep);
   hipLaunchKernelGGL(k_pack_interior_b<T>, dim3(grid1(tot), nmem), dim3(256), 0, s, in, offs, bufA, n0, n1, n2);
@@ -732,9 +911,9 @@ int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long lo
 }
 
 template int precond_apply_batch<double>(const cheb_plan*, const double*, double*, const long long*, const int*,
-                                         const double*, int, double*, double*, hipStream_t);
+                                         const double*, int, size_t, double*, double*, hipStream_t);
 template int precond_apply_batch<float>(const cheb_plan*, const float*, float*, const long long*, const int*,
-                                        const double*, int, float*, float*, hipStream_t);
+                                        const double*, int, size_t, float*, float*, hipStream_t);
 template int precond_apply<double>(const cheb_plan*, const double*, double*, double*, double*, double, bool,
                                    hipStream_t);
 template int precond_apply<float>(const cheb_plan*, const float*, float*, float*, float*, double, bool,
