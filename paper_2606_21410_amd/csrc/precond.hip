@@ -338,7 +338,7 @@ __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
   __shared__ int pbx[2][C], pby[2][C];    // first element of each pencil in X and Y (-1 past the last)
   __shared__ double psc[SCL ? 2 : 1][C];  // the pencil's transverse eigenvalues and 1 / Kc (scaling)
   __shared__ double pik[SCL ? 2 : 1][C];
-  __shared__ T lam_s[SCL ? 3 : 1][MP];
+  __shared__ T lam_s[SCL ? 3 : 1][SCL ? 128 : 1];  // every axis' eigenvalues (the fused path has m <= 128)
   __shared__ int boff[FULL ? kFdmMaxNb : 1];
   __shared__ double bik[SCL ? kFdmMaxNb : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
     const T* lp[3] = {(const T*)g.lam0, (const T*)g.lam1, (const T*)g.lam2};
     const int md[3] = {g.m0, g.m1, g.m2};
     for (int a = 0; a < 3; ++a)
-      for (int i = tid; i < MP; i += NT) lam_s[SCL ? a : 0][i] = i < md[a] ? lp[a][i] : T(0);
+      for (int i = tid; i < 128; i += NT) lam_s[SCL ? a : 0][SCL ? i : 0] = i < md[a] ? lp[a][i] : T(0);
     for (int b = tid; b < g.nb; b += NT) bik[SCL ? b : 0] = g.sys ? 1.0 / g.kc[g.sys[b]] : g.inv_k;
   }
   if (FULL)
