@@ -14,6 +14,8 @@
 // reduction to Hessenberg form, implicit single-shift QR with Wilkinson shifts
 // to the real Schur form -- the eigenvalues of these operators are real -- and
 // back-substitution for the eigenvectors), and the inverse by Gauss-Jordan.
+// An axis with the same face type at both ends has a centro-symmetric 1-D
+// operator, which splits into two half-size problems.
 // Apply (device): pack interior -> three dense axis contractions with V^{-1}
 // -> divide by the eigenvalue sums -> three contractions with V -> unpack (for
 // m <= 128 the packing, scaling and unpacking run inside the contractions).
@@ -75,9 +77,12 @@ void reduced_1d(int N, double L, int blo, int bhi, std::vector<double>& A) {
 // columns and lam the eigenvalues; returns false if the QR iteration failed.
 bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
   auto H = [&](int i, int j) -> double& { return A[(size_t)i * m + j]; };
-  std::vector<double> Z((size_t)m * m, 0.0);
-  for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
-  auto Zm = [&](int i, int j) -> double& { return Z[(size_t)i * m + j]; };
+  // accumulated orthogonal transform, stored transposed (row k of Zt is
+  // column k of Z) so that its updates run along contiguous rows
+  std::vector<double> Zt((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Zt[(size_t)i * m + i] = 1.0;
+  auto Zr = [&](int k) { return &Zt[(size_t)k * m]; };
+  std::vector<double> zs(m);
   // Householder reduction to upper Hessenberg form, accumulating Z
   std::vector<double> v(m);
   for (int k = 0; k + 2 < m; ++k) {
@@ -105,11 +110,18 @@ bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vect
       s *= 2.0 / vn;
       for (int j = k + 1; j < m; ++j) H(i, j) -= s * v[j];
     }
-    for (int i = 0; i < m; ++i) {
-      double s = 0.0;
-      for (int j = k + 1; j < m; ++j) s += Zm(i, j) * v[j];
-      s *= 2.0 / vn;
-      for (int j = k + 1; j < m; ++j) Zm(i, j) -= s * v[j];
+    // Z = Z P: zs_i = sum_j Z(i,j) v_j (j ascending), then Z(i,j) -= (2/vn) zs_i v_j
+    std::fill(zs.begin(), zs.end(), 0.0);
+    for (int j = k + 1; j < m; ++j) {
+      const double vj = v[j];
+      const double* zr = Zr(j);
+      for (int i = 0; i < m; ++i) zs[i] += zr[i] * vj;
+    }
+    for (int i = 0; i < m; ++i) zs[i] *= 2.0 / vn;
+    for (int j = k + 1; j < m; ++j) {
+      const double vj = v[j];
+      double* zr = Zr(j);
+      for (int i = 0; i < m; ++i) zr[i] -= zs[i] * vj;
     }
     for (int i = k + 2; i < m; ++i) H(i, k) = 0.0;
   }
@@ -163,10 +175,12 @@ bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vect
         H(i, k) = cs * h1 + sn * h2;
         H(i, k + 1) = -sn * h1 + cs * h2;
       }
+      double* z1r = Zr(k);
+      double* z2r = Zr(k + 1);
       for (int i = 0; i < m; ++i) {
-        const double z1 = Zm(i, k), z2 = Zm(i, k + 1);
-        Zm(i, k) = cs * z1 + sn * z2;
-        Zm(i, k + 1) = -sn * z1 + cs * z2;
+        const double z1 = z1r[i], z2 = z2r[i];
+        z1r[i] = cs * z1 + sn * z2;
+        z2r[i] = -sn * z1 + cs * z2;
       }
       if (k + 1 < hi) {
         x = H(k + 1, k);
@@ -193,15 +207,17 @@ bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vect
       if (std::fabs(den) < small) den = den >= 0 ? small : -small;
       y[j] = -s / den;
     }
-    double nrm = 0.0;
-    for (int i = 0; i < m; ++i) {
-      double s = 0.0;
-      for (int l = 0; l <= k; ++l) s += Zm(i, l) * y[l];
-      V[(size_t)i * m + k] = s;
-      nrm += s * s;
+    // column k of V = Z y (l ascending for every i)
+    std::fill(zs.begin(), zs.end(), 0.0);
+    for (int l = 0; l <= k; ++l) {
+      const double yl = y[l];
+      const double* zr = Zr(l);
+      for (int i = 0; i < m; ++i) zs[i] += zr[i] * yl;
     }
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm += zs[i] * zs[i];
     nrm = std::sqrt(nrm);
-    for (int i = 0; i < m; ++i) V[(size_t)i * m + k] /= nrm;
+    for (int i = 0; i < m; ++i) V[(size_t)i * m + k] = zs[i] / nrm;
   }
   return true;
 }
@@ -236,6 +252,76 @@ bool invert(int m, const std::vector<double>& A, std::vector<double>& Ainv) {
       }
     }
   }
+  return true;
+}
+
+// Eigen-decomposition of a centro-symmetric A (J A J = A, J the exchange; the
+// 1-D operator of an axis with the same face type at both ends).  With
+// p = floor(m/2) and the orthogonal change of basis Q to symmetric vectors
+// [u; sqrt(2) t; J u] / sqrt(2) and antisymmetric ones [u; 0; -J u] / sqrt(2),
+// Q^T A Q = diag(S, W) with S = [A_aa + A_ab J, sqrt(2) a_ac; sqrt(2) a_ca, a_cc]
+// (the centre row and column only for odd m) and W = A_aa - A_ab J, so the
+// two half-size problems give V = Q diag(Vs, Vw) and V^{-1} = diag(Vs^{-1},
+// Vw^{-1}) Q^T.  A's upper half is used (exact up to rounding for these).
+bool eig_centro(int m, const std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V,
+                std::vector<double>& Vi) {
+  const int p = m / 2, odd = m & 1, ps = p + odd;
+  auto a = [&](int i, int j) { return A[(size_t)i * m + j]; };
+  std::vector<double> S((size_t)ps * ps), W((size_t)p * p);
+  const double r2 = std::sqrt(2.0);
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      const double ab = a(i, m - 1 - j);  // (A_ab J)_ij
+      S[(size_t)i * ps + j] = a(i, j) + ab;
+      W[(size_t)i * p + j] = a(i, j) - ab;
+    }
+  if (odd) {
+    for (int i = 0; i < p; ++i) {
+      S[(size_t)i * ps + p] = r2 * a(i, p);
+      S[(size_t)p * ps + i] = r2 * a(p, i);
+    }
+    S[(size_t)p * ps + p] = a(p, p);
+  }
+  std::vector<double> ls, Vs, Vsi, lw, Vw, Vwi;
+  if (!eig_real(ps, S, ls, Vs) || !invert(ps, Vs, Vsi)) return false;
+  if (p > 0 && (!eig_real(p, W, lw, Vw) || !invert(p, Vw, Vwi))) return false;
+  lam.assign(m, 0.0);
+  V.assign((size_t)m * m, 0.0);
+  Vi.assign((size_t)m * m, 0.0);
+  const double h = 1.0 / r2;
+  // symmetric eigenvectors: columns k < ps; antisymmetric: columns ps + k
+  for (int k = 0; k < ps; ++k) {
+    lam[k] = ls[k];
+    for (int i = 0; i < p; ++i) {
+      const double u = Vs[(size_t)i * ps + k] * h;
+      V[(size_t)i * m + k] = u;
+      V[(size_t)(m - 1 - i) * m + k] = u;
+    }
+    if (odd) V[(size_t)p * m + k] = Vs[(size_t)p * ps + k];
+  }
+  for (int k = 0; k < p; ++k) {
+    lam[ps + k] = lw[k];
+    for (int i = 0; i < p; ++i) {
+      const double u = Vw[(size_t)i * p + k] * h;
+      V[(size_t)i * m + ps + k] = u;
+      V[(size_t)(m - 1 - i) * m + ps + k] = -u;
+    }
+  }
+  // V^{-1} = diag(Vs^{-1}, Vw^{-1}) Q^T
+  for (int k = 0; k < ps; ++k) {
+    for (int j = 0; j < p; ++j) {
+      const double u = Vsi[(size_t)k * ps + j] * h;
+      Vi[(size_t)k * m + j] = u;
+      Vi[(size_t)k * m + (m - 1 - j)] = u;
+    }
+    if (odd) Vi[(size_t)k * m + p] = Vsi[(size_t)k * ps + p];
+  }
+  for (int k = 0; k < p; ++k)
+    for (int j = 0; j < p; ++j) {
+      const double u = Vwi[(size_t)k * p + j] * h;
+      Vi[(size_t)(ps + k) * m + j] = u;
+      Vi[(size_t)(ps + k) * m + (m - 1 - j)] = -u;
+    }
   return true;
 }
 
@@ -630,7 +716,9 @@ int precond_setup(cheb_plan* p) {
         const int m = p->ax[a].N - 1;
         std::vector<double> A;
         reduced_1d(p->ax[a].N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], A);
-        okv[a] = eig_real(m, A, lamv[a], Vv[a]) && invert(m, Vv[a], Viv[a]);
+        // the same face type at both ends: the 1-D operator is centro-symmetric
+        okv[a] = p->g.bc[2 * a] == p->g.bc[2 * a + 1] ? eig_centro(m, A, lamv[a], Vv[a], Viv[a])
+                                                      : eig_real(m, A, lamv[a], Vv[a]) && invert(m, Vv[a], Viv[a]);
       });
     }
     for (auto& t : th) t.join();
