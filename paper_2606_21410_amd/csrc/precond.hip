@@ -57,14 +57,18 @@ void reduced_1d(int N, double L, int blo, int bhi, std::vector<double>& A) {
       lN[j] = -b / dNN;
     }
   }
-  // DD
+  // DD on the interior rows 1..N-1 (the only ones A uses), k ascending per entry
   std::vector<double> D2((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i)
+  const double* __restrict__ Dp = D.data();
+  for (int i = 1; i < N; ++i) {
+    double* __restrict__ row = D2.data() + (size_t)i * n;
     for (int k = 0; k < n; ++k) {
-      const double dik = D[(size_t)i * n + k];
+      const double dik = Dp[(size_t)i * n + k];
       if (dik == 0.0) continue;
-      for (int j = 0; j < n; ++j) D2[(size_t)i * n + j] += dik * D[(size_t)k * n + j];
+      const double* __restrict__ dk = Dp + (size_t)k * n;
+      for (int j = 0; j < n; ++j) row[j] += dik * dk[j];
     }
+  }
   A.assign((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j)
