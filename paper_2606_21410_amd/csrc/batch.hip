@@ -547,7 +547,7 @@ int blgmres(cheb_batch* B, const T* K, const T* b, T* x, bool x_zero, const std:
           h2 -= d[i] * d[i];
         }
         hh2[s] = h2;
-        if (!(h2 > 0.5 * d[j + 1])) reorth = true;
+        if (!(h2 > kReorthEta2 * d[j + 1])) reorth = true;
       }
       T* vnext = kw.V + (size_t)(j + 1) * kw.ld;
       std::fill(coef.begin(), coef.end(), 0.0);

@@ -106,6 +106,9 @@ inline bool use_dense(const cheb_plan* p, int axis, int pi) {
   return p->route == CHEB_ROUTE_MATRIX || !p->auto_fft[pi];
 }
 
+// Arnoldi: a second Gram-Schmidt pass runs when ||w - V h||^2 <= kReorthEta2 ||w||^2
+constexpr double kReorthEta2 = 0.01;
+
 // ---- vector kernels (blas.hip) ----
 size_t multidot_partials_len(size_t npts, int nv);
 // out[i] = <V_i, w> for i < nv, out[nv] = <w, w>  (double accumulation)

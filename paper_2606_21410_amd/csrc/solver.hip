@@ -10,7 +10,9 @@
 // least-squares minimiser over that augmented space.  Orthogonalisation is
 // classical Gram-Schmidt in one pass: the multi-dot returns <v_i, w> and <w, w>
 // together; ||w - V h||^2 = ||w||^2 - ||h||^2, and a second pass runs when
-// that difference signals cancellation (||w_new|| < ||w|| / sqrt(2)).
+// that difference signals severe cancellation, ||w_new|| < ||w|| / 10 (the
+// criterion of Daniel, Gragg, Kaufman and Stewart with eta = 0.1; at 1/sqrt(2)
+// the second pass ran on nearly every step here, to no effect on convergence).
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -205,7 +207,7 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
         hh2 -= dots[i] * dots[i];
       }
       T* vnext = kw.V + (size_t)(j + 1) * kw.ld;
-      if (!(hh2 > 0.5 * dots[j + 1])) {
+      if (!(hh2 > kReorthEta2 * dots[j + 1])) {
         // cancellation: orthogonalise again
         rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots, w, w, 1.0, npts, s);
         if (rc) return rc;
