@@ -92,10 +92,17 @@ static int launch_dense_common(const cheb_plan* p, int axis, int transpose, int 
   a.first = first;
   a.bcmask = bc_mask(p->g.bc);
   a.npencils = pencil_count(axis, a.n);
-  a.m00 = T(p->ax[axis].m00);
-  a.m0N = T(p->ax[axis].m0N);
-  a.mN0 = T(p->ax[axis].mN0);
-  a.mNN = T(p->ax[axis].mNN);
+  {
+    const double m00 = p->ax[axis].m00, m0N = p->ax[axis].m0N, mN0 = p->ax[axis].mN0, mNN = p->ax[axis].mNN;
+    // entries that belong to a Dirichlet end are never used; keep them finite
+    const double det = m00 * mNN - m0N * mN0, id = det != 0.0 ? 1.0 / det : 0.0;
+    a.i00 = T(mNN * id);
+    a.i0N = T(-m0N * id);
+    a.iN0 = T(-mN0 * id);
+    a.iNN = T(m00 * id);
+    a.r00 = T(m00 != 0.0 ? 1.0 / m00 : 0.0);
+    a.rNN = T(mNN != 0.0 ? 1.0 / mNN : 0.0);
+  }
   const int variant = p->dense_var[axis][sizeof(T) == sizeof(double) ? 0 : 1];
   switch (p->ax[axis].N) {
     case 16: return launch_dense_n<T, 16>(a, transpose, variant, s);

@@ -28,6 +28,32 @@ namespace cheb {
 
 enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1 };
 
+// lane move across a DPP pattern (quad permutation, half-row or row mirror)
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over aligned groups of G <= 16 consecutive lanes (within one DPP row),
+// left in every lane of the group: swaps within pairs and quads, then the
+// half-row mirror pairs the two quads of each 8, the row mirror the two 8s
+template <int G, typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "row_sum: group of 1 to 16 lanes");
+  if (G >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  if (G >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  if (G >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+  if (G >= 16) v += dpp_move<0x140>(v); // row_mirror
+  return v;
+}
+
 // Compile-time shape of the split product for one N (also used by the host
 // code that writes the fragment tables and sizes the LDS).
 struct DenseDims {
@@ -94,6 +120,23 @@ struct DenseSys {
 };
 
 template <typename T>
+struct DenseArgs;
+
+// entry i of the active-system list, read through the constant address space
+// (scalar loads; the tables are not written while a pass runs)
+template <typename T>
+__device__ inline DenseSys dense_sys_at(const DenseArgs<T>& a, int i) {
+  typedef const __attribute__((address_space(4))) int ci4;
+  typedef const __attribute__((address_space(4))) long long cl4;
+  const DenseSys* e = a.sys + ((ci4*)a.act)[i];
+  DenseSys s;
+  s.off = *(cl4*)&e->off;
+  s.bcmask = *(ci4*)&e->bcmask;
+  s.pad_ = 0;
+  return s;
+}
+
+template <typename T>
 struct DenseArgs {
   const T* u;  // single system (sys == nullptr)
   const T* K;
@@ -107,7 +150,9 @@ struct DenseArgs {
   T* sink;         // one word that stores of off-tile elements go to
   int n[3];
   int axis, first, bcmask, npencils;  // bcmask of the single system
-  T m00, m0N, mN0, mNN;
+  // the face rows' 2 x 2 matrix M = [m00 m0N; mN0 mNN] of the lift: the
+  // entries of M^{-1} (both ends Neumann) and 1 / m00, 1 / mNN (one end)
+  T i00, i0N, iN0, iNN, r00, rNN;
 };
 
 // tile element e -> (node j along the pencil, column c): pencil-contiguous for
@@ -140,8 +185,8 @@ struct DenseArgs {
   } while (0)
 
 // vector-ALU dot products of each tile column with the LDS tile for the middle
-// row N/2 of the odd part (when it does not fill a 16-row block); lane lg == 0
-// of each column's group holds the sum.
+// row N/2 of the odd part (when it does not fill a 16-row block); every lane of
+// each column's group holds the sum.
 #define DENSE_VDOT(MIDOUT)                                                         \
   do {                                                                             \
     MIDOUT = T(0);                                                                 \
@@ -149,7 +194,7 @@ struct DenseArgs {
       if (lc < C)                                                                  \
         for (int j = lg; j < S.KO; j += LPC)                                       \
           MIDOUT += amid[j] * (U[j * SC + lc] - U[(N - j) * SC + lc]);             \
-      MIDOUT = group_sum<LPC>(MIDOUT);                                             \
+      MIDOUT = row_sum<LPC>(MIDOUT);                                               \
     }                                                                              \
   } while (0)
 
@@ -164,13 +209,12 @@ struct DenseArgs {
       const T s0_ = ACCO[0] + ACCE[0], sN_ = ACCO[0] - ACCE[0];             \
       T u0 = T(0), uN = T(0);                                               \
       if (nlo && nhi) {                                                     \
-        const T det = a.m00 * a.mNN - a.m0N * a.mN0;                        \
-        u0 = (-s0_ * a.mNN + sN_ * a.m0N) / det;                            \
-        uN = (-sN_ * a.m00 + s0_ * a.mN0) / det;                            \
+        u0 = -(a.i00 * s0_ + a.i0N * sN_);                                  \
+        uN = -(a.iN0 * s0_ + a.iNN * sN_);                                  \
       } else if (nlo) {                                                     \
-        u0 = -s0_ / a.m00;                                                  \
+        u0 = -a.r00 * s0_;                                                  \
       } else if (nhi) {                                                     \
-        uN = -sN_ / a.mNN;                                                  \
+        uN = -a.rNN * sN_;                                                  \
       }                                                                     \
       cend[2 * col] = u0;                                                   \
       cend[2 * col + 1] = uN;                                               \
@@ -255,11 +299,12 @@ struct DenseArgs {
     }                                                                 \
   } while (0)
 
-// pointers and face types of the system that owns tile TILE
+// pointers and face types of the system that owns tile TILE (uniform, so the
+// tables are read with scalar loads, which wait on nothing in the vector queue)
 #define DENSE_SYS(TILE, PU, PK, PY, BM)                   \
   do {                                                    \
     if (a.sys) {                                          \
-      const DenseSys s_ = a.sys[a.act[(TILE) / tps]];     \
+      const DenseSys s_ = dense_sys_at(a, (TILE) / tps);  \
       PU = a.u + s_.off;                                  \
       PK = a.K + s_.off;                                  \
       PY = a.y + s_.off;                                  \
@@ -395,18 +440,19 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     drw[j] = a.drow0[j];
     drw[n + j] = a.drowN[j];
   }
-  // u tile -> LDS with its end nodes cleared (the interior values of the lift)
-#define DENSE_PUT(DU, UR, KR)                       \
-  do {                                              \
-    _Pragma("unroll") for (int q = 0; q < EPT; ++q) { \
-      const int e = tid + q * NT;                   \
-      if (e < TOT) {                                \
-        int j, c;                                   \
-        DENSE_MAP(e, j, c);                         \
-        (DU)[j * SC + c] = j != 0 && j != N ? UR[q] : T(0); \
-        Kt[j * SC + c] = KR[q];                     \
-      }                                             \
-    }                                               \
+  // u tile -> LDS with its end nodes cleared (the interior values of the lift).
+  // Every element is written, past the tile's last element to the padding
+  // column C, which nothing reads: under a branch the compiler would sink the
+  // tail's loads into it and wait for them in a second round trip.
+#define DENSE_PUT(DU, UR, KR)                                 \
+  do {                                                        \
+    _Pragma("unroll") for (int q = 0; q < EPT; ++q) {         \
+      const int e = tid + q * NT;                             \
+      int j = 0, c = C;                                       \
+      if (e < TOT) DENSE_MAP(e, j, c);                        \
+      (DU)[j * SC + c] = j != 0 && j != N ? UR[q] : T(0);     \
+      Kt[j * SC + c] = KR[q];                                 \
+    }                                                         \
   } while (0)
 
   for (; tile < t_end; tile += t_step, slot ^= 1) {
@@ -489,13 +535,12 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         const T z0 = U[tid], zN = U[N * SC + tid];
         T mu0 = T(0), muN = T(0);
         if (nlo && nhi) {
-          const T det = a.m00 * a.mNN - a.m0N * a.mN0;
-          mu0 = (z0 * a.mNN - zN * a.mN0) / det;
-          muN = (zN * a.m00 - z0 * a.m0N) / det;
+          mu0 = a.i00 * z0 + a.iN0 * zN;
+          muN = a.i0N * z0 + a.iNN * zN;
         } else if (nlo) {
-          mu0 = z0 / a.m00;
+          mu0 = a.r00 * z0;
         } else if (nhi) {
-          muN = zN / a.mNN;
+          muN = a.rNN * zN;
         }
         cend[2 * tid] = mu0;
         cend[2 * tid + 1] = muN;
