@@ -18,7 +18,11 @@
 //   s_i = sum_{j < KO} Ao[i][j] o_j,   d_i = sum_{j < KE} Ae[i][j] e_j,
 //   Ao[i][j] = (M[i][j] - M[i][N-j]) / 2,  Ae[i][j] = (M[i][j] + M[i][N-j]) / 2
 // (Ae[i][N/2] = M[i][N/2] / 2 for even N, where e_{N/2} = 2 u_{N/2}), which
-// halves the multiply-adds of the dense product.
+// halves the multiply-adds of the dense product.  The tile is kept in LDS in
+// split form, e_j in rows j <= N/2 and o_j in rows N/2 + 1 + j, so the matrix
+// instructions take their B operands straight from LDS: the loads fetch each
+// pencil's nodes j and N - j together, and the first product's epilogue
+// writes the flux split the same way.
 #pragma once
 
 #include "dev_common.h"
@@ -168,20 +172,32 @@ struct DenseArgs {
     }                        \
   } while (0)
 
-// ACCO/ACCE = split products of the LDS tile (B operand) with this wave's A
-// fragments (from the LDS table).  Rows j > N/2 of the last k-step meet zero
-// table entries.
-#define DENSE_GEMM(ACCO, ACCE, ISSUE)                                          \
-  do {                                                                         \
-    ACCO = V4{0, 0, 0, 0};                                                     \
-    ACCE = V4{0, 0, 0, 0};                                                     \
-    _Pragma("unroll") for (int ks = 0; ks < S.KE4; ++ks) {                     \
-      ISSUE(ks);                                                               \
-      const int j = 4 * ks + lk;                                               \
-      const T x0 = U[j * SC + col], x1 = U[(N - j) * SC + col];                \
-      if (ks < S.KO4) ACCO = Mfma<T>::mac(V == 0 ? Ao[ks * 64] : ao[ks], x0 - x1, ACCO); \
-      ACCE = Mfma<T>::mac(V == 0 ? Ae[ks * 64] : ae[ks], x0 + x1, ACCE);       \
-    }                                                                          \
+// tile pair p -> (row jp <= N/2 of the pair (jp, N - jp), column c), laid
+// out like DENSE_MAP
+#define DENSE_PMAP(p, jp, c)  \
+  do {                        \
+    if (contig) {             \
+      c = (p) / S.KE;         \
+      jp = (p) - c * S.KE;    \
+    } else {                  \
+      jp = (p) / C;           \
+      c = (p) - jp * C;       \
+    }                         \
+  } while (0)
+
+// ACCO/ACCE = split products of the split LDS tile (B operand: o_j, e_j) with
+// this wave's A fragments (from the LDS table).  Rows j > N/2 of the last
+// k-step of the even part meet zero table entries.
+#define DENSE_GEMM(ACCO, ACCE, ISSUE)                                              \
+  do {                                                                             \
+    ACCO = V4{0, 0, 0, 0};                                                         \
+    ACCE = V4{0, 0, 0, 0};                                                         \
+    _Pragma("unroll") for (int ks = 0; ks < S.KE4; ++ks) {                         \
+      ISSUE(ks);                                                                   \
+      const int j = 4 * ks + lk;                                                   \
+      if (ks < S.KO4) ACCO = Mfma<T>::mac(V == 0 ? Ao[ks * 64] : ao[ks], U[(S.KE + j) * SC + col], ACCO); \
+      ACCE = Mfma<T>::mac(V == 0 ? Ae[ks * 64] : ae[ks], U[j * SC + col], ACCE);   \
+    }                                                                              \
   } while (0)
 
 // vector-ALU dot products of each tile column with the LDS tile for the middle
@@ -193,7 +209,7 @@ struct DenseArgs {
     if (S.MIDV) {                                                                  \
       if (lc < C)                                                                  \
         for (int j = lg; j < S.KO; j += LPC)                                       \
-          MIDOUT += amid[j] * (U[j * SC + lc] - U[(N - j) * SC + lc]);             \
+          MIDOUT += amid[j] * U[(S.KE + j) * SC + lc];                             \
       MIDOUT = row_sum<LPC>(MIDOUT);                                               \
     }                                                                              \
   } while (0)
@@ -244,10 +260,16 @@ struct DenseArgs {
           hi -= u0_ * cN_ + uN_ * c0_;                                       \
         }                                                                    \
         if (FLUX) {                                                          \
+          /* flux K * (M u), stored split for the second product */          \
           lo *= Kt[i * SC + col];                                            \
           hi *= Kt[(N - i) * SC + col];                                      \
-        }                                                                    \
-        if (2 * i == N) {                                                    \
+          if (2 * i == N) {                                                  \
+            U[i * SC + col] = lo + lo;                                       \
+          } else {                                                           \
+            U[i * SC + col] = lo + hi;                                       \
+            U[(S.KE + i) * SC + col] = lo - hi;                              \
+          }                                                                  \
+        } else if (2 * i == N) {                                             \
           U[i * SC + col] = lo;                                              \
         } else {                                                             \
           U[i * SC + col] = lo;                                              \
@@ -259,7 +281,7 @@ struct DenseArgs {
       T m_ = MIDVAL;                                                         \
       if (lift_) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
       if (FLUX) m_ *= Kt[S.HALF * SC + lc];                                  \
-      U[S.HALF * SC + lc] = m_;                                              \
+      U[S.HALF * SC + lc] = FLUX ? m_ + m_ : m_;                             \
     }                                                                        \
   } while (0)
 
@@ -278,24 +300,27 @@ struct DenseArgs {
     }                                                                      \
   } while (0)
 
-// global -> registers: u and K of the tile in slot SLOT (u's end nodes are
-// cleared when the tile is written to LDS).  Every load is issued (off-tile
-// elements read node 0 and their columns are discarded), so the number of
-// outstanding loads is static and the compiler's waits stay exact; nothing here
-// waits for the loads.
+// global -> registers: u and K of the tile in slot SLOT, pair by pair (nodes
+// jp and N - jp of a pencil; u's end nodes are cleared when the tile is written
+// to LDS).  Every load is issued (off-tile pairs read node 0 and their columns
+// are discarded), so the number of outstanding loads is static and the
+// compiler's waits stay exact; nothing here waits for the loads.
 #define DENSE_LOAD(SLOT, UR, KR, PU, PK)                              \
   do {                                                                \
-    int ad_[EPT];                                                     \
-    _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
-      const int e = tid + q * NT < TOT ? tid + q * NT : TOT - 1;      \
-      int j, c;                                                       \
-      DENSE_MAP(e, j, c);                                             \
+    int alo_[EPP], ahi_[EPP];                                         \
+    _Pragma("unroll") for (int q = 0; q < EPP; ++q) {                 \
+      const int p = tid + q * NT < TOTP ? tid + q * NT : TOTP - 1;    \
+      int jp, c;                                                      \
+      DENSE_PMAP(p, jp, c);                                           \
       const int b = cbase[SLOT][c];                                   \
-      ad_[q] = b >= 0 ? b + j * stride : 0;                           \
+      alo_[q] = b >= 0 ? b + jp * stride : 0;                         \
+      ahi_[q] = b >= 0 ? b + (N - jp) * stride : 0;                   \
     }                                                                 \
-    _Pragma("unroll") for (int q = 0; q < EPT; ++q) {                 \
-      UR[q] = (PU)[ad_[q]];                                           \
-      KR[q] = (PK)[ad_[q]];                                           \
+    _Pragma("unroll") for (int q = 0; q < EPP; ++q) {                 \
+      UR[2 * q] = (PU)[alo_[q]];                                      \
+      UR[2 * q + 1] = (PU)[ahi_[q]];                                  \
+      KR[2 * q] = (PK)[alo_[q]];                                      \
+      KR[2 * q + 1] = (PK)[ahi_[q]];                                  \
     }                                                                 \
   } while (0)
 
@@ -330,6 +355,10 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   constexpr int SC = C + 1;  // LDS row stride (odd: conflict-free transposed writes)
   constexpr int TOT = n * C;
   constexpr int EPT = (TOT + NT - 1) / NT;
+  static_assert(N % 2 == 0, "split tile layout needs even N");
+  constexpr int TOTP = S.KE * C;                 // node pairs (jp, N - jp) of a tile
+  constexpr int EPP = (TOTP + NT - 1) / NT;      // pairs per thread
+  constexpr int NL = 4 * EPP;                    // u and K loads per thread
   constexpr int LPC = pow2_floor(NT / C) < 64 ? pow2_floor(NT / C) : 64;  // lanes per column
   typedef typename Mfma<T>::v4 V4;
 
@@ -427,7 +456,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   // top and relies on the second workgroup of the CU for overlap (prefetch
   // registers would spill, and spill reloads wait for every load in flight).
   constexpr bool PREF = V == 0;
-  T ureg[EPT], kreg[EPT];
+  T ureg[2 * EPP], kreg[2 * EPP];
   if (PREF) DENSE_LOAD(0, ureg, kreg, cu, cK);
 #pragma unroll
   for (int i = 0; i < TI; ++i)
@@ -440,18 +469,23 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     drw[j] = a.drow0[j];
     drw[n + j] = a.drowN[j];
   }
-  // u tile -> LDS with its end nodes cleared (the interior values of the lift).
-  // Every element is written, past the tile's last element to the padding
-  // column C, which nothing reads: under a branch the compiler would sink the
-  // tail's loads into it and wait for them in a second round trip.
+  // registers -> LDS: u in split form (e_jp in row jp, o_jp in row N/2 + 1 + jp)
+  // with its end nodes cleared (the interior values of the lift), K as it is.
+  // Every pair is written, past the tile's last pair to the padding column C,
+  // which nothing reads: under a branch the compiler would sink the tail's
+  // loads into it and wait for them in a second round trip.
 #define DENSE_PUT(DU, UR, KR)                                 \
   do {                                                        \
-    _Pragma("unroll") for (int q = 0; q < EPT; ++q) {         \
-      const int e = tid + q * NT;                             \
-      int j = 0, c = C;                                       \
-      if (e < TOT) DENSE_MAP(e, j, c);                        \
-      (DU)[j * SC + c] = j != 0 && j != N ? UR[q] : T(0);     \
-      Kt[j * SC + c] = KR[q];                                 \
+    _Pragma("unroll") for (int q = 0; q < EPP; ++q) {         \
+      const int p = tid + q * NT;                             \
+      int jp = 0, c = C;                                      \
+      if (p < TOTP) DENSE_PMAP(p, jp, c);                     \
+      const T ua = jp != 0 ? UR[2 * q] : T(0);                \
+      const T ub = jp != 0 ? UR[2 * q + 1] : T(0);            \
+      (DU)[jp * SC + c] = ua + ub;                            \
+      if (2 * jp != N) (DU)[(S.KE + jp) * SC + c] = ua - ub;  \
+      Kt[jp * SC + c] = KR[2 * q];                            \
+      Kt[(N - jp) * SC + c] = KR[2 * q + 1];                  \
     }                                                         \
   } while (0)
 
@@ -471,7 +505,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     // addresses are formed here and the loads are issued a few at a time
     // between the products' matrix instructions, so the matrix cores keep
     // working while load issue waits for queue space.
-    T unx[PREF ? EPT : 1], knx[PREF ? EPT : 1], yreg[EPT];
+    T unx[PREF ? 2 * EPP : 1], knx[PREF ? 2 * EPP : 1], yreg[EPT];
     {
       T* ny_;
       int nbm_;
@@ -488,15 +522,29 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     const int b_ = cbase[SL][c_];                                            \
     return b_ >= 0 ? b_ + j_ * stride : 0;                                   \
   }())
-    // loads issued at k-step KS of the first product: prefetch element KS/2 (u
-    // at even steps, K at odd ones); y loads go between the second product's
-    // k-steps
-#define DENSE_ISSUE1(KS)                                   \
-  do {                                                     \
-    if (PREF && (KS) < 2 * EPT) {                          \
-      if ((KS) % 2 == 0) unx[PREF ? (KS) / 2 : 0] = nu[DENSE_AD(slot ^ 1, (KS) / 2)]; \
-      else knx[PREF ? (KS) / 2 : 0] = nK[DENSE_AD(slot ^ 1, (KS) / 2)];              \
-    }                                                      \
+    // global offset of node jp (HI: N - jp) of pair q of the tile in slot SL
+#define DENSE_PAD(SL, q, HI)                                                 \
+  ([&]() {                                                                   \
+    const int p_ = tid + (q) * NT < TOTP ? tid + (q) * NT : TOTP - 1;        \
+    int jp_, c_;                                                             \
+    DENSE_PMAP(p_, jp_, c_);                                                 \
+    const int b_ = cbase[SL][c_];                                            \
+    return b_ >= 0 ? b_ + ((HI) ? N - jp_ : jp_) * stride : 0;               \
+  }())
+    // prefetch load L of the next tile: pair L / 4, u_jp, u_{N-jp}, K_jp, K_{N-jp}
+#define DENSE_PREF1(L)                                                                     \
+  do {                                                                                     \
+    const int q_ = PREF ? (L) / 4 : 0;                                                     \
+    if ((L) % 4 == 0) unx[PREF ? 2 * q_ : 0] = nu[DENSE_PAD(slot ^ 1, q_, false)];         \
+    else if ((L) % 4 == 1) unx[PREF ? 2 * q_ + 1 : 0] = nu[DENSE_PAD(slot ^ 1, q_, true)]; \
+    else if ((L) % 4 == 2) knx[PREF ? 2 * q_ : 0] = nK[DENSE_PAD(slot ^ 1, q_, false)];    \
+    else knx[PREF ? 2 * q_ + 1 : 0] = nK[DENSE_PAD(slot ^ 1, q_, true)];                   \
+  } while (0)
+    // loads issued at k-step KS of the first product: prefetch load KS; y loads
+    // go between the second product's k-steps
+#define DENSE_ISSUE1(KS)                     \
+  do {                                       \
+    if (PREF && (KS) < NL) DENSE_PREF1(KS);  \
   } while (0)
 #define DENSE_ISSUE2(KS)                                                           \
   do {                                                                             \
@@ -509,10 +557,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_GEMM(acco, acce, DENSE_ISSUE1);
     // whatever did not fit between the k-steps
 #pragma unroll
-    for (int ks = S.KE4; ks < (PREF ? 2 * EPT : 0); ++ks) {
-      if (ks % 2 == 0) unx[PREF ? ks / 2 : 0] = nu[DENSE_AD(slot ^ 1, ks / 2)];
-      else knx[PREF ? ks / 2 : 0] = nK[DENSE_AD(slot ^ 1, ks / 2)];
-    }
+    for (int ks = S.KE4; ks < (PREF ? NL : 0); ++ks) DENSE_PREF1(ks);
     DENSE_VDOT(midv);
     if (MODE == DENSE_REDUCED) DENSE_LIFTVALS(acco, acce);
     __syncthreads();
@@ -572,7 +617,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     }
     if (PREF) {
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
+      for (int q = 0; q < 2 * EPP; ++q) {
         ureg[q] = unx[PREF ? q : 0];
         kreg[q] = knx[PREF ? q : 0];
       }
@@ -583,6 +628,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 #undef DENSE_MAP
 #undef DENSE_GEMM
 #undef DENSE_ISSUE1
+#undef DENSE_PREF1
+#undef DENSE_PAD
+#undef DENSE_PMAP
 #undef DENSE_PUT
 #undef DENSE_AD
 #undef DENSE_ISSUE2
