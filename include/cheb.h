@@ -160,6 +160,14 @@ int cheb_plan_set_route(cheb_plan* plan, int32_t route);
 int cheb_plan_autotune(cheb_plan* plan, int32_t field_precision, const void* K, const void* u, void* y,
                        double* report, int32_t report_len);
 
+/* Tile shape of the matrix-core route for one precision, on every axis:
+ * 0 = 8-wave workgroups with the derivative's fragment table in LDS, 1 = 4-wave
+ * workgroups with each wave's fragments in registers (the two shapes the
+ * autotuner times).  field_precision: CHEB_F64 or CHEB_F32 (the passes that run
+ * in that type).  Returns CHEB_ERR_INVALID_ARG for another precision or shape;
+ * affects only the matrix-core route. */
+int cheb_plan_set_tile_shape(cheb_plan* plan, int32_t field_precision, int32_t shape);
+
 int cheb_plan_destroy(cheb_plan* plan);
 
 /* Operator application (Algorithm 3 with the rows of Section 2.3.1).

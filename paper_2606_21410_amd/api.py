@@ -82,6 +82,12 @@ class Plan:
         L.check(self.lib.cheb_plan_set_route(self._h, _ROUTE[route]))
         self.route = route
 
+    def set_tile_shape(self, shape: int, precision: str = "f64"):
+        """Tile shape of the matrix-core route for the passes that run in
+        ``precision`` ('f64' or 'f32'): 0 = 8-wave workgroups with the fragment
+        table in LDS, 1 = 4-wave workgroups with register fragments."""
+        L.check(self.lib.cheb_plan_set_tile_shape(self._h, _PREC[precision], int(shape)))
+
     def capture_applies(self, K, us, ys, mode: str = "reduced"):
         """Record one operator application per (u, y) pair into a HIP graph
         (torch.cuda.CUDAGraph; the applies launch only kernels, no memsets or

@@ -284,6 +284,24 @@ int cheb_plan_set_route(cheb_plan* plan, int32_t route) {
   return CHEB_OK;
 }
 
+int cheb_plan_set_tile_shape(cheb_plan* plan, int32_t field_precision, int32_t shape) {
+  if (!plan) {
+    set_error("null plan");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (field_precision != CHEB_F64 && field_precision != CHEB_F32) {
+    set_error("tile shape: field_precision must be CHEB_F64 or CHEB_F32");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (shape != 0 && shape != 1) {
+    set_error("tile shape must be 0 (8-wave, LDS table) or 1 (4-wave, register fragments)");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  const int pi = field_precision == CHEB_F64 ? 0 : 1;
+  for (int a = 0; a < 3; ++a) plan->dense_var[a][pi] = shape;
+  return CHEB_OK;
+}
+
 int cheb_plan_destroy(cheb_plan* plan) {
   if (!plan) return CHEB_OK;
   if (plan->dconst64) (void)hipFree(plan->dconst64);

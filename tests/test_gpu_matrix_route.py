@@ -73,6 +73,45 @@ def test_matrix_route_f32(n, bcname):
     assert rel_l2(yt, O.apply_reduced_transpose(G, K32, u32)) <= F32_TOL
 
 
+@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_matrix_route_every_tile_shape(shape, prec):
+    """Both tile shapes in both precisions, whatever the default or the
+    autotuner would pick: two grids whose axes cover every N of the route
+    (unit-stride and strided passes, the middle-row sums over 4, 8 and 16
+    lanes), reduced operator and transpose, against the oracle."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    dt, tol = (torch.float64, F64_TOL) if prec == "f64" else (torch.float32, F32_TOL)
+    for n, bcname in (((129, 33, 97), "NDNNDN"), ((17, 65, 49), "DDNNNN")):
+        bc = BC_SETS[bcname]
+        log(f"tile shape {shape} {prec} n={n} bc={bcname}")
+        G, u, K = _case(n, bc, 800)
+        if prec == "f32":
+            u = u.astype(np.float32).astype(np.float64)
+            K = K.astype(np.float32).astype(np.float64)
+        plan = Plan(n, G.lo, G.hi, bc, prec, route="matrix")
+        plan.set_tile_shape(shape, prec)
+        Kd, ud = to_dev(K, dt), to_dev(u, dt)
+        yr = to_host(plan.apply(Kd, ud, mode="reduced"))
+        assert rel_l2(yr, O.apply_reduced(G, K, u)) <= tol
+        assert np.all(yr[~G.interior] == 0.0)
+        yt = to_host(plan.apply(Kd, ud, mode="transpose"))
+        assert rel_l2(yt, O.apply_reduced_transpose(G, K, u)) <= tol
+        assert np.all(yt[~G.interior] == 0.0)
+
+
+def test_tile_shape_rejects_bad_arguments():
+    require_gpu()
+    from paper_2606_21410_amd.api import Plan
+    from paper_2606_21410_amd import _lib as L
+    plan = Plan((17, 17, 17), (0, 0, 0), (1, 1, 1), BC_SETS["DDNNNN"], "f64")
+    for shape, prec in ((2, "f64"), (-1, "f32"), (0, "mixed")):
+        with pytest.raises(L.ChebError):
+            plan.set_tile_shape(shape, prec)
+
+
 def test_matrix_route_dot_identity_129():
     """<v, A u> = <A^T v, u> for the matrix route at the benchmark size."""
     require_gpu()
