@@ -239,8 +239,11 @@ struct DenseArgs {
 
 // accumulators -> LDS tile rows i and N-i.  FLUX (first product): add the
 // lift's rank-2 correction u0 M[:][0] + uN M[:][N] (LIFT, on axes with a
-// Neumann end) and multiply by K.  M is centro-antisymmetric, so row N-i of the
-// correction is -(u0 M[i][N] + uN M[i][0]).
+// Neumann end), multiply by K and store the flux split into the u tile.  M is
+// centro-antisymmetric, so row N-i of the correction is -(u0 M[i][N] +
+// uN M[i][0]).  Otherwise (second product) the rows go to the K tile, dead
+// since the first epilogue, so the second product's reads of the u tile need
+// no barrier before this.
 #define DENSE_EPI(ACCO, ACCE, MIDVAL, FLUX, LIFT)                            \
   do {                                                                       \
     T u0_ = T(0), uN_ = T(0);                                                \
@@ -270,10 +273,10 @@ struct DenseArgs {
             U[(S.KE + i) * SC + col] = lo - hi;                              \
           }                                                                  \
         } else if (2 * i == N) {                                             \
-          U[i * SC + col] = lo;                                              \
+          Kt[i * SC + col] = lo;                                             \
         } else {                                                             \
-          U[i * SC + col] = lo;                                              \
-          U[(N - i) * SC + col] = hi;                                        \
+          Kt[i * SC + col] = lo;                                             \
+          Kt[(N - i) * SC + col] = hi;                                       \
         }                                                                    \
       }                                                                      \
     }                                                                        \
@@ -281,7 +284,8 @@ struct DenseArgs {
       T m_ = MIDVAL;                                                         \
       if (lift_) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
       if (FLUX) m_ *= Kt[S.HALF * SC + lc];                                  \
-      U[S.HALF * SC + lc] = FLUX ? m_ + m_ : m_;                             \
+      if (FLUX) U[S.HALF * SC + lc] = m_ + m_;                               \
+      else Kt[S.HALF * SC + lc] = m_;                                        \
     }                                                                        \
   } while (0)
 
@@ -453,8 +457,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   // V = 0 loads the next tile's u and K into registers between the first
   // product's matrix instructions and writes them to LDS at the top of the next
   // tile.  V = 1, whose registers hold the fragments, loads each tile at its
-  // top and relies on the second workgroup of the CU for overlap (prefetch
-  // registers would spill, and spill reloads wait for every load in flight).
+  // top and relies on the second workgroup of the CU for overlap: prefetching
+  // into registers (during the first product, or after the second epilogue)
+  // and into a second LDS buffer pair all measured slower at 129^3.
   constexpr bool PREF = V == 0;
   T ureg[2 * EPP], kreg[2 * EPP];
   if (PREF) DENSE_LOAD(0, ureg, kreg, cu, cK);
@@ -570,14 +575,13 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     for (int q = S.KE4; q < EPT; ++q)
       if (!FIRST) yreg[q] = cy[DENSE_AD(slot, q)];
     DENSE_VDOT(midv);
-    __syncthreads();
-    DENSE_EPI(acco, acce, midv, false, false);
+    DENSE_EPI(acco, acce, midv, false, false);  // into the K tile: no barrier needed before it
     __syncthreads();
 
     if (MODE == DENSE_TRANSPOSE) {
       // transposed lift: mu = M^{-T} [z_0, z_N]; interior -= mu0 D[0][:] + muN D[N][:]
       if (tid < C) {
-        const T z0 = U[tid], zN = U[N * SC + tid];
+        const T z0 = Kt[tid], zN = Kt[N * SC + tid];
         T mu0 = T(0), muN = T(0);
         if (nlo && nhi) {
           mu0 = a.i00 * z0 + a.iN0 * zN;
@@ -606,7 +610,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         const int b = cbase[slot][c];
         const bool ok = b >= 0 && tid + q * NT < TOT;
         const bool in = j != 0 && j != N;
-        T x = U[j * SC + c];
+        T x = Kt[j * SC + c];
         if (MODE == DENSE_TRANSPOSE && (nlo || nhi)) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
         if (!FIRST) x += yreg[q];
         ov[q] = in ? x : T(0);
