@@ -241,6 +241,47 @@ def homogenisation_section(dev, n_struct=32, rtol=1e-10):
     return out
 
 
+def inclusion_section(dev, n=129, n_plain=33, rtol=1e-10):
+    """Section 3.3's spherical-inclusion study: one sphere of radius 0.2 at the
+    box centre (phi = 0.0335), or its eighths at the eight corners, sampled
+    sharply at the nodes; u = -1 / +1 on the x faces, zero flux elsewhere;
+    contrast k_i/k_m = 1e-4 .. 1e4.  Per contrast: the preconditioned FP64
+    solve at n^3 (matvecs, seconds, K_num = <K du/dx>/G, Maxwell's dilute
+    estimate, their relative difference) and the plain LGMRES iteration count
+    at n_plain^3 to rtol 1e-6 (the paper's solver)."""
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+
+    def d(a):
+        return torch.from_numpy(a).to(dev, torch.float64)
+
+    out = {"n": n, "n_plain": n_plain, "rtol": rtol, "radius": 0.2}
+    for layout in ("center", "corner"):
+        rows = []
+        for k in range(-4, 5):
+            c = 10.0 ** k
+            P = W.inclusion_problem(n, c, layout)
+            pl = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, info = pl.solve(d(P.K), d(P.f), d(P.g), opts=SolveOptions(rtol=rtol, maxiter=20000, precond=True))
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            knum = pl.flux_average(d(P.K), u)[0] / P.meta["G"]
+            km = W.maxwell_keff(P.meta["phi"], c)
+            Pp = W.inclusion_problem(n_plain, c, layout)
+            pp = Plan(Pp.grid.n, Pp.grid.lo, Pp.grid.hi, Pp.grid.bc, "f64", dev)
+            _, pinfo = pp.solve(d(Pp.K), d(Pp.f), d(Pp.g), opts=SolveOptions(rtol=1e-6, maxiter=30000))
+            rows.append({"contrast": c, "matvecs": info["matvecs"], "status": info["status"], "seconds": round(el, 4),
+                         "K_num": round(knum, 7), "K_maxwell": round(km, 7), "rel_diff": float(abs(knum - km) / km),
+                         "plain_matvecs": pinfo["matvecs"], "plain_status": pinfo["status"]})
+            _log(f"  {layout} contrast {c:g}: {rows[-1]}")
+        out[layout] = rows
+    out["phi"] = 4.0 / 3.0 * 3.141592653589793 * 0.2 ** 3
+    return out
+
+
 def picard_chain_section(dev, levels=(33, 65, 129, 257)):
     """Nonlinear two-phase workload: spheres at volume fraction 0.3 (seed 1003),
     contrast 100, tanh width 2/256, K = K0 (1 + u^2/2), u = -1/+1 on the x faces;
@@ -441,6 +482,11 @@ def main():
         _log("hierarchical Picard chain 33 -> 65 -> 129 -> 257")
         chain = picard_chain_section(dev)
 
+    inclusion = None
+    if not args.no_solve and n == 129:
+        _log("spherical inclusion, contrast sweep 1e-4 .. 1e4")
+        inclusion = inclusion_section(dev)
+
     batch = None
     if not args.no_batch and not args.profile_apply:
         _log("batched homogenisation (32 microstructures x 3 load cases)")
@@ -475,6 +521,7 @@ def main():
         "time_to_1e-8_129": solve,
         "homogenisation_batch": batch,
         "picard_chain": chain,
+        "inclusion_contrast_sweep": inclusion,
     }
     print(json.dumps(out), flush=True)
 

@@ -348,6 +348,49 @@ def two_phase_problem(n: int, seed: int = 1002, volume_fraction: float = 0.2,
                     "contrast": contrast, "spheres": len(centres)})
 
 
+def maxwell_keff(phi: float, k_inc: float, k_mat: float = 1.0) -> float:
+    """Maxwell's dilute estimate of the effective conductivity of spheres of
+    conductivity k_inc at volume fraction phi in a matrix k_mat (Section 3.3)."""
+    d = k_inc - k_mat
+    return k_mat * (2.0 * k_mat + k_inc + 2.0 * phi * d) / (2.0 * k_mat + k_inc - phi * d)
+
+
+def inclusion_conductivity(grid: Grid, contrast: float, layout: str = "center",
+                           radius: float = 0.2, k_mat: float = 1.0) -> np.ndarray:
+    """Two-phase field sampled sharply at the nodes (Section 3.3): k_mat * contrast
+    inside the inclusion, k_mat outside.  layout 'center': one sphere of radius R
+    at the box centre; 'corner': the sphere's eighths at the eight box corners
+    (the same volume, so the same volume fraction 4 pi R^3 / 3 in the unit box)."""
+    X, Y, Z = grid.mesh()
+    lo, hi = np.array(grid.lo), np.array(grid.hi)
+    if layout == "center":
+        c = 0.5 * (lo + hi)
+        inside = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2 <= radius ** 2
+    elif layout == "corner":
+        inside = np.zeros(grid.n, dtype=bool)
+        for cx in (lo[0], hi[0]):
+            for cy in (lo[1], hi[1]):
+                for cz in (lo[2], hi[2]):
+                    inside |= (X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2 <= radius ** 2
+    else:
+        raise ValueError("layout must be 'center' or 'corner'")
+    return np.where(inside, k_mat * contrast, k_mat)
+
+
+def inclusion_problem(n: int, contrast: float, layout: str = "center", radius: float = 0.2,
+                      g: float = 1.0) -> Problem:
+    """The spherical-inclusion homogenisation problem of Section 3.3 in (0,1)^3:
+    u = -g at x = 0, u = +g at x = 1, zero flux elsewhere, f = 0; the imposed
+    mean gradient is G = 2 g / L_x."""
+    grid = Grid((n, n, n), (0.0,) * 3, (1.0,) * 3, MIXED_X_BC)
+    K = inclusion_conductivity(grid, contrast, layout, radius)
+    f = np.zeros(grid.n)
+    phi = 4.0 / 3.0 * math.pi * radius ** 3
+    return Problem(grid, K, f, dirichlet_x_faces(grid, -g, g), None,
+                   {"name": "inclusion", "layout": layout, "contrast": contrast, "radius": radius,
+                    "phi": phi, "G": 2.0 * g / (grid.hi[0] - grid.lo[0])})
+
+
 def random_field(shape, seed: int, dtype=np.float64) -> np.ndarray:
     return rng(seed).standard_normal(size=shape).astype(dtype)
 
