@@ -350,6 +350,51 @@ def load_case(n, axis, device="cuda"):
     return tuple(bc), g
 
 
+def solve_2d(K, f, g, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(L.CHEB_DIRICHLET,) * 4, precision="f64", opts=None,
+             device="cuda"):
+    """The 2-D problem div(K grad u) = f on a rectangle (the setting in which
+    Algorithms 2 and 3 are written), through the 3-D solver.  The grid gets a
+    third axis of three nodes with zero-flux faces, and K, f and the face data
+    are constant along it.  A z-constant field has zero z-derivative, so the 3-D
+    collocation system maps z-constant fields to z-constant fields and is the
+    2-D system on them.  Its solution repeats the 2-D one along z (the Krylov
+    iterates stay z-constant: the same iterations, at three times the 2-D
+    work per matvec).
+
+    K, f: (n0, n1) tensors.  g: four face vectors [x_lo (n1,), x_hi (n1,),
+    y_lo (n0,), y_hi (n0,)], Dirichlet values or outward normal derivatives per
+    ``bc``.  Returns (u of shape (n0, n1), info)."""
+    n0, n1 = K.shape
+    plan = Plan((n0, n1, 3), (lo[0], lo[1], 0.0), (hi[0], hi[1], 1.0), tuple(bc) + (L.CHEB_NEUMANN,) * 2,
+                precision, device)
+    dt = plan.dtype
+    col = lambda t, m: torch.as_tensor(t).to(device, dt).reshape(m, 1).expand(m, 3).reshape(-1)
+    K3 = torch.as_tensor(K).to(device, dt).reshape(n0, n1, 1).expand(n0, n1, 3).contiguous()
+    f3 = torch.as_tensor(f).to(device, dt).reshape(n0, n1, 1).expand(n0, n1, 3).contiguous()
+    zeros = torch.zeros(2 * n0 * n1, dtype=dt, device=device)
+    gp = torch.cat([col(g[0], n1), col(g[1], n1), col(g[2], n0), col(g[3], n0), zeros]).contiguous()
+    u3, info = plan.solve(K3, f3, gp, opts=opts)
+    return u3[:, :, 0].contiguous(), info
+
+
+def solve_1d(K, f, g, lo=-1.0, hi=1.0, bc=(L.CHEB_DIRICHLET,) * 2, precision="f64", opts=None, device="cuda"):
+    """The 1-D problem (K u')' = f on [lo, hi] (the setting of the paper's
+    first example), through the 3-D solver with two further axes of three
+    nodes, zero-flux faces and data constant along them (see solve_2d).
+    K, f: (n,) tensors; g: [value or outward derivative at lo, at hi].  Returns
+    (u of shape (n,), info)."""
+    n = K.shape[0]
+    plan = Plan((n, 3, 3), (lo, 0.0, 0.0), (hi, 1.0, 1.0), tuple(bc) + (L.CHEB_NEUMANN,) * 4, precision, device)
+    dt = plan.dtype
+    K3 = torch.as_tensor(K).to(device, dt).reshape(n, 1, 1).expand(n, 3, 3).contiguous()
+    f3 = torch.as_tensor(f).to(device, dt).reshape(n, 1, 1).expand(n, 3, 3).contiguous()
+    gp = torch.cat([torch.full((9,), float(g[0]), dtype=dt, device=device),
+                    torch.full((9,), float(g[1]), dtype=dt, device=device),
+                    torch.zeros(4 * 3 * n, dtype=dt, device=device)]).contiguous()
+    u3, info = plan.solve(K3, f3, gp, opts=opts)
+    return u3[:, 1, 1].contiguous(), info
+
+
 def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", opts=None, device="cuda"):
     """Apparent conductivity tensors of several microstructures (Section 3.3):
     three load cases per microstructure (unit mean gradient along x, y, z
