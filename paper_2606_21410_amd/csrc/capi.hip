@@ -239,7 +239,6 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
     if (p->dconst32) (void)hipFree(p->dconst32);
     if (p->dd64) (void)hipFree(p->dd64);
     if (p->dd32) (void)hipFree(p->dd32);
-    if (p->dsink) (void)hipFree(p->dsink);
     if (p->hpinned) (void)hipHostFree(p->hpinned);
     delete p;
     return rc;
@@ -308,7 +307,6 @@ int cheb_plan_destroy(cheb_plan* plan) {
   if (plan->dconst32) (void)hipFree(plan->dconst32);
   if (plan->dd64) (void)hipFree(plan->dd64);
   if (plan->dd32) (void)hipFree(plan->dd32);
-  if (plan->dsink) (void)hipFree(plan->dsink);
   if (plan->hpinned) (void)hipHostFree(plan->hpinned);
   if (plan->pc64) (void)hipFree(plan->pc64);
   if (plan->pc32) (void)hipFree(plan->pc32);

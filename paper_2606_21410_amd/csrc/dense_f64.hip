@@ -59,7 +59,6 @@ int dense_setup(cheb_plan* p) {
   }
   p->dd64 = nullptr;
   p->dd32 = nullptr;
-  p->dsink = nullptr;
   if (total == 0) return CHEB_OK;
   std::vector<double> h(total, 0.0);
   for (int a = 0; a < 3; ++a) {
@@ -76,7 +75,6 @@ int dense_setup(cheb_plan* p) {
   for (size_t i = 0; i < total; ++i) h32[i] = float(h[i]);
   int rc = hip_check(hipMalloc((void**)&p->dd64, total * sizeof(double)), "hipMalloc(matrix-core tables)");
   if (!rc) rc = hip_check(hipMalloc((void**)&p->dd32, total * sizeof(float)), "hipMalloc(matrix-core tables)");
-  if (!rc) rc = hip_check(hipMalloc(&p->dsink, 256), "hipMalloc(matrix-core sink)");
   if (!rc)
     rc = hip_check(hipMemcpy(p->dd64, h.data(), total * sizeof(double), hipMemcpyHostToDevice),
                    "hipMemcpy(matrix-core tables)");

@@ -77,7 +77,6 @@ static int launch_dense_common(const cheb_plan* p, int axis, int transpose, int 
   a.act = act;
   a.nact = nact;
   a.tab = dense_tab<T>(p, axis, transpose);
-  a.sink = (T*)p->dsink;
   const size_t slot0 = (size_t)(kConstSlots * axis) * p->dconst_stride;
   const size_t slotN = (size_t)(kConstSlots * axis + 1) * p->dconst_stride;
   if (sizeof(T) == sizeof(double)) {

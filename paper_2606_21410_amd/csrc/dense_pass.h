@@ -32,6 +32,18 @@ namespace cheb {
 
 enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1 };
 
+// element i of a system's field at base (uniform): a system's field stays
+// below 4 GiB (at most 129^3 nodes per axis triple), so the byte offset fits
+// 32 bits and the address is a scalar base plus one vector offset register
+template <typename T>
+__device__ __forceinline__ T dense_at(const T* base, int i) {
+  return *(const T*)((const char*)base + (unsigned)i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T& dense_ref(T* base, unsigned i) {
+  return *(T*)((char*)base + i * (unsigned)sizeof(T));
+}
+
 // lane move across a DPP pattern (quad permutation, half-row or row mirror)
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float x) {
@@ -151,7 +163,6 @@ struct DenseArgs {
   const T* tab;    // fragment table of D (reduced) or D^T (transpose)
   const T* drow0;  // face rows D[0][:], D[N][:] for the lift
   const T* drowN;
-  T* sink;         // one word that stores of off-tile elements go to
   int n[3];
   int axis, first, bcmask, npencils;  // bcmask of the single system
   // the face rows' 2 x 2 matrix M = [m00 m0N; mN0 mNN] of the lift: the
@@ -321,10 +332,10 @@ struct DenseArgs {
       ahi_[q] = b >= 0 ? b + (N - jp) * stride : 0;                   \
     }                                                                 \
     _Pragma("unroll") for (int q = 0; q < EPP; ++q) {                 \
-      UR[2 * q] = (PU)[alo_[q]];                                      \
-      UR[2 * q + 1] = (PU)[ahi_[q]];                                  \
-      KR[2 * q] = (PK)[alo_[q]];                                      \
-      KR[2 * q + 1] = (PK)[ahi_[q]];                                  \
+      UR[2 * q] = dense_at(PU, alo_[q]);                              \
+      UR[2 * q + 1] = dense_at(PU, ahi_[q]);                          \
+      KR[2 * q] = dense_at(PK, alo_[q]);                              \
+      KR[2 * q + 1] = dense_at(PK, ahi_[q]);                          \
     }                                                                 \
   } while (0)
 
@@ -553,7 +564,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   } while (0)
 #define DENSE_ISSUE2(KS)                                                           \
   do {                                                                             \
-    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = cy[DENSE_AD(slot, (KS) < EPT ? (KS) : 0)]; \
+    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = dense_at(cy, DENSE_AD(slot, (KS) < EPT ? (KS) : 0)); \
   } while (0)
 
     V4 acco, acce;
@@ -573,7 +584,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_GEMM(acco, acce, DENSE_ISSUE2);
 #pragma unroll
     for (int q = S.KE4; q < EPT; ++q)
-      if (!FIRST) yreg[q] = cy[DENSE_AD(slot, q)];
+      if (!FIRST) yreg[q] = dense_at(cy, DENSE_AD(slot, q));
     DENSE_VDOT(midv);
     DENSE_EPI(acco, acce, midv, false, false);  // into the K tile: no barrier needed before it
     __syncthreads();
@@ -598,10 +609,12 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     }
 
     // store: interior nodes (accumulated), the two end nodes (0); values
-    // first, then one unconditional store per element (off-tile ones to the sink)
+    // first, then one unconditional store per element.  Off-tile elements
+    // store 0 to the system's node 0, a corner, whose value in the reduced
+    // operator's output is 0.
     {
       T ov[EPT];
-      T* op[EPT];
+      unsigned op[EPT];
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * NT < TOT ? tid + q * NT : TOT - 1;
@@ -614,10 +627,11 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         if (MODE == DENSE_TRANSPOSE && (nlo || nhi)) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
         if (!FIRST) x += yreg[q];
         ov[q] = in ? x : T(0);
-        op[q] = ok ? cy + (b + j * stride) : a.sink;
+        op[q] = ok ? (unsigned)(b + j * stride) : 0u;
+        if (!ok) ov[q] = T(0);
       }
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) *op[q] = ov[q];
+      for (int q = 0; q < EPT; ++q) dense_ref(cy, op[q]) = ov[q];
     }
     if (PREF) {
 #pragma unroll

@@ -64,7 +64,6 @@ struct cheb_plan {
   int auto_fft[2];      // CHEB_ROUTE_AUTO resolved to the FFT route, [f64, f32] (autotuner)
   double* dd64;
   float* dd32;
-  void* dsink;  // 256 bytes that masked-off stores of the matrix-core pass land in
 };
 
 namespace cheb {
