@@ -21,7 +21,9 @@ recurrence here.  Everything is the plain definition, written out:
   interpolant) and the refinement indicator e_ref;
 * Clenshaw-Curtis volume averages and the effective conductivity (Section 3.3);
 * the adjoint of the reduced system and dL/dlog K;
-* Picard (lagged-coefficient) iteration for K = K0 (1 + u^2/2).
+* Picard (lagged-coefficient) iteration for K = K0 (1 + u^2/2);
+* Newton's method for k = K0 / (1 + alpha T) (Section 3.4): residual, the
+  reduced Jacobian action and the outer loop.
 
 Readings of the paper that this oracle fixes (edge/corner ownership, Neumann
 datum = outward du/dn, operator sign div(K grad u) = f, ascending node order)
@@ -675,3 +677,73 @@ def picard_closed_form_1d(x: np.ndarray, L: float = 1.0) -> np.ndarray:
     q = 3.0 * phi
     s = np.sqrt(q * q + 8.0)
     return np.cbrt(q + s) + np.cbrt(q - s)
+
+
+# -----------------------------------------------------------------------------
+# Newton iteration for k(x, T) = K0(x) / (1 + alpha T)  (Section 3.4)
+# -----------------------------------------------------------------------------
+
+def newton_conductivity(K0, alpha: float, T):
+    """k = K0 / (1 + alpha T) and its derivative in T, k' = -alpha K0 / (1 + alpha T)^2
+    (the reciprocal law of Section 3.4, alpha = 0.5 and K0 = 1 there)."""
+    d = 1.0 + alpha * T
+    return K0 / d, -alpha * K0 / (d * d)
+
+
+def newton_residual(G: Grid3, K0, alpha: float, T, f) -> np.ndarray:
+    """Interior rows of R(T) = sum_a D_a (k(T) D_a T) - f (Section 3.4 residual,
+    written for div(k grad T) = f); boundary entries 0.  T is a full state that
+    satisfies its boundary rows (T = lift(x, g)), so those rows have no residual."""
+    k, _ = newton_conductivity(K0, alpha, T)
+    r = interior_operator(G, k, T) - f
+    r[~G.interior] = 0.0
+    return r
+
+
+def newton_jacobian(G: Grid3, K0, alpha: float, T, v) -> np.ndarray:
+    """Action of the reduced Jacobian of newton_residual at T on interior values v
+    (Section 3.4 Jacobian action): with V = lift(v, 0),
+    sum_a D_a (k(T) D_a V + k'(T) V D_a T) on interior rows, 0 on boundary rows."""
+    k, dk = newton_conductivity(K0, alpha, T)
+    V = lift(G, np.where(G.interior, v, 0.0), None)
+    y = sum(deriv(G.D[a], k * deriv(G.D[a], V, a) + dk * V * deriv(G.D[a], T, a), a)
+            for a in range(3))
+    y[~G.interior] = 0.0
+    return y
+
+
+def newton(G: Grid3, K0, alpha: float, f, g, tol=1e-10, max_steps=50, U0=None, lin_tol=1e-13):
+    """Newton's method on the reduced system (Section 2.3 Newton form, Section 3.4):
+    T_m = lift(x_m, g); stop once ||R(T_m)|| <= tol ||R(T_0)||; otherwise solve
+    J(T_m) dx = -R(T_m) by GMRES (preconditioned by the constant-coefficient
+    inverse at the mean of k(T_m)) and set x_{m+1} = x_m + dx.
+    Returns (T, steps, gmres iterations per step)."""
+    K0 = np.broadcast_to(np.asarray(K0, dtype=np.float64), G.n)
+    x = np.zeros(G.n) if U0 is None else np.where(G.interior, U0, 0.0)
+    T = lift(G, x, g)
+    r0 = None
+    its = []
+    for step in range(max_steps + 1):
+        R = newton_residual(G, K0, alpha, T, f)
+        rn = float(np.linalg.norm(R))
+        if r0 is None:
+            r0 = rn
+        if rn <= tol * r0 or rn == 0.0 or step == max_steps:
+            return T, step, its
+        k, _ = newton_conductivity(K0, alpha, T)
+        if not np.all(k > 0):
+            raise ValueError("Newton iterate left the range where 1 + alpha T > 0")
+        fdm = FDM(G, float(np.mean(k)))
+        Tm = T
+
+        def mv(v):
+            return newton_jacobian(G, K0, alpha, Tm, v.reshape(G.n)).ravel()
+
+        def pc(v):
+            return fdm.solve(v.reshape(G.n)).ravel()
+
+        dx, it, _ = gmres(mv, (-R).ravel(), pc, tol=lin_tol)
+        its.append(it)
+        x = x + np.where(G.interior, dx.reshape(G.n), 0.0)
+        T = lift(G, x, g)
+    return T, max_steps, its

@@ -171,6 +171,37 @@ def manufactured_paper3d(n: int) -> Problem:
                    {"name": "paper-3d-poisson"})
 
 
+def thermal_nonlinear(n: int, alpha: float = 0.5) -> Problem:
+    """The nonlinear thermal example of Section 3.4 on (0,1)^3, written for
+    div(k(T) grad T) = f with k(T) = K0 / (1 + alpha T), K0 = 1:
+    Phi = sin(pi x) sin(pi y) sin(pi z), T = (exp(alpha Phi) - 1) / alpha, so
+    k(T) grad T = grad Phi and f = Laplacian(Phi) = -3 pi^2 Phi.  Dirichlet on
+    x=0 and y=0, Neumann (outward dT/dn) on x=1, y=1, z=0 and z=1.  Phi = 0 on
+    every face, so there T = 0, k = 1 and dT/dn equals the prescribed flux."""
+    grid = Grid((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
+                (DIRICHLET, NEUMANN, DIRICHLET, NEUMANN, NEUMANN, NEUMANN))
+    pi = math.pi
+
+    def phi(X, Y, Z):
+        return np.sin(pi * X) * np.sin(pi * Y) * np.sin(pi * Z)
+
+    def u(X, Y, Z):
+        return np.expm1(alpha * phi(X, Y, Z)) / alpha
+
+    def grad(X, Y, Z):
+        e = np.exp(alpha * phi(X, Y, Z))
+        sx, sy, sz = np.sin(pi * X), np.sin(pi * Y), np.sin(pi * Z)
+        return (e * pi * np.cos(pi * X) * sy * sz,
+                e * pi * sx * np.cos(pi * Y) * sz,
+                e * pi * sx * sy * np.cos(pi * Z))
+
+    X, Y, Z = grid.mesh()
+    ue = u(X, Y, Z)
+    f = -3.0 * pi * pi * phi(X, Y, Z)
+    return Problem(grid, np.ones_like(ue), f, _faces_from(grid, u, grad), ue,
+                   {"name": "thermal-nonlinear", "alpha": alpha})
+
+
 def manufactured_polynomial(n: int, bc, seed: int = 7, deg_u: int = 3,
                             lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Problem:
     """Random separable-sum polynomial u with polynomial K (degree 1); the

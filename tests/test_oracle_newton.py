@@ -1,0 +1,94 @@
+"""Pins of the oracle's Newton iteration (Section 3.4) against facts that do not
+come from the oracle's own formulas: a central finite difference of the
+residual, the linear solve it must reduce to at alpha = 0, the analytic
+temperature of the manufactured problem and the errors Table 1 prints for it.
+"""
+import numpy as np
+import pytest
+
+from oracle import cheb_oracle as O
+from paper_2606_21410_amd import workloads as W
+
+D_, N_ = O.DIRICHLET, O.NEUMANN
+
+
+def grid_of(P):
+    return O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+
+
+@pytest.mark.parametrize("n,bc", [((5, 5, 5), (D_, N_, D_, N_, N_, N_)),
+                                  ((6, 5, 7), (N_, D_, N_, N_, D_, N_)),
+                                  ((9, 9, 9), (D_, D_, N_, N_, N_, N_))])
+def test_jacobian_matches_central_difference(n, bc):
+    """J v against (R(lift(x + e v)) - R(lift(x - e v))) / 2e on a random state:
+    a dropped k' term, a wrong sign or an un-lifted direction fails this."""
+    rng = np.random.default_rng(11)
+    G = O.Grid3(n, bc=bc)
+    K0 = W.random_conductivity(n, 12)
+    g = W.random_faces(W.Grid(G.n, G.lo, G.hi, G.bc), 13) * 0.2
+    f = rng.standard_normal(n)
+    x = np.where(G.interior, 0.3 * rng.standard_normal(n), 0.0)
+    v = np.where(G.interior, rng.standard_normal(n), 0.0)
+    alpha = 0.5
+    J = O.newton_jacobian(G, K0, alpha, O.lift(G, x, g), v)
+    e = 1e-5
+    rp = O.newton_residual(G, K0, alpha, O.lift(G, x + e * v, g), f)
+    rm = O.newton_residual(G, K0, alpha, O.lift(G, x - e * v, g), f)
+    fd = (rp - rm) / (2 * e)
+    assert np.linalg.norm(J - fd) <= 1e-8 * np.linalg.norm(fd)
+    # the k' term is not negligible on this state, so the check has teeth
+    J0 = O.apply_reduced(G, O.newton_conductivity(K0, alpha, O.lift(G, x, g))[0], v)
+    assert np.linalg.norm(J0 - fd) > 1e-2 * np.linalg.norm(fd)
+
+
+def test_alpha_zero_is_the_linear_solve():
+    """alpha = 0 makes k = K0 constant in T: one Newton step from T = lift(0, g)
+    solves the linear collocation system exactly (dense LU reference)."""
+    P = W.manufactured_polynomial(7, (D_, N_, D_, D_, N_, N_), seed=3)
+    G = grid_of(P)
+    K0 = W.random_conductivity(G.n, 4)
+    T, steps, its = O.newton(G, K0, 0.0, P.f, P.g, tol=1e-12)
+    U = O.solve_dense(G, K0, P.f, P.g)
+    assert steps == 1 or np.linalg.norm(O.newton_residual(G, K0, 0.0, T, P.f)) < 1e-9
+    np.testing.assert_allclose(T, U, atol=1e-10 * np.abs(U).max())
+
+
+def test_thermal_manufactured_against_table1():
+    """Section 3.4 problem: the discrete solution converges spectrally to the
+    analytic T, and the max errors at N = 8 and N = 16 are within a factor 2
+    of the ones Table 1 prints (4.903119e-4 and 6.270730e-9; the paper's flux
+    form of the Neumann rows differs from the dT/dn rows here, which moves the
+    digits but not the size)."""
+    err = {}
+    for N in (8, 16, 24):
+        P = W.thermal_nonlinear(N + 1)
+        G = grid_of(P)
+        T, steps, its = O.newton(G, P.K, P.meta["alpha"], P.f, P.g, tol=1e-12)
+        assert steps <= 8
+        err[N] = float(np.max(np.abs(T - P.u_exact)))
+    assert 0.5 * 4.903119e-4 <= err[8] <= 2.0 * 4.903119e-4
+    assert 0.5 * 6.270730e-9 <= err[16] <= 2.0 * 6.270730e-9
+    assert err[24] < 1e-2 * err[16]
+
+
+def test_newton_converges_quadratically():
+    """Residual norms of the Section 3.4 problem at N = 16 fall quadratically
+    once close: r_{m+1} <= C r_m^2 with a modest C."""
+    P = W.thermal_nonlinear(17)
+    G = grid_of(P)
+    alpha = P.meta["alpha"]
+    rs = []
+    x = np.zeros(G.n)
+    for _ in range(5):
+        T = O.lift(G, x, P.g)
+        R = O.newton_residual(G, P.K, alpha, T, P.f)
+        rs.append(float(np.linalg.norm(R)))
+        k, _ = O.newton_conductivity(P.K, alpha, T)
+        fdm = O.FDM(G, float(np.mean(k)))
+        dx, _, _ = O.gmres(lambda v: O.newton_jacobian(G, P.K, alpha, T, v.reshape(G.n)).ravel(),
+                           (-R).ravel(), lambda v: fdm.solve(v.reshape(G.n)).ravel(), tol=1e-14)
+        x = x + np.where(G.interior, dx.reshape(G.n), 0.0)
+    # r_{m+1} / r_m^2 stays put over two steps (a linear rate would leave
+    # rs[4] / rs[3] near rs[3] / rs[2] = 2e-3 instead)
+    c = rs[3] / rs[2] ** 2
+    assert rs[4] <= 4.0 * c * rs[3] ** 2 and rs[4] < 1e-4 * rs[3]
