@@ -218,6 +218,52 @@ int cheb_picard(cheb_plan* plan, const void* K0, const void* f, const void* g_fa
                 void* Kwork, double picard_tol, int32_t max_steps, const cheb_solve_opts* opts,
                 cheb_solve_info* info, int32_t* steps);
 
+/* Newton iteration for the conductivity law k(x, T) = K0(x) / (1 + alpha T)
+ * (Section 3.4, reciprocal law, with alpha = 0.5 and K0 = 1 in the paper's
+ * example; Section 2.3, Newton form).  All arrays are FP64 fields of the plan's
+ * grid except g_faces (packed face data as in cheb_solve).  FP64 or MIXED plans
+ * only (CHEB_ERR_UNSUPPORTED otherwise); the linear solves run in FP64.
+ *
+ * work: caller device buffer of cheb_newton_work_bytes() bytes, 256-byte
+ * aligned, holding k(T), c_a = k'(T) D_a T (a = 0, 1, 2) and three scratch
+ * fields; its contents are not kept between calls.  Every call fails with
+ * CHEB_ERR_BAD_INPUT when k(T) is not finite and positive at some node
+ * (1 + alpha T <= 0, or K0 <= 0). */
+int cheb_newton_work_bytes(const cheb_plan* plan, size_t* bytes);
+
+/* r = R(T) = sum_a D_a (k(T) D_a T) - f on interior nodes, 0 on boundary nodes
+ * (the Section 3.4 residual, written for div(k grad T) = f).  T is a full
+ * nodal state; its boundary rows are taken as satisfied.  Synchronises. */
+int cheb_newton_residual(cheb_plan* plan, const void* K0, double alpha, const void* T, const void* f, void* r,
+                         void* work);
+
+/* y = J(T) v, the reduced Jacobian of cheb_newton_residual at T applied to the
+ * interior values of v (boundary values of v are ignored): with V the
+ * homogeneous lift of v (Section 2.3.1),
+ *   y = sum_a D_a (k(T) D_a V + k'(T) V D_a T)   on interior nodes, 0 elsewhere
+ * (the Jacobian action of Section 3.4).  Synchronises. */
+int cheb_newton_jacobian(cheb_plan* plan, const void* K0, double alpha, const void* T, const void* v, void* y,
+                         void* work);
+
+/* Newton-LGMRES solve of div(k(T) grad T) = f with the boundary rows of
+ * cheb_solve (Dirichlet values; Neumann outward dT/dn).  The state is
+ * T_m = lift(x_m, g).  The scale is r_ref = ||R(lift(0, g))||, the residual of
+ * the cold start, also when a warm start is given.  The iteration stops once
+ * ||R(T_m)|| <= newton_tol r_ref (CHEB_OK) or after max_steps updates
+ * (CHEB_NOT_CONVERGED); otherwise it solves J(T_m) dx = -R(T_m) by LGMRES to
+ * max(opts->rtol ||R(T_m)||, opts->atol, newton_tol r_ref / 10) (an inexact
+ * Newton step; fast-diagonalisation preconditioner at the mean of k(T_m) when
+ * bit 1 of opts->flags is set) and sets x_{m+1} = x_m + dx.  u_inout: initial
+ * state when bit 0 of opts->flags is set (its interior values are used), else
+ * T_0 = lift(0, g); receives the final full state.  opts->history, if given,
+ * receives ||R(T_m)|| / r_ref for m = 0, 1, ...  *steps receives the number of
+ * updates; mv_per_step (host, max_steps entries, may be NULL) the LGMRES
+ * matrix-vector products of each.  Needs the plan workspace of
+ * cheb_plan_workspace_bytes(opts).  Synchronises. */
+int cheb_newton(cheb_plan* plan, const void* K0, double alpha, const void* f, const void* g_faces, void* u_inout,
+                void* work, double newton_tol, int32_t max_steps, const cheb_solve_opts* opts,
+                cheb_solve_info* info, int32_t* steps, int32_t* mv_per_step);
+
 /* Derivative along one axis, D_a u at every node (first half of an axis pass).
  * Asynchronous. */
 int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis);

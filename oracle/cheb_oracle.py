@@ -714,21 +714,21 @@ def newton_jacobian(G: Grid3, K0, alpha: float, T, v) -> np.ndarray:
 
 def newton(G: Grid3, K0, alpha: float, f, g, tol=1e-10, max_steps=50, U0=None, lin_tol=1e-13):
     """Newton's method on the reduced system (Section 2.3 Newton form, Section 3.4):
-    T_m = lift(x_m, g); stop once ||R(T_m)|| <= tol ||R(T_0)||; otherwise solve
-    J(T_m) dx = -R(T_m) by GMRES (preconditioned by the constant-coefficient
-    inverse at the mean of k(T_m)) and set x_{m+1} = x_m + dx.
+    T_m = lift(x_m, g); stop once ||R(T_m)|| <= tol r_ref, r_ref = ||R(lift(0, g))||
+    (the paper states no stopping rule; this one judges warm and cold starts on
+    the same scale); otherwise solve J(T_m) dx = -R(T_m) by GMRES (preconditioned
+    by the constant-coefficient inverse at the mean of k(T_m)) to a relative
+    residual max(lin_tol, tol r_ref / (10 ||R(T_m)||)) and set x_{m+1} = x_m + dx.
     Returns (T, steps, gmres iterations per step)."""
     K0 = np.broadcast_to(np.asarray(K0, dtype=np.float64), G.n)
+    rref = float(np.linalg.norm(newton_residual(G, K0, alpha, lift(G, np.zeros(G.n), g), f)))
     x = np.zeros(G.n) if U0 is None else np.where(G.interior, U0, 0.0)
     T = lift(G, x, g)
-    r0 = None
     its = []
     for step in range(max_steps + 1):
         R = newton_residual(G, K0, alpha, T, f)
         rn = float(np.linalg.norm(R))
-        if r0 is None:
-            r0 = rn
-        if rn <= tol * r0 or rn == 0.0 or step == max_steps:
+        if rn <= tol * rref or step == max_steps:
             return T, step, its
         k, _ = newton_conductivity(K0, alpha, T)
         if not np.all(k > 0):
@@ -742,7 +742,7 @@ def newton(G: Grid3, K0, alpha: float, f, g, tol=1e-10, max_steps=50, U0=None, l
         def pc(v):
             return fdm.solve(v.reshape(G.n)).ravel()
 
-        dx, it, _ = gmres(mv, (-R).ravel(), pc, tol=lin_tol)
+        dx, it, _ = gmres(mv, (-R).ravel(), pc, tol=max(lin_tol, 0.1 * tol * rref / rn))
         its.append(it)
         x = x + np.where(G.interior, dx.reshape(G.n), 0.0)
         T = lift(G, x, g)

@@ -73,6 +73,13 @@ _SIGS = {
     "cheb_picard": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                    ctypes.POINTER(cheb_solve_opts), ctypes.POINTER(cheb_solve_info),
                                    ctypes.POINTER(ctypes.c_int32)]),
+    "cheb_newton_work_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "cheb_newton_residual": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]),
+    "cheb_newton_jacobian": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]),
+    "cheb_newton": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_double,
+                                   ctypes.c_int32, ctypes.POINTER(cheb_solve_opts),
+                                   ctypes.POINTER(cheb_solve_info), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]),
     "cheb_derivative": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "cheb_flux_average": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "cheb_debug_gemm": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,

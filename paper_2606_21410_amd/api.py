@@ -250,6 +250,60 @@ class Plan:
             d["history"] = [hist[i] for i in range(min(steps.value, opts.history_len))]
         return u, d
 
+    def _newton_work(self):
+        b = ctypes.c_size_t()
+        L.check(self.lib.cheb_newton_work_bytes(self._h, ctypes.byref(b)))
+        if getattr(self, "_nwork", None) is None or self._nwork.numel() < b.value:
+            self._nwork = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        return ctypes.c_void_p(self._nwork.data_ptr())
+
+    def newton_residual(self, K0, T, f, alpha=0.5, out=None):
+        """R(T) = sum_a D_a (k(T) D_a T) - f on interior rows, k = K0 / (1 + alpha T)."""
+        self._sync_stream()
+        f64 = torch.float64
+        r = out if out is not None else torch.empty(self.n, dtype=f64, device=self.device)
+        L.check(self.lib.cheb_newton_residual(self._h, self._field(K0, "K0", f64), float(alpha),
+                                              self._field(T, "T", f64), self._field(f, "f", f64),
+                                              self._field(r, "r", f64), self._newton_work()))
+        return r
+
+    def newton_jacobian(self, K0, T, v, alpha=0.5, out=None):
+        """Reduced Jacobian action J(T) v of newton_residual (interior rows)."""
+        self._sync_stream()
+        f64 = torch.float64
+        y = out if out is not None else torch.empty(self.n, dtype=f64, device=self.device)
+        L.check(self.lib.cheb_newton_jacobian(self._h, self._field(K0, "K0", f64), float(alpha),
+                                              self._field(T, "T", f64), self._field(v, "v", f64),
+                                              self._field(y, "y", f64), self._newton_work()))
+        return y
+
+    def newton(self, K0, f, g, alpha=0.5, u0=None, tol=1e-10, max_steps=30,
+               opts: SolveOptions | None = None):
+        """Newton-LGMRES for div(k(T) grad T) = f, k = K0 / (1 + alpha T)."""
+        opts = opts or SolveOptions()
+        self._sync_stream()
+        self.ensure_workspace(opts)
+        f64 = torch.float64
+        u = torch.zeros(self.n, dtype=f64, device=self.device)
+        if u0 is not None:
+            u.copy_(u0)
+        o, hist = opts.to_c(u0 is not None)
+        info = L.cheb_solve_info()
+        steps = ctypes.c_int32()
+        mv = (ctypes.c_int32 * max(int(max_steps), 1))()
+        rc = L.check(self.lib.cheb_newton(self._h, self._field(K0, "K0", f64), float(alpha),
+                                          self._field(f, "f", f64), ctypes.c_void_p(g.data_ptr()),
+                                          self._field(u, "u", f64), self._newton_work(), float(tol),
+                                          int(max_steps), ctypes.byref(o), ctypes.byref(info),
+                                          ctypes.byref(steps), mv))
+        d = info.as_dict()
+        d["rc"] = rc
+        d["newton_steps"] = steps.value
+        d["mv_per_step"] = [mv[i] for i in range(steps.value)]
+        if hist is not None:
+            d["history"] = [hist[i] for i in range(min(steps.value + 1, opts.history_len))]
+        return u, d
+
     def flux_average(self, K, u):
         self._sync_stream()
         self.ensure_workspace()

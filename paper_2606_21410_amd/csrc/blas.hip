@@ -212,6 +212,23 @@ __global__ void k_picard_coeff(double* K, const double* K0, const double* u, siz
   }
 }
 
+// reciprocal law of the nonlinear example: k = K0 / (1 + alpha T) and
+// k' = -alpha K0 / (1 + alpha T)^2 = -alpha k / (1 + alpha T)
+__global__ void k_newton_coeff(double* k, double* kp, const double* K0, const double* T, double alpha,
+                               size_t npts) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (size_t)gridDim.x * blockDim.x) {
+    const double d = 1.0 + alpha * T[i];
+    const double kv = K0[i] / d;
+    k[i] = kv;
+    kp[i] = -alpha * kv / d;
+  }
+}
+
+__global__ void k_vmul(double* y, const double* a, const double* b, size_t npts) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a[i] * b[i];
+}
+
 __global__ void k_grad_acc(double* g, const double* du, const double* dl, int first, size_t npts) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (size_t)gridDim.x * blockDim.x)
     g[i] = (first ? 0.0 : g[i]) + du[i] * dl[i];
@@ -374,6 +391,17 @@ int mask_interior(T* y, const int* n, hipStream_t s) {
 int picard_coeff(double* K, const double* K0, const double* u, size_t npts, hipStream_t s) {
   hipLaunchKernelGGL(k_picard_coeff, dim3(grid_for(npts)), dim3(kThreads), 0, s, K, K0, u, npts);
   return hip_check(hipGetLastError(), "picard_coeff");
+}
+
+int newton_coeff(double* k, double* kp, const double* K0, const double* T, double alpha, size_t npts,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_newton_coeff, dim3(grid_for(npts)), dim3(kThreads), 0, s, k, kp, K0, T, alpha, npts);
+  return hip_check(hipGetLastError(), "newton_coeff");
+}
+
+int vmul(double* y, const double* a, const double* b, size_t npts, hipStream_t s) {
+  hipLaunchKernelGGL(k_vmul, dim3(grid_for(npts)), dim3(kThreads), 0, s, y, a, b, npts);
+  return hip_check(hipGetLastError(), "vmul");
 }
 
 int grad_accumulate(double* g, const double* du, const double* dl, int first, size_t npts, hipStream_t s) {

@@ -137,6 +137,10 @@ template <typename T>
 int mask_interior(T* y, const int* n, hipStream_t s);
 // K-dependent pointwise kernels
 int picard_coeff(double* K, const double* K0, const double* u, size_t npts, hipStream_t s);
+// k = K0 / (1 + alpha T), kp = dk/dT
+int newton_coeff(double* k, double* kp, const double* K0, const double* T, double alpha, size_t npts,
+                 hipStream_t s);
+int vmul(double* y, const double* a, const double* b, size_t npts, hipStream_t s);  // y = a * b (y may alias)
 int grad_accumulate(double* g, const double* du, const double* dl, int first, size_t npts,
                     hipStream_t s);
 int grad_finish(double* g, const double* K, size_t npts, hipStream_t s);

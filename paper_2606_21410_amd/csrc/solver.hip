@@ -455,6 +455,84 @@ int solve_plain(cheb_plan* p, const T* K, const T* bt, T* x, T* r, KrylovWS<T>& 
   return CHEB_OK;
 }
 
+
+// Newton iteration for k(x, T) = K0(x) / (1 + alpha T) (Section 3.4).  Fields of
+// the caller's work array, each padded to 256 bytes: k(T), c_a = k'(T) D_a T for
+// a = 0, 1, 2, three scratch fields (lifted direction, product, derivative) and
+// a 256-byte flag slot.
+constexpr int kNewtonFields = 7;
+
+struct NewtonWS {
+  double *k, *c[3], *V, *tw, *td;
+  int* flag;
+};
+
+NewtonWS newton_ws(const cheb_plan* p, void* work) {
+  Carver c{(char*)work, 0};
+  NewtonWS w;
+  w.k = c.take<double>(p->npts);
+  for (int a = 0; a < 3; ++a) w.c[a] = c.take<double>(p->npts);
+  w.V = c.take<double>(p->npts);
+  w.tw = c.take<double>(p->npts);
+  w.td = c.take<double>(p->npts);
+  w.flag = c.take<int>(64);
+  return w;
+}
+
+// k and c_a at the state T (full nodal array); fails when 1 + alpha T <= 0
+// somewhere, where the law has no positive conductivity.
+int newton_linearise(cheb_plan* p, const double* K0, double alpha, const double* T, NewtonWS& w) {
+  int rc = newton_coeff(w.k, w.V, K0, T, alpha, p->npts, p->stream);
+  for (int a = 0; a < 3 && !rc; ++a) {
+    rc = launch_axis_pass<double>(p, a, 3, 1, nullptr, T, w.c[a], p->stream);
+    if (!rc) rc = vmul(w.c[a], w.c[a], w.V, p->npts, p->stream);
+  }
+  if (!rc) rc = hip_check(hipMemsetAsync(w.flag, 0, sizeof(int), p->stream), "hipMemsetAsync");
+  if (!rc) rc = check_positive_finite(w.k, p->npts, w.flag, p->stream);
+  if (rc) return rc;
+  int* hf = (int*)(p->hpinned + 3 * 256);
+  rc = hip_check(hipMemcpyAsync(hf, w.flag, sizeof(int), hipMemcpyDeviceToHost, p->stream), "hipMemcpyAsync");
+  if (!rc) rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (*hf) {
+    set_error("k(T) = K0 / (1 + alpha T) must be finite and positive at every node (check K0 and 1 + alpha T)");
+    return CHEB_ERR_BAD_INPUT;
+  }
+  return CHEB_OK;
+}
+
+// y = J(T) v on interior rows (boundary rows 0): the reduced operator with
+// coefficient k(T), plus sum_a D_a (c_a V) with V the homogeneous lift of v.
+int newton_jv(cheb_plan* p, NewtonWS& w, const double* v, double* y) {
+  hipStream_t s = p->stream;
+  int rc = apply_t<double>(p, w.k, v, y, 1, s);
+  if (!rc) rc = copy_scale<double>(w.V, v, 1.0, p->npts, s);
+  if (!rc) rc = mask_interior<double>(w.V, p->g.n, s);
+  if (!rc) rc = lift_full<double>(p, w.V, nullptr, s);
+  for (int a = 0; a < 3 && !rc; ++a) {
+    rc = vmul(w.tw, w.c[a], w.V, p->npts, s);
+    if (!rc) rc = launch_axis_pass<double>(p, a, 3, 1, nullptr, w.tw, w.td, s);
+    if (!rc) rc = axpby<double>(y, w.td, 1.0, 1.0, p->npts, s);
+  }
+  if (!rc) rc = mask_interior<double>(y, p->g.n, s);
+  return rc;
+}
+
+// out = -R(T) = f - sum_a D_a (k D_a T) on interior rows, 0 on boundary rows
+int newton_neg_residual(cheb_plan* p, NewtonWS& w, const double* T, const double* f, double* out) {
+  int rc = apply_t<double>(p, w.k, T, out, 0, p->stream);
+  if (!rc) rc = rhs_reduced<double>(out, f, p->g.n, p->stream);
+  return rc;
+}
+
+int newton_check_plan(const cheb_plan* p) {
+  if (p->prec == CHEB_F32) {
+    set_error("Newton needs an FP64 or MIXED plan");
+    return CHEB_ERR_UNSUPPORTED;
+  }
+  return CHEB_OK;
+}
+
 }  // namespace
 }  // namespace cheb
 
@@ -762,6 +840,139 @@ int cheb_picard(cheb_plan* plan, const void* K0, const void* f, const void* g_fa
   tot.status = status;
   tot.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   tot.history_used = nsteps < sp.hist_len ? nsteps : sp.hist_len;
+  if (info) *info = tot;
+  return status;
+}
+
+int cheb_newton_work_bytes(const cheb_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  *bytes = kNewtonFields * field_bytes(plan->npts, sizeof(double)) + 256;
+  return CHEB_OK;
+}
+
+int cheb_newton_residual(cheb_plan* plan, const void* K0, double alpha, const void* T, const void* f, void* r,
+                         void* work) {
+  if (!plan || !K0 || !T || !f || !r || !work) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  int rc = newton_check_plan(plan);
+  if (rc) return rc;
+  cheb_plan* p = plan;
+  NewtonWS w = newton_ws(p, work);
+  rc = newton_linearise(p, (const double*)K0, alpha, (const double*)T, w);
+  if (!rc) rc = newton_neg_residual(p, w, (const double*)T, (const double*)f, (double*)r);
+  if (!rc) rc = copy_scale<double>((double*)r, (const double*)r, -1.0, p->npts, p->stream);
+  if (!rc) rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  return rc;
+}
+
+int cheb_newton_jacobian(cheb_plan* plan, const void* K0, double alpha, const void* T, const void* v, void* y,
+                         void* work) {
+  if (!plan || !K0 || !T || !v || !y || !work) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  int rc = newton_check_plan(plan);
+  if (rc) return rc;
+  cheb_plan* p = plan;
+  NewtonWS w = newton_ws(p, work);
+  rc = newton_linearise(p, (const double*)K0, alpha, (const double*)T, w);
+  if (!rc) rc = newton_jv(p, w, (const double*)v, (double*)y);
+  if (!rc) rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  return rc;
+}
+
+int cheb_newton(cheb_plan* plan, const void* K0, double alpha, const void* f, const void* g_faces, void* u_inout,
+                void* work, double newton_tol, int32_t max_steps, const cheb_solve_opts* opts,
+                cheb_solve_info* info, int32_t* steps, int32_t* mv_per_step) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!plan || !K0 || !f || !g_faces || !u_inout || !work || max_steps < 0 || !(newton_tol >= 0.0)) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  int rc = newton_check_plan(plan);
+  if (rc) return rc;
+  cheb_plan* p = plan;
+  const SolveParams sp = params_from(opts);
+  if (sp.m < 1 || sp.m > 64 || sp.k < 0 || sp.k > 6) {
+    set_error("inner_m must be in [1, 64] and outer_k in [0, 6]");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  SolveWS64 w64;
+  const size_t need = carve64(p, sp, nullptr, w64);
+  if (!p->ws || p->ws_bytes < need) {
+    set_error("workspace missing or too small (see cheb_plan_workspace_bytes)");
+    return CHEB_ERR_WORKSPACE;
+  }
+  carve64(p, sp, (char*)p->ws, w64);
+  NewtonWS w = newton_ws(p, work);
+  double* T = (double*)u_inout;
+  hipStream_t s = p->stream;
+  // reference scale: the residual of the cold start lift(0, g), whatever the
+  // initial state, so that a warm start is judged on the same scale
+  double rref = 0.0, rn = 0.0;
+  int rc2 = fill<double>(w64.r, 0.0, p->npts, s);
+  if (!rc2) rc2 = lift_full<double>(p, w64.r, (const double*)g_faces, s);
+  if (!rc2) rc2 = newton_linearise(p, (const double*)K0, alpha, w64.r, w);
+  if (!rc2) rc2 = newton_neg_residual(p, w, w64.r, (const double*)f, w64.bt);
+  if (!rc2) rc2 = vnorm<double>(p, w64.bt, w64.sc, &rref);
+  if (rc2) return rc2;
+  if (!sp.warm) rc = copy_scale<double>(T, w64.r, 1.0, p->npts, s);
+  else rc = lift_full<double>(p, T, (const double*)g_faces, s);
+  if (!rc && sp.precond) rc = precond_setup(p);
+  cheb_solve_info tot{};
+  int status = CHEB_NOT_CONVERGED;
+  int nsteps = 0;
+  const double stop = newton_tol * rref;
+  for (int m = 0; !rc; ++m) {
+    rc = newton_linearise(p, (const double*)K0, alpha, T, w);
+    if (!rc) rc = newton_neg_residual(p, w, T, (const double*)f, w64.bt);
+    if (!rc) rc = vnorm<double>(p, w64.bt, w64.sc, &rn);
+    if (rc) break;
+    if (sp.hist && m < sp.hist_len) sp.hist[m] = rref > 0 ? rn / rref : 0.0;
+    tot.history_used = m + 1 < sp.hist_len ? m + 1 : sp.hist_len;
+    if (!(rn > stop)) {
+      status = CHEB_OK;
+      break;
+    }
+    if (m >= max_steps) break;
+    double kc = 1.0;
+    if (sp.precond) rc = mean_K<double>(p, w.k, w64.sc, &kc);
+    if (!rc) rc = fill<double>(w64.x, 0.0, p->npts, s);
+    if (rc) break;
+    auto J = [&](const double* in, double* out) { return newton_jv(p, w, in, out); };
+    auto Mi = [&](const double* in, double* out) {
+      return precond_apply<double>(p, in, out, w64.kw.pa, w64.kw.pb, kc, false, s);
+    };
+    Stats st;
+    double res = 0.0;
+    // inexact Newton: the correction need not be more accurate than a tenth of
+    // the outer target
+    const double tol_lin = std::fmax(std::fmax(sp.rtol * rn, sp.atol), 0.1 * stop);
+    const int r2 = lgmres<double>(p, J, w64.bt, w64.x, true, tol_lin, sp.maxiter, w64.kw,
+                                  w64.sc, st, &res, rn, nullptr, 0, 0.0, sp.precond, Mi);
+    if (r2 < 0) {
+      rc = r2;
+      break;
+    }
+    if (mv_per_step) mv_per_step[m] = st.matvecs;
+    tot.matvecs += st.matvecs;
+    tot.restarts += st.restarts;
+    nsteps++;
+    rc = mask_interior<double>(w64.x, p->g.n, s);
+    if (!rc) rc = axpby<double>(T, w64.x, 1.0, 1.0, p->npts, s);
+    if (!rc) rc = lift_full<double>(p, T, (const double*)g_faces, s);
+  }
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (steps) *steps = nsteps;
+  tot.status = status;
+  tot.relres_final = rref > 0 ? rn / rref : 0.0;
+  tot.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = tot;
   return status;
 }
