@@ -318,6 +318,47 @@ def picard_chain_section(dev, levels=(33, 65, 129, 257)):
     return out
 
 
+def thermal_newton_section(dev, levels=(8, 16, 32, 64, 128, 256), tol=1e-11, max_steps=20, maxiter=2000):
+    """Section 3.4 nonlinear thermal problem, k(T) = 1 / (1 + T/2) on (0,1)^3
+    with the analytic T = (exp(Phi/2) - 1) * 2, Phi = sin(pi x) sin(pi y) sin(pi z):
+    Newton-LGMRES (FP64, fast-diagonalisation preconditioner) along the chain
+    N = 8 -> 16 -> ... -> 256 with the modal prolongation as warm start.  Per
+    level: Newton updates, LGMRES products (total and per update), max error
+    against the analytic T, e_ref and the time of prolongation + Newton
+    (inputs already on the GPU)."""
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan, SolveOptions, prolong
+    opts = SolveOptions(rtol=1e-10, maxiter=maxiter, precond=True)
+    out = []
+    prev = None
+    for N in levels:
+        P = W.thermal_nonlinear(N + 1)
+        K0 = torch.from_numpy(P.K).to(dev)
+        f = torch.from_numpy(P.f).to(dev)
+        g = torch.from_numpy(P.g).to(dev)
+        plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev)
+        plan.ensure_workspace(opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u0 = prolong(prev[0], plan, prev[1])[0] if prev else None
+        u, info = plan.newton(K0, f, g, alpha=P.meta["alpha"], u0=u0, tol=tol, max_steps=max_steps,
+                              opts=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        err = float((u - torch.from_numpy(P.u_exact).to(dev)).abs().max().item())
+        rec = {"N": N, "newton_steps": info["newton_steps"], "lgmres_total": sum(info["mv_per_step"]),
+               "lgmres_per_step": info["mv_per_step"], "max_error": err, "seconds": round(el, 4),
+               "status": info["rc"]}
+        if prev:
+            rec["e_ref"] = prolong(prev[0], plan, prev[1], uf_solved=u)[1]
+        _log(f"thermal newton {rec}")
+        out.append(rec)
+        prev = (plan, u)
+        del K0, f, g
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,6 +528,11 @@ def main():
         _log("spherical inclusion, contrast sweep 1e-4 .. 1e4")
         inclusion = inclusion_section(dev)
 
+    thermal = None
+    if not args.no_solve and n == 129:
+        _log("nonlinear thermal problem, Newton-LGMRES chain N = 8 .. 256")
+        thermal = thermal_newton_section(dev)
+
     batch = None
     if not args.no_batch and not args.profile_apply:
         _log("batched homogenisation (32 microstructures x 3 load cases)")
@@ -522,6 +568,7 @@ def main():
         "homogenisation_batch": batch,
         "picard_chain": chain,
         "inclusion_contrast_sweep": inclusion,
+        "thermal_newton_chain": thermal,
     }
     print(json.dumps(out), flush=True)
 
