@@ -93,11 +93,15 @@ def deriv_t(D: np.ndarray, U: np.ndarray, axis: int) -> np.ndarray:
 class Grid3:
     """Tensor CGL grid with per-face boundary types (x_lo, x_hi, y_lo, y_hi, z_lo, z_hi)."""
 
-    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(DIRICHLET,) * 6):
+    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(DIRICHLET,) * 6, robin=None):
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)
         self.bc = tuple(int(v) for v in bc)
+        # sigma of the row du/dn + sigma u = g on each Neumann face (0: plain Neumann)
+        self.robin = tuple(float(v) for v in (robin if robin is not None else (0.0,) * 6))
+        if any(self.robin[f] != 0.0 and self.bc[f] == DIRICHLET for f in range(6)):
+            raise ValueError("a Robin coefficient needs a Neumann face")
         if any(v < 3 for v in self.n):
             raise ValueError("at least 3 nodes per axis")
         self.D = [diff_matrix(self.n[a] - 1, self.lo[a], self.hi[a]) for a in range(3)]
@@ -158,9 +162,21 @@ def interior_operator(G: Grid3, K: np.ndarray, U: np.ndarray) -> np.ndarray:
     return sum(deriv(G.D[a], K * deriv(G.D[a], U, a), a) for a in range(3))
 
 
+def end_block(G: Grid3, a: int):
+    """Coefficients of the two end values in the boundary rows of a pencil along
+    axis a, written as  m00 U_0 + m0N U_N = -g_lo - s_0,  mN0 U_0 + mNN U_N = g_hi - s_N
+    with s the rows' sums over the inner nodes.  The lo row is
+    -(D U)_0 + sigma_lo U_0 = g_lo, the hi row (D U)_N + sigma_hi U_N = g_hi
+    (the general linear row a u + b du/dn = g of Section 2.3.1 with b != 0,
+    divided by b; sigma = 0 is the Neumann row)."""
+    D = G.D[a]
+    N = G.n[a] - 1
+    return (D[0, 0] - G.robin[2 * a], D[0, N], D[N, 0], D[N, N] + G.robin[2 * a + 1])
+
+
 def bc_rows(G: Grid3, U: np.ndarray) -> np.ndarray:
-    """Value of each node's boundary row: U (Dirichlet) or outward du/dn
-    (Neumann: -D_a U on the lo face, +D_a U on the hi face).  Interior: 0."""
+    """Value of each node's boundary row: U (Dirichlet) or outward du/dn + sigma U
+    (Neumann/Robin: -D_a U on the lo face, +D_a U on the hi face).  Interior: 0."""
     y = np.zeros_like(U)
     for f in range(6):
         a, side = divmod(f, 2)
@@ -171,7 +187,7 @@ def bc_rows(G: Grid3, U: np.ndarray) -> np.ndarray:
             y[m] = U[m]
         else:
             d = deriv(G.D[a], U, a)
-            y[m] = (d if side == 1 else -d)[m]
+            y[m] = (d if side == 1 else -d)[m] + G.robin[f] * U[m]
     return y
 
 
@@ -230,20 +246,21 @@ def lift(G: Grid3, x: np.ndarray, g=None) -> np.ndarray:
         both = nlo & nhi
         lo_only = nlo & ~nhi
         hi_only = nhi & ~nlo
+        m00, m0N, mN0, mNN = end_block(G, a)
         if both.any():
             s0 = inner[both] @ D[0, 1:N]
             sN = inner[both] @ D[N, 1:N]
-            M = np.array([[D[0, 0], D[0, N]], [D[N, 0], D[N, N]]])
+            M = np.array([[m00, m0N], [mN0, mNN]])
             rhs = np.stack([-glo[both] - s0, ghi[both] - sN])
             sol = np.linalg.solve(M, rhs)
             Um[..., 0][both] = sol[0]
             Um[..., N][both] = sol[1]
         if lo_only.any():
             s0 = Um[lo_only][:, 1:] @ D[0, 1:]
-            Um[..., 0][lo_only] = (-glo[lo_only] - s0) / D[0, 0]
+            Um[..., 0][lo_only] = (-glo[lo_only] - s0) / m00
         if hi_only.any():
             sN = Um[hi_only][:, :N] @ D[N, :N]
-            Um[..., N][hi_only] = (ghi[hi_only] - sN) / D[N, N]
+            Um[..., N][hi_only] = (ghi[hi_only] - sN) / mNN
     if np.isnan(U).any():
         raise AssertionError("lift left boundary values undetermined")
     return U
@@ -274,8 +291,9 @@ def lift_transpose(G: Grid3, z: np.ndarray) -> np.ndarray:
         both = nlo & nhi
         lo_only = nlo & ~nhi
         hi_only = nhi & ~nlo
+        m00, m0N, mN0, mNN = end_block(G, a)
         if both.any():
-            M = np.array([[D[0, 0], D[0, N]], [D[N, 0], D[N, N]]])
+            M = np.array([[m00, m0N], [mN0, mNN]])
             # forward: [U0, UN] = M^{-1} [-s0, -sN] (+ data), s = D_{end, 1:N} . inner
             zl = Wm[..., 0][both]
             zh = Wm[..., N][both]
@@ -287,13 +305,13 @@ def lift_transpose(G: Grid3, z: np.ndarray) -> np.ndarray:
             Wm[both] = blk
         if lo_only.any():
             blk = Wm[lo_only]
-            mu = blk[:, 0] / D[0, 0]
+            mu = blk[:, 0] / m00
             blk[:, 1:] -= np.outer(mu, D[0, 1:])
             blk[:, 0] = 0.0
             Wm[lo_only] = blk
         if hi_only.any():
             blk = Wm[hi_only]
-            mu = blk[:, N] / D[N, N]
+            mu = blk[:, N] / mNN
             blk[:, :N] -= np.outer(mu, D[N, :N])
             blk[:, N] = 0.0
             Wm[hi_only] = blk
@@ -351,6 +369,7 @@ def assemble_full(G: Grid3, K: np.ndarray) -> np.ndarray:
             A[rows, rows] = 1.0
         else:
             A[rows, :] = (Da[a][rows, :].toarray()) * (1.0 if side == 1 else -1.0)
+            A[rows, rows] += G.robin[f]
     return A
 
 
@@ -381,21 +400,23 @@ def assemble_reduced(G: Grid3, K) -> np.ndarray:
 # Fast diagonalisation (constant K) and FDM-preconditioned GMRES (variable K)
 # -----------------------------------------------------------------------------
 
-def reduced_1d(D: np.ndarray, bclo: int, bchi: int) -> np.ndarray:
+def reduced_1d(D: np.ndarray, bclo: int, bchi: int, slo: float = 0.0, shi: float = 0.0) -> np.ndarray:
     """1-D reduced second-derivative operator R D D L on the N-1 interior nodes,
-    L the homogeneous lift of one pencil."""
+    L the homogeneous lift of one pencil (Robin coefficients slo, shi on
+    Neumann ends)."""
     N = D.shape[0] - 1
     L = np.zeros((N + 1, N - 1))
     L[1:N, :] = np.eye(N - 1)
+    m00, mNN = D[0, 0] - slo, D[N, N] + shi
     if bclo == NEUMANN and bchi == NEUMANN:
-        M = np.array([[D[0, 0], D[0, N]], [D[N, 0], D[N, N]]])
+        M = np.array([[m00, D[0, N]], [D[N, 0], mNN]])
         E = -np.linalg.solve(M, np.stack([D[0, 1:N], D[N, 1:N]]))
         L[0, :] = E[0]
         L[N, :] = E[1]
     elif bclo == NEUMANN:
-        L[0, :] = -D[0, 1:N] / D[0, 0]
+        L[0, :] = -D[0, 1:N] / m00
     elif bchi == NEUMANN:
-        L[N, :] = -D[N, 1:N] / D[N, N]
+        L[N, :] = -D[N, 1:N] / mNN
     return (D @ D @ L)[1:N, :]
 
 
@@ -404,13 +425,13 @@ class FDM:
     (Kronecker sum of 1-D reduced operators) by eigendecomposition of each."""
 
     def __init__(self, G: Grid3, Kc: float = 1.0):
-        if all(b == NEUMANN for b in G.bc):
+        if all(b == NEUMANN for b in G.bc) and not any(G.robin):
             raise ValueError("all-Neumann problem is singular")
         self.G = G
         self.Kc = float(Kc)
         self.V, self.Vi, self.lam = [], [], []
         for a in range(3):
-            A1 = reduced_1d(G.D[a], G.bc[2 * a], G.bc[2 * a + 1])
+            A1 = reduced_1d(G.D[a], G.bc[2 * a], G.bc[2 * a + 1], G.robin[2 * a], G.robin[2 * a + 1])
             w, V = np.linalg.eig(A1)
             if np.max(np.abs(w.imag)) > 1e-8 * np.max(np.abs(w)):
                 raise AssertionError("complex eigenvalues in 1-D reduced operator")

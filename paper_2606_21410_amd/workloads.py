@@ -53,6 +53,8 @@ class Grid:
     lo: tuple[float, float, float] = (0.0, 0.0, 0.0)
     hi: tuple[float, float, float] = (1.0, 1.0, 1.0)
     bc: tuple[int, int, int, int, int, int] = (DIRICHLET,) * 6
+    # sigma of the Neumann row du/dn + sigma u = g per face (0: plain Neumann)
+    robin: tuple[float, float, float, float, float, float] = (0.0,) * 6
 
     def coords(self):
         return [cgl_coords(self.n[a], self.lo[a], self.hi[a]) for a in range(3)]
@@ -122,17 +124,21 @@ def _faces_from(grid: Grid, value_fn, grad_fn):
             faces.append(value_fn(X, Y, Z))
         else:
             sgn = -1.0 if side == 0 else 1.0
-            faces.append(sgn * grad_fn(X, Y, Z)[a])
+            data = sgn * grad_fn(X, Y, Z)[a]
+            if grid.robin[f] != 0.0:
+                data = data + grid.robin[f] * value_fn(X, Y, Z)
+            faces.append(data)
     return pack_faces(faces)
 
 
-def manufactured_sincos(n: int = 17) -> Problem:
+def manufactured_sincos(n: int = 17, robin=(0.0,) * 6) -> Problem:
     """Homogeneous Poisson on [-1,1]^3: u = sin(pi x) cos(pi y) exp(z), K = 1.
 
-    Dirichlet on the x faces, Neumann (outward du/dn) on the y and z faces.
+    Dirichlet on the x faces, Neumann (outward du/dn, plus robin[f] u where
+    robin[f] is nonzero) on the y and z faces.
     """
     grid = Grid((n, n, n), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0),
-                (DIRICHLET, DIRICHLET, NEUMANN, NEUMANN, NEUMANN, NEUMANN))
+                (DIRICHLET, DIRICHLET, NEUMANN, NEUMANN, NEUMANN, NEUMANN), tuple(float(v) for v in robin))
     pi = math.pi
 
     def u(X, Y, Z):
@@ -203,11 +209,12 @@ def thermal_nonlinear(n: int, alpha: float = 0.5) -> Problem:
 
 
 def manufactured_polynomial(n: int, bc, seed: int = 7, deg_u: int = 3,
-                            lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Problem:
+                            lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), robin=(0.0,) * 6) -> Problem:
     """Random separable-sum polynomial u with polynomial K (degree 1); the
-    discrete operator is exact for it when deg u + deg K - 1 <= N."""
+    discrete operator is exact for it when deg u + deg K - 1 <= N.  Neumann faces
+    with a nonzero robin[f] carry the data du/dn + robin[f] u."""
     r = rng(seed)
-    grid = Grid((n, n, n), tuple(lo), tuple(hi), tuple(bc))
+    grid = Grid((n, n, n), tuple(lo), tuple(hi), tuple(bc), tuple(float(v) for v in robin))
     cu = r.normal(size=(deg_u + 1, deg_u + 1, deg_u + 1)) / 4
     ck = r.uniform(0.1, 0.3, size=3)
 

@@ -1,0 +1,111 @@
+"""Pins of the oracle's Robin rows du/dn + sigma u = g (the general linear
+boundary operator of Section 2.3.1 with a nonzero derivative coefficient):
+exactness on polynomials, the limits sigma -> 0 (Neumann) and sigma -> infinity
+(Dirichlet), spectral convergence, and the elimination / transpose identities
+that a misplaced or mis-signed sigma breaks."""
+import numpy as np
+import pytest
+
+from oracle import cheb_oracle as O
+from paper_2606_21410_amd import workloads as W
+
+D_, N_ = O.DIRICHLET, O.NEUMANN
+
+
+def grid_of(P):
+    return O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, P.grid.robin)
+
+
+ROBIN_CASES = [((D_, N_, N_, N_, N_, N_), (0.0, 2.5, 0.7, 0.0, 1.3, 4.0)),
+               ((N_, N_, D_, N_, N_, N_), (3.0, 0.5, 0.0, 0.2, 1.0, 1.0)),
+               ((N_,) * 6, (1.0, 2.0, 0.5, 0.5, 3.0, 0.1))]
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_polynomial_exact_with_robin_faces(bc, robin):
+    """A degree-3 polynomial with linear K satisfies every collocation row and
+    every Robin row exactly, so the discrete solution is the polynomial.  A sign
+    error on sigma, or sigma on the wrong end, moves the solution by O(1)."""
+    P = W.manufactured_polynomial(7, bc, seed=5, robin=robin)
+    G = grid_of(P)
+    U = O.solve_dense(G, P.K, P.f, P.g)
+    np.testing.assert_allclose(U, P.u_exact, atol=1e-10 * np.abs(P.u_exact).max())
+    Ug = O.solve(G, P.K, P.f, P.g, method="gmres")
+    np.testing.assert_allclose(Ug, P.u_exact, atol=1e-9 * np.abs(P.u_exact).max())
+    # the same data read as plain Neumann rows is a different problem
+    Gn = O.Grid3(G.n, G.lo, G.hi, G.bc)
+    assert np.abs(O.solve_dense(Gn, P.K, P.f, P.g) - P.u_exact).max() > 1e-3
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_lift_satisfies_robin_rows(bc, robin):
+    r = np.random.default_rng(3)
+    G = O.Grid3((6, 7, 5), (0, 0, 0), (1.0, 2.0, 0.5), bc, robin)
+    x = r.standard_normal(G.n)
+    g = W.random_faces(W.Grid(G.n, G.lo, G.hi, G.bc), 9)
+    U = O.lift(G, x, g)
+    rows = O.bc_rows(G, U)
+    fv = O.face_values(G, g)
+    np.testing.assert_allclose(rows[~G.interior], fv[~G.interior], atol=1e-10)
+    np.testing.assert_array_equal(U[G.interior], x[G.interior])
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_reduced_operator_and_transpose_with_robin(bc, robin):
+    """Reduced operator = A_kk + A_kr (-B_r^{-1} B_k) from the assembled matrix,
+    and its transpose, with Robin rows in B."""
+    r = np.random.default_rng(4)
+    G = O.Grid3((5, 6, 7), (0, 0, 0), (1, 1.5, 2), bc, robin)
+    K = np.exp(0.4 * r.standard_normal(G.n))
+    A = O.assemble_full(G, K)
+    k = np.nonzero(G.interior.ravel())[0]
+    rr = np.nonzero(~G.interior.ravel())[0]
+    Ared = A[np.ix_(k, k)] - A[np.ix_(k, rr)] @ np.linalg.solve(A[np.ix_(rr, rr)], A[np.ix_(rr, k)])
+    x = r.standard_normal(G.n)
+    v = r.standard_normal(G.n)
+    y = O.apply_reduced(G, K, x)
+    np.testing.assert_allclose(y.ravel()[k], Ared @ x.ravel()[k], atol=1e-9 * np.abs(Ared).max())
+    yt = O.apply_reduced_transpose(G, K, v)
+    np.testing.assert_allclose(yt.ravel()[k], Ared.T @ v.ravel()[k], atol=1e-9 * np.abs(Ared).max())
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_fdm_equals_lu_with_robin(bc, robin):
+    r = np.random.default_rng(6)
+    G = O.Grid3((7, 6, 8), (0, 0, 0), (1, 2, 1), bc, robin)
+    f = r.standard_normal(G.n)
+    g = W.random_faces(W.Grid(G.n, G.lo, G.hi, G.bc), 7)
+    K = np.full(G.n, 1.7)
+    U_lu = O.solve_dense(G, K, f, g)
+    U_fdm = O.solve(G, K, f, g, method="fdm")
+    np.testing.assert_allclose(U_fdm, U_lu, atol=1e-9 * np.abs(U_lu).max())
+
+
+def test_robin_limits():
+    """sigma = 1e-12 reproduces the Neumann solve; sigma = 1e10 with data
+    sigma * u_D reproduces the Dirichlet solve with data u_D."""
+    P = W.manufactured_polynomial(7, (D_, N_, D_, N_, D_, N_), seed=8, deg_u=4)
+    G = grid_of(P)
+    Un = O.solve_dense(G, P.K, P.f, P.g)
+    Gs = O.Grid3(G.n, G.lo, G.hi, G.bc, (0.0, 1e-12, 0.0, 1e-12, 0.0, 1e-12))
+    np.testing.assert_allclose(O.solve_dense(Gs, P.K, P.f, P.g), Un, atol=1e-9 * np.abs(Un).max())
+    big = 1e10
+    Gd = O.Grid3(G.n, G.lo, G.hi, (D_,) * 6)
+    grid_d = W.Grid(G.n, G.lo, G.hi, (D_,) * 6)
+    gd = W.random_faces(grid_d, 10)
+    Ud = O.solve_dense(Gd, P.K, P.f, gd)
+    Gb = O.Grid3(G.n, G.lo, G.hi, (D_, N_, D_, N_, D_, N_), (0.0, big, 0.0, big, 0.0, big))
+    gb = [fc * (big if Gb.bc[f] == N_ else 1.0) for f, fc in enumerate(Gd.unpack_faces(gd))]
+    Ub = O.solve_dense(Gb, P.K, P.f, W.pack_faces(gb))
+    # interior values converge like 1/sigma; edges owned differently are excluded
+    np.testing.assert_allclose(Ub[1:-1, 1:-1, 1:-1], Ud[1:-1, 1:-1, 1:-1], atol=1e-6 * np.abs(Ud).max())
+
+
+def test_sincos_robin_spectral_convergence():
+    err = []
+    for n in (9, 17):
+        P = W.manufactured_sincos(n, robin=(0.0, 0.0, 1.5, 0.5, 2.0, 0.25))
+        G = grid_of(P)
+        U = O.solve(G, P.K, P.f, P.g)
+        err.append(np.max(np.abs(U - P.u_exact)))
+    assert err[1] < 1e-4 * err[0] and err[1] < 1e-7
