@@ -3,7 +3,8 @@
  *
  * Problem (Section 2, 3-D extension; Section 3.3 flux form):
  *     div(K(x) grad u) = f   in the box  prod_a [lo_a, hi_a],
- *     per face either u = g (Dirichlet) or du/dn = g (Neumann, outward normal),
+ *     per face either u = g (Dirichlet) or du/dn + sigma u = g (Neumann,
+ *     outward normal; sigma = 0 unless a Robin coefficient is given),
  * discretised by collocation at the tensor Chebyshev-Gauss-Lobatto (CGL) nodes:
  * the PDE holds at interior nodes, one boundary-condition row holds at every
  * boundary node (Section 2.3.1).  The discrete operator is applied matrix-free
@@ -24,7 +25,8 @@
  *   - Faces are numbered 0..5 = x_lo, x_hi, y_lo, y_hi, z_lo, z_hi.  Face data
  *     (g_faces) are packed face after face; the array of face f on axis a has
  *     shape (n[b], n[c]) with b < c the two other axes.
- *   - Neumann data are the outward normal derivative du/dn (not the flux).
+ *   - Neumann data are the outward normal derivative du/dn (not the flux),
+ *     plus sigma u on faces with a Robin coefficient (cheb_grid.robin).
  *   - Edge and corner nodes (on several faces) carry exactly one equation: the
  *     Dirichlet face of lowest axis if one contains the node, otherwise the
  *     Neumann face of lowest axis.  (The paper is silent on this; the interior
@@ -83,6 +85,14 @@ typedef struct cheb_grid {
   double lo[3];  /* box lower corner */
   double hi[3];  /* box upper corner, hi > lo */
   int32_t bc[6]; /* CHEB_DIRICHLET or CHEB_NEUMANN per face */
+  /* Robin coefficient sigma per face (Section 2.3.1, general linear boundary
+   * operator): a Neumann face's row becomes du/dn + sigma u = g (outward
+   * normal derivative).  A row a u + b du/dn = g with b != 0 is sigma = a / b
+   * with data g / b.  0 gives the plain Neumann row; must be 0 on Dirichlet
+   * faces.  A plan rejects (CHEB_ERR_INVALID_ARG) coefficients that make an
+   * end-value elimination block singular, and accepts six Neumann faces only
+   * when some sigma is nonzero.  Batches take sigma = 0 only. */
+  double robin[6];
 } cheb_grid;
 
 typedef struct cheb_solve_opts {
@@ -116,8 +126,9 @@ typedef struct cheb_solve_info {
 
 typedef struct cheb_plan cheb_plan;
 
-/* Create a plan for one grid.  Validates n (3..513), lo < hi, bc values, and
- * rejects all-Neumann problems with CHEB_ERR_SINGULAR_BC.  `stream` is a
+/* Create a plan for one grid.  Validates n (3..513), lo < hi, bc values and
+ * Robin coefficients, and rejects all-Neumann problems without a Robin
+ * coefficient with CHEB_ERR_SINGULAR_BC.  `stream` is a
  * hipStream_t (NULL = default stream).  Allocates a few KB of device constants
  * (boundary rows of the differentiation matrix). */
 int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, cheb_plan** out);

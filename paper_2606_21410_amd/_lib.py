@@ -30,7 +30,8 @@ CHEB_ROUTE_AUTO, CHEB_ROUTE_FFT, CHEB_ROUTE_MATRIX = 0, 1, 2
 
 class cheb_grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 6)]
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 6),
+                ("robin", ctypes.c_double * 6)]
 
 
 class cheb_solve_opts(ctypes.Structure):

@@ -55,12 +55,13 @@ class Plan:
     """One grid: sizes, box, face types, precision ('f64', 'f32', 'mixed')."""
 
     def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0,) * 6, precision="f64",
-                 device="cuda", route: str = "auto"):
+                 device="cuda", route: str = "auto", robin=None):
         self.lib = L.load()
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)
         self.bc = tuple(int(v) for v in bc)
+        self.robin = tuple(float(v) for v in (robin if robin is not None else (0.0,) * 6))
         self.precision = precision
         self.device = torch.device(device)
         self.dtype = torch.float32 if precision == "f32" else torch.float64
@@ -69,6 +70,7 @@ class Plan:
             g.n[a], g.lo[a], g.hi[a] = self.n[a], self.lo[a], self.hi[a]
         for f in range(6):
             g.bc[f] = self.bc[f]
+            g.robin[f] = self.robin[f]
         self._h = ctypes.c_void_p()
         stream = _stream_handle(self.device) if self.device.type == "cuda" else 0
         L.check(self.lib.cheb_plan_create(ctypes.byref(g), _PREC[precision], ctypes.c_void_p(stream),
@@ -315,7 +317,8 @@ class Plan:
 class Batch:
     """Many independent systems solved in lockstep (cheb_batch_*).
 
-    ``grids``: list of (n, lo, hi, bc) tuples, one per system.  Systems with the
+    ``grids``: list of (n, lo, hi, bc) tuples, one per system (a fifth entry,
+    Robin coefficients, must be all zero).  Systems with the
     same n, lo, hi share operator launches; systems that also share the face
     types share preconditioner launches."""
 
@@ -323,14 +326,17 @@ class Batch:
         self.lib = L.load()
         self.device = torch.device(device)
         self.precision = precision
-        self.grids = [(tuple(int(v) for v in n), tuple(float(v) for v in lo), tuple(float(v) for v in hi),
-                       tuple(int(v) for v in bc)) for n, lo, hi, bc in grids]
+        self.grids = [(tuple(int(v) for v in gr[0]), tuple(float(v) for v in gr[1]),
+                       tuple(float(v) for v in gr[2]), tuple(int(v) for v in gr[3])) for gr in grids]
+        # optional fifth entry: Robin coefficients (the library accepts only zeros here)
+        robins = [tuple(float(v) for v in gr[4]) if len(gr) > 4 else (0.0,) * 6 for gr in grids]
         arr = (L.cheb_grid * len(self.grids))()
         for i, (n, lo, hi, bc) in enumerate(self.grids):
             for a in range(3):
                 arr[i].n[a], arr[i].lo[a], arr[i].hi[a] = n[a], lo[a], hi[a]
             for f in range(6):
                 arr[i].bc[f] = bc[f]
+                arr[i].robin[f] = robins[i][f]
         self._h = ctypes.c_void_p()
         L.check(self.lib.cheb_batch_create(arr, len(self.grids), _PREC[precision],
                                            ctypes.c_void_p(_stream_handle(self.device)), ctypes.byref(self._h)))

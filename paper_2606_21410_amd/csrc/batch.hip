@@ -684,6 +684,14 @@ int cheb_batch_create(const cheb_grid* grids, int32_t nprob, int32_t precision, 
     set_error("batched solves run in CHEB_F64 or CHEB_MIXED");
     return CHEB_ERR_INVALID_ARG;
   }
+  // systems of a group share one plan's boundary constants, which carry no
+  // per-system Robin coefficient
+  for (int s = 0; s < nprob; ++s)
+    for (int f = 0; f < 6; ++f)
+      if (grids[s].robin[f] != 0.0) {
+        set_error("batched solves take Robin coefficient 0 on every face");
+        return CHEB_ERR_UNSUPPORTED;
+      }
   cheb_batch* B = new (std::nothrow) cheb_batch();
   if (!B) {
     set_error("out of host memory");

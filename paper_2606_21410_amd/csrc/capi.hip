@@ -162,15 +162,20 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
       return CHEB_ERR_INVALID_ARG;
     }
   }
-  bool allN = true;
+  bool allN = true, anyRobin = false;
   for (int f = 0; f < 6; ++f) {
     if (grid->bc[f] != CHEB_DIRICHLET && grid->bc[f] != CHEB_NEUMANN) {
       set_error("face type must be CHEB_DIRICHLET or CHEB_NEUMANN");
       return CHEB_ERR_INVALID_ARG;
     }
+    if (!std::isfinite(grid->robin[f]) || (grid->bc[f] == CHEB_DIRICHLET && grid->robin[f] != 0.0)) {
+      set_error("Robin coefficients must be finite, and 0 on Dirichlet faces");
+      return CHEB_ERR_INVALID_ARG;
+    }
     allN = allN && grid->bc[f] == CHEB_NEUMANN;
+    anyRobin = anyRobin || grid->robin[f] != 0.0;
   }
-  if (allN) {
+  if (allN && !anyRobin) {
     set_error("all six faces Neumann: the problem is singular");
     return CHEB_ERR_SINGULAR_BC;
   }
@@ -205,10 +210,22 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
     std::vector<double> r0, rN, w;
     boundary_rows(c.N, c.L, r0, rN);
     cc_weights(c.N, c.L, w);
-    c.m00 = r0[0];
+    // end-value block of the boundary rows: lo row -(D u)_0 + sigma_lo u_0,
+    // hi row (D u)_N + sigma_hi u_N (sigma = 0 on plain Neumann faces)
+    c.m00 = r0[0] - grid->robin[2 * a];
     c.m0N = r0[c.N];
     c.mN0 = rN[0];
-    c.mNN = rN[c.N];
+    c.mNN = rN[c.N] + grid->robin[2 * a + 1];
+    const bool nlo = grid->bc[2 * a] == CHEB_NEUMANN, nhi = grid->bc[2 * a + 1] == CHEB_NEUMANN;
+    const double det = c.m00 * c.mNN - c.m0N * c.mN0;
+    const double scale = std::fabs(c.m00 * c.mNN) + std::fabs(c.m0N * c.mN0);
+    if ((nlo && !(std::fabs(c.m00) > 1e-12 * std::fabs(r0[0]))) ||
+        (nhi && !(std::fabs(c.mNN) > 1e-12 * std::fabs(rN[c.N]))) ||
+        (nlo && nhi && !(std::fabs(det) > 1e-12 * scale))) {
+      set_error("Robin coefficients make a boundary elimination block singular");
+      delete p;
+      return CHEB_ERR_INVALID_ARG;
+    }
     for (int j = 0; j <= c.N; ++j) {
       h64[(kConstSlots * a + 0) * p->dconst_stride + j] = r0[j];
       h64[(kConstSlots * a + 1) * p->dconst_stride + j] = rN[j];

@@ -44,7 +44,8 @@ struct PassArgs {
   int first;  // this pass initialises every row it owns ('='); later passes accumulate
   int bcmask; // bit f set when face f is Neumann
   T cscale;   // -1 / (N * L_axis)
-  T m00, m0N, mN0, mNN;  // corner entries of that matrix
+  T m00, m0N, mN0, mNN;  // end-value block of the boundary rows (corner entries, Robin-shifted)
+  T slo, shi;            // Robin coefficients of the axis' lo and hi faces (FULL rows)
   int npencils;
 };
 
@@ -601,7 +602,7 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
             const int bct = (a.bcmask >> (2 * axis + (m == 0 ? 0 : 1))) & 1;
             T r;
             if (bct == 0) r = ends[4 * pl + (m == 0 ? 0 : 1)];
-            else r = (m == 0) ? -ends[4 * pl + 2] : ends[4 * pl + 3];
+            else r = (m == 0) ? a.slo * ends[4 * pl + 0] - ends[4 * pl + 2] : ends[4 * pl + 3] + a.shi * ends[4 * pl + 1];
             a.y[ad] = r;
           }
         }

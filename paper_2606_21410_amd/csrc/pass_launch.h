@@ -89,6 +89,8 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
   a.m0N = T(p->ax[axis].m0N);
   a.mN0 = T(p->ax[axis].mN0);
   a.mNN = T(p->ax[axis].mNN);
+  a.slo = T(p->g.robin[2 * axis]);
+  a.shi = T(p->g.robin[2 * axis + 1]);
   a.npencils = pencil_count(axis, a.n);
   return dispatch_pass<T>(a, mode, s);
 }

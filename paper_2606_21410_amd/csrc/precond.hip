@@ -38,13 +38,15 @@ namespace cheb {
 namespace {
 
 // 1-D reduced operator R D D L (m x m, m = N-1) for the boundary pair (blo, bhi)
-void reduced_1d(int N, double L, int blo, int bhi, std::vector<double>& A) {
+// with Robin coefficients (slo, shi) on Neumann ends
+void reduced_1d(int N, double L, int blo, int bhi, double slo, double shi, std::vector<double>& A) {
   const int n = N + 1, m = N - 1;
   std::vector<double> D;
   dense_D(N, L, D);
-  // lift: rows 0 and N of L as functions of the interior values
+  // lift: rows 0 and N of L as functions of the interior values; the end-value
+  // block of the rows -(D u)_0 + slo u_0 and (D u)_N + shi u_N
   std::vector<double> l0(m, 0.0), lN(m, 0.0);
-  const double d00 = D[0], d0N = D[N], dN0 = D[(size_t)N * n], dNN = D[(size_t)N * n + N];
+  const double d00 = D[0] - slo, d0N = D[N], dN0 = D[(size_t)N * n], dNN = D[(size_t)N * n + N] + shi;
   for (int j = 0; j < m; ++j) {
     const double a = D[j + 1], b = D[(size_t)N * n + j + 1];
     if (blo == 1 && bhi == 1) {
@@ -705,7 +707,8 @@ int precond_setup(cheb_plan* p) {
     src[a] = a;
     for (int b = 0; b < a; ++b)
       if (src[b] == b && p->ax[b].N == p->ax[a].N && p->ax[b].L == p->ax[a].L &&
-          p->g.bc[2 * b] == p->g.bc[2 * a] && p->g.bc[2 * b + 1] == p->g.bc[2 * a + 1]) {
+          p->g.bc[2 * b] == p->g.bc[2 * a] && p->g.bc[2 * b + 1] == p->g.bc[2 * a + 1] &&
+          p->g.robin[2 * b] == p->g.robin[2 * a] && p->g.robin[2 * b + 1] == p->g.robin[2 * a + 1]) {
         src[a] = b;
         break;
       }
@@ -719,9 +722,11 @@ int precond_setup(cheb_plan* p) {
       th.emplace_back([&, a]() {
         const int m = p->ax[a].N - 1;
         std::vector<double> A;
-        reduced_1d(p->ax[a].N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], A);
-        // the same face type at both ends: the 1-D operator is centro-symmetric
-        okv[a] = p->g.bc[2 * a] == p->g.bc[2 * a + 1] ? eig_centro(m, A, lamv[a], Vv[a], Viv[a])
+        reduced_1d(p->ax[a].N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], p->g.robin[2 * a],
+                   p->g.robin[2 * a + 1], A);
+        // the same face row at both ends: the 1-D operator is centro-symmetric
+        const bool centro = p->g.bc[2 * a] == p->g.bc[2 * a + 1] && p->g.robin[2 * a] == p->g.robin[2 * a + 1];
+        okv[a] = centro ? eig_centro(m, A, lamv[a], Vv[a], Viv[a])
                                                       : eig_real(m, A, lamv[a], Vv[a]) && invert(m, Vv[a], Viv[a]);
       });
     }

@@ -32,12 +32,13 @@ def test_status_strings():
         assert s and s != "unknown status"
 
 
-def _grid(n=(9, 9, 9), lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 1, 1, 1, 1)):
+def _grid(n=(9, 9, 9), lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 1, 1, 1, 1), robin=(0.0,) * 6):
     g = L.cheb_grid()
     for a in range(3):
         g.n[a], g.lo[a], g.hi[a] = n[a], lo[a], hi[a]
     for f in range(6):
         g.bc[f] = bc[f]
+        g.robin[f] = robin[f]
     return g
 
 
@@ -47,6 +48,12 @@ def _grid(n=(9, 9, 9), lo=(0, 0, 0), hi=(1, 1, 1), bc=(0, 0, 1, 1, 1, 1)):
     (dict(lo=(0, 1, 0), hi=(1, 1, 1)), L.CHEB_ERR_INVALID_ARG),
     (dict(bc=(0, 0, 2, 1, 1, 1)), L.CHEB_ERR_INVALID_ARG),
     (dict(bc=(1, 1, 1, 1, 1, 1)), L.CHEB_ERR_SINGULAR_BC),
+    # Robin coefficient on a Dirichlet face, a non-finite one, and sigma_lo
+    # equal to the corner entry D_00 = -(2 N^2 + 1) / 3 of the unit interval
+    # at N = 8, which zeroes the end value's coefficient
+    (dict(robin=(1.0, 0, 0, 0, 0, 0)), L.CHEB_ERR_INVALID_ARG),
+    (dict(robin=(0, 0, float("nan"), 0, 0, 0)), L.CHEB_ERR_INVALID_ARG),
+    (dict(robin=(0, 0, -43.0, 0, 0, 0)), L.CHEB_ERR_INVALID_ARG),
 ])
 def test_plan_validation(kw, code):
     lib = _lib()
