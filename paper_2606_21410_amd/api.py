@@ -411,7 +411,7 @@ def load_case(n, axis, device="cuda"):
 
 
 def solve_2d(K, f, g, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(L.CHEB_DIRICHLET,) * 4, precision="f64", opts=None,
-             device="cuda"):
+             device="cuda", robin=None):
     """The 2-D problem div(K grad u) = f on a rectangle (the setting in which
     Algorithms 2 and 3 are written), through the 3-D solver.  The grid gets a
     third axis of three nodes with zero-flux faces, and K, f and the face data
@@ -423,10 +423,12 @@ def solve_2d(K, f, g, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(L.CHEB_DIRICHLET,) * 4, 
 
     K, f: (n0, n1) tensors.  g: four face vectors [x_lo (n1,), x_hi (n1,),
     y_lo (n0,), y_hi (n0,)], Dirichlet values or outward normal derivatives per
-    ``bc``.  Returns (u of shape (n0, n1), info)."""
+    ``bc`` (plus robin[f] u on faces with a Robin coefficient).  Returns
+    (u of shape (n0, n1), info)."""
     n0, n1 = K.shape
+    r3 = tuple(robin) + (0.0, 0.0) if robin is not None else None
     plan = Plan((n0, n1, 3), (lo[0], lo[1], 0.0), (hi[0], hi[1], 1.0), tuple(bc) + (L.CHEB_NEUMANN,) * 2,
-                precision, device)
+                precision, device, robin=r3)
     dt = plan.dtype
     col = lambda t, m: torch.as_tensor(t).to(device, dt).reshape(m, 1).expand(m, 3).reshape(-1)
     K3 = torch.as_tensor(K).to(device, dt).reshape(n0, n1, 1).expand(n0, n1, 3).contiguous()
@@ -437,14 +439,17 @@ def solve_2d(K, f, g, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(L.CHEB_DIRICHLET,) * 4, 
     return u3[:, :, 0].contiguous(), info
 
 
-def solve_1d(K, f, g, lo=-1.0, hi=1.0, bc=(L.CHEB_DIRICHLET,) * 2, precision="f64", opts=None, device="cuda"):
+def solve_1d(K, f, g, lo=-1.0, hi=1.0, bc=(L.CHEB_DIRICHLET,) * 2, precision="f64", opts=None, device="cuda",
+             robin=None):
     """The 1-D problem (K u')' = f on [lo, hi] (the setting of the paper's
     first example), through the 3-D solver with two further axes of three
     nodes, zero-flux faces and data constant along them (see solve_2d).
-    K, f: (n,) tensors; g: [value or outward derivative at lo, at hi].  Returns
-    (u of shape (n,), info)."""
+    K, f: (n,) tensors; g: [value or outward derivative at lo, at hi] (plus
+    robin[f] u with a Robin coefficient).  Returns (u of shape (n,), info)."""
     n = K.shape[0]
-    plan = Plan((n, 3, 3), (lo, 0.0, 0.0), (hi, 1.0, 1.0), tuple(bc) + (L.CHEB_NEUMANN,) * 4, precision, device)
+    r3 = tuple(robin) + (0.0,) * 4 if robin is not None else None
+    plan = Plan((n, 3, 3), (lo, 0.0, 0.0), (hi, 1.0, 1.0), tuple(bc) + (L.CHEB_NEUMANN,) * 4, precision, device,
+                robin=r3)
     dt = plan.dtype
     K3 = torch.as_tensor(K).to(device, dt).reshape(n, 1, 1).expand(n, 3, 3).contiguous()
     f3 = torch.as_tensor(f).to(device, dt).reshape(n, 1, 1).expand(n, 3, 3).contiguous()

@@ -92,3 +92,25 @@ def test_solve_2d_matches_3d_oracle_on_embedding():
     log(f"embedding: oracle z-variation {np.max(np.abs(U3 - U3[:, :, :1])):.1e}")
     assert np.max(np.abs(U3 - U3[:, :, :1])) <= 1e-12 * np.max(np.abs(U3))
     assert rel_l2(to_host(u), U3[:, :, 0]) <= 1e-11
+
+
+@pytest.mark.parametrize("sig", [(0.5, 2.0), (3.0, 0.0)])
+def test_solve_1d_robin_polynomial(sig):
+    """u = x^3 + x on [-1, 1] with K = 1 (u'' = 6x) and Robin rows at both ends
+    (-u'(-1) + s_lo u(-1) = g_lo, u'(1) + s_hi u(1) = g_hi): a cubic is exact
+    at any N >= 3, so the collocation solution is the cubic itself."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd import _lib as L
+    from paper_2606_21410_amd.api import SolveOptions, solve_1d
+    N = 12
+    x = W.cgl_coords(N + 1, -1.0, 1.0)
+    ue = x ** 3 + x
+    glo = -(3.0 + 1.0) + sig[0] * (-2.0)
+    ghi = (3.0 + 1.0) + sig[1] * 2.0
+    u, info = solve_1d(torch.ones(N + 1, dtype=torch.float64), torch.from_numpy(6.0 * x), [glo, ghi],
+                       bc=(L.CHEB_NEUMANN, L.CHEB_NEUMANN), robin=sig,
+                       opts=SolveOptions(rtol=1e-14, maxiter=2000, precond=True))
+    err = np.max(np.abs(to_host(u) - ue))
+    log(f"1-D Robin {sig}: {info['matvecs']} matvecs, max error {err:.2e}")
+    assert info["status"] == 0 and err <= 1e-12
