@@ -359,6 +359,54 @@ def thermal_newton_section(dev, levels=(8, 16, 32, 64, 128, 256), tol=1e-11, max
     return out
 
 
+def robin_section(dev, P, steps=100, warmup=10):
+    """Robin rows on the metric workload: the 129^3 two-phase K with
+    du/dn + u = 0 on its four former zero-flux faces (sigma = 1), reduced FP64
+    applies timed with events; and the sin(pi x) cos(pi y) e^z field on
+    [-1,1]^3 (Dirichlet x faces, Robin sigma = 1.5, 0.5, 2, 0.25 on the y and z
+    faces) solved at 129^3 by preconditioned FP64 LGMRES, with its max error
+    against the analytic field."""
+    import numpy as np
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    robin = tuple(0.0 if b == W.DIRICHLET else 1.0 for b in P.grid.bc)
+    shape = P.grid.n
+    plan = Plan(shape, P.grid.lo, P.grid.hi, P.grid.bc, "f64", device=dev, robin=robin)
+    K = torch.from_numpy(P.K).to(dev)
+    us = [torch.from_numpy(W.random_field(shape, 100 + i)).to(dev) for i in range(4)]
+    ys = [torch.empty_like(us[0]) for _ in range(4)]
+    for i in range(warmup):
+        plan.apply(K, us[i % 4], ys[i % 4], "reduced")
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(steps):
+        plan.apply(K, us[i % 4], ys[i % 4], "reduced")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    out = {"apply_ms": round(ms, 5), "apply_gdofs": round(float(np.prod(shape)) / (ms * 1e-3) / 1e9, 3),
+           "robin": list(robin)}
+    sig = (0.0, 0.0, 1.5, 0.5, 2.0, 0.25)
+    M = W.manufactured_sincos(shape[0], robin=sig)
+    pm = Plan(M.grid.n, M.grid.lo, M.grid.hi, M.grid.bc, "f64", device=dev, robin=sig)
+    opts = SolveOptions(rtol=1e-10, precond=True)
+    pm.ensure_workspace(opts)
+    Km, fm, gm = (torch.from_numpy(a).to(dev) for a in (M.K, M.f, M.g))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, info = pm.solve(Km, fm, gm, opts=opts)
+    torch.cuda.synchronize()
+    out["sincos_solve"] = {"seconds": round(time.perf_counter() - t0, 4), "matvecs": info["matvecs"],
+                           "status": info["status"], "robin": list(sig),
+                           "max_error": float((u - torch.from_numpy(M.u_exact).to(dev)).abs().max().item())}
+    _log(f"robin {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +419,9 @@ def main():
     ap.add_argument("--profile-apply", action="store_true",
                     help="for profiler runs: 4 plain device copies of one FP64 field (the byte-counter "
                          "calibration), then the FP64 applies only")
+    ap.add_argument("--profile-newton", action="store_true",
+                    help="for profiler runs: the Section 3.4 Newton solve from a cold start at N = 128, then "
+                         "the refinement chain N = 8 .. 128")
     ap.add_argument("--profile-solve", action="store_true",
                     help="for profiler runs: the preconditioned FP64 and mixed solves only, each twice on "
                          "one plan (the first with plan and preconditioner set-up)")
@@ -399,6 +450,23 @@ def main():
 
     res = {}
     stream = torch.cuda.current_stream(dev)
+
+    if args.profile_newton:
+        T = W.thermal_nonlinear(129)
+        pl = Plan(T.grid.n, T.grid.lo, T.grid.hi, T.grid.bc, "f64", device=dev)
+        opts = SolveOptions(rtol=1e-10, precond=True)
+        pl.ensure_workspace(opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info = pl.newton(d(T.K), d(T.f), d(T.g), alpha=T.meta["alpha"], tol=1e-11, max_steps=20, opts=opts)
+        torch.cuda.synchronize()
+        cold = {"seconds": round(time.perf_counter() - t0, 4), "newton_steps": info["newton_steps"],
+                "mv_per_step": info["mv_per_step"], "status": info["rc"],
+                "max_error": float((u - d(T.u_exact)).abs().max().item())}
+        _log(f"cold Newton N=128: {cold}")
+        chain = thermal_newton_section(dev, levels=(8, 16, 32, 64, 128))
+        print(json.dumps({"profile_newton": {"cold_128": cold, "chain": chain}}), flush=True)
+        return
 
     if args.profile_solve:
         K, f, g = d(P.K), d(P.f), d(P.g)
@@ -528,6 +596,11 @@ def main():
         _log("spherical inclusion, contrast sweep 1e-4 .. 1e4")
         inclusion = inclusion_section(dev)
 
+    robin_rows = None
+    if not args.no_solve and n == 129:
+        _log("Robin rows: apply rate and a manufactured solve at 129^3")
+        robin_rows = robin_section(dev, P)
+
     thermal = None
     if not args.no_solve and n == 129:
         _log("nonlinear thermal problem, Newton-LGMRES chain N = 8 .. 256")
@@ -569,6 +642,7 @@ def main():
         "picard_chain": chain,
         "inclusion_contrast_sweep": inclusion,
         "thermal_newton_chain": thermal,
+        "robin_rows": robin_rows,
     }
     print(json.dumps(out), flush=True)
 

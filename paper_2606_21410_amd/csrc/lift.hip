@@ -5,7 +5,8 @@
 //   transpose:  the homogeneous lift transposed, steps in reverse order (x, y,
 //               z), each adding the end value (mapped by the transposed block)
 //               onto the pencil's other values; finally boundary entries are 0.
-// One thread per pencil; the pencil loop reads n values along the axis.
+// The lift reads each pencil with many lanes (a wave per z pencil; eight waves
+// per 64 x or y pencils); the transpose runs one thread per pencil.
 #include "internal.h"
 #include "pencil.h"
 
@@ -53,25 +54,41 @@ __global__ void k_set_dirichlet(T* U, const T* g, int f, LiftArgs a) {
   U[ad] = g ? g[a.goff[f] + t] : T(0);
 }
 
+// Pencils along x or y: lanes take adjacent pencils (adjacent addresses, so
+// every load is coalesced) and the 8 waves of a workgroup split each pencil's
+// inner nodes, so a launch holds eight times as many waves as pencils/64; the
+// partial row sums meet in LDS and wave 0 solves for the end values.
 template <typename T>
-__global__ void k_lift_axis(T* U, const T* g, int axis, const T* drow0, const T* drowN, double m00, double m0N,
-                            double mN0, double mNN, LiftArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(512) void k_lift_axis(T* U, const T* g, int axis, const T* drow0, const T* drowN,
+                                                   double m00, double m0N, double mN0, double mNN, LiftArgs a) {
+  __shared__ double red[2][8][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
   const int np = pencil_count(axis, a.n);
-  long long base;
-  const int fl = pencil_flags(axis, p, np, a.n[0], a.n[1], a.n[2], a.bcmask, &base);
-  if (!(fl & PF_VALID)) return;
-  const bool nlo = (fl & PF_OWN_LO) && a.bc[2 * axis] == 1;
-  const bool nhi = (fl & PF_OWN_HI) && a.bc[2 * axis + 1] == 1;
-  if (!nlo && !nhi) return;
+  long long base = 0;
+  const int fl = p < np ? pencil_flags(axis, p, np, a.n[0], a.n[1], a.n[2], a.bcmask, &base) : 0;
+  const bool nlo = (fl & PF_VALID) && (fl & PF_OWN_LO) && a.bc[2 * axis] == 1;
+  const bool nhi = (fl & PF_VALID) && (fl & PF_OWN_HI) && a.bc[2 * axis + 1] == 1;
   const long long st = pencil_stride(axis, a.n);
   const int N = a.n[axis] - 1;
   T* u = U + base;
   double s0 = 0.0, sN = 0.0;
-  for (int m = 1; m < N; ++m) {
-    const double v = double(u[m * st]);
-    s0 = fma(double(drow0[m]), v, s0);
-    sN = fma(double(drowN[m]), v, sN);
+  if (nlo || nhi) {
+    for (int m = 1 + w; m < N; m += 8) {
+      const double v = double(u[m * st]);
+      s0 = fma(double(drow0[m]), v, s0);
+      sN = fma(double(drowN[m]), v, sN);
+    }
+  }
+  red[0][w][lane] = s0;
+  red[1][w][lane] = sN;
+  __syncthreads();
+  if (w != 0 || !(nlo || nhi)) return;
+  s0 = 0.0;
+  sN = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    s0 += red[0][k][lane];
+    sN += red[1][k][lane];
   }
   const double glo = g ? double(g[a.goff[2 * axis] + p]) : 0.0;
   const double ghi = g ? double(g[a.goff[2 * axis + 1] + p]) : 0.0;
@@ -86,6 +103,52 @@ __global__ void k_lift_axis(T* U, const T* g, int axis, const T* drow0, const T*
   } else {
     const double rN = ghi - sN - double(drowN[0]) * double(u[0]);
     u[N * st] = T(rN / mNN);
+  }
+}
+
+// The same lift for pencils along z, whose nodes are contiguous: one 64-lane
+// wave per pencil reads it in coalesced strips, the two row sums are reduced
+// across the wave, and lane 0 solves for the end values (one thread per pencil
+// would read 64 separate lines per load here).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lift_z_wave(T* U, const T* g, const T* drow0, const T* drowN, double m00,
+                                                     double m0N, double mN0, double mNN, LiftArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int np = pencil_count(2, a.n);
+  if (p >= np) return;  // uniform per wave
+  long long base;
+  const int fl = pencil_flags(2, p, np, a.n[0], a.n[1], a.n[2], a.bcmask, &base);
+  if (!(fl & PF_VALID)) return;
+  const bool nlo = (fl & PF_OWN_LO) && a.bc[4] == 1;
+  const bool nhi = (fl & PF_OWN_HI) && a.bc[5] == 1;
+  if (!nlo && !nhi) return;
+  const int N = a.n[2] - 1;
+  T* u = U + base;
+  double s0 = 0.0, sN = 0.0;
+  for (int m = 1 + lane; m < N; m += 64) {
+    const double v = double(u[m]);
+    s0 = fma(double(drow0[m]), v, s0);
+    sN = fma(double(drowN[m]), v, sN);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o);
+    sN += __shfl_xor(sN, o);
+  }
+  if (lane != 0) return;
+  const double glo = g ? double(g[a.goff[4] + p]) : 0.0;
+  const double ghi = g ? double(g[a.goff[5] + p]) : 0.0;
+  if (nlo && nhi) {
+    const double r0 = -glo - s0, rN = ghi - sN;
+    const double det = m00 * mNN - m0N * mN0;
+    u[0] = T((r0 * mNN - m0N * rN) / det);
+    u[N] = T((m00 * rN - mN0 * r0) / det);
+  } else if (nlo) {
+    const double r0 = -glo - s0 - double(drow0[N]) * double(u[N]);
+    u[0] = T(r0 / m00);
+  } else {
+    const double rN = ghi - sN - double(drowN[0]) * double(u[0]);
+    u[N] = T(rN / mNN);
   }
 }
 
@@ -163,8 +226,12 @@ int lift_full(const cheb_plan* p, T* U, const T* g_faces, hipStream_t s) {
     if (p->g.bc[2 * ax] != 1 && p->g.bc[2 * ax + 1] != 1) continue;
     const int np = pencil_count(ax, a.n);
     const AxisConst& c = p->ax[ax];
-    hipLaunchKernelGGL(k_lift_axis<T>, dim3((np + 127) / 128), dim3(128), 0, s, U, g_faces, ax,
-                       plan_rows<T>(p, ax, 0), plan_rows<T>(p, ax, 1), c.m00, c.m0N, c.mN0, c.mNN, a);
+    if (ax == 2)
+      hipLaunchKernelGGL(k_lift_z_wave<T>, dim3((np + 3) / 4), dim3(256), 0, s, U, g_faces, plan_rows<T>(p, ax, 0),
+                         plan_rows<T>(p, ax, 1), c.m00, c.m0N, c.mN0, c.mNN, a);
+    else
+      hipLaunchKernelGGL(k_lift_axis<T>, dim3((np + 63) / 64), dim3(512), 0, s, U, g_faces, ax,
+                         plan_rows<T>(p, ax, 0), plan_rows<T>(p, ax, 1), c.m00, c.m0N, c.mN0, c.mNN, a);
   }
   return hip_check(hipGetLastError(), "lift_full");
 }
