@@ -15,7 +15,8 @@ THERMAL_BC = (O.DIRICHLET, O.NEUMANN, O.DIRICHLET, O.NEUMANN, O.NEUMANN, O.NEUMA
 CASES = [((17, 17, 17), THERMAL_BC, (0, 0, 0), (1, 1, 1)),
          ((19, 13, 9), BC_SETS["NDNNDN"], (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)),
          ((33, 17, 65), BC_SETS["DDNNNN"], (0, 0, 0), (1, 2, 1)),
-         ((5, 4, 3), BC_SETS["NNNNND"], (0, 0, 0), (1, 1, 1))]
+         ((5, 4, 3), BC_SETS["NNNNND"], (0, 0, 0), (1, 1, 1)),
+         ((129, 129, 129), THERMAL_BC, (0, 0, 0), (1, 1, 1))]
 
 
 def _state(n, seed):
