@@ -359,6 +359,70 @@ def thermal_newton_section(dev, levels=(8, 16, 32, 64, 128, 256), tol=1e-11, max
     return out
 
 
+def copy_reference(dev, n=64 * 1024 * 1024, reps=20):
+    """Attainable HBM bandwidth: the library's stream-copy kernel (cheb_debug_copy)
+    moving n doubles (512 MiB read + 512 MiB written, far beyond the 256 MB
+    Infinity Cache), event-timed on the current stream.  GB/s counts read plus
+    write bytes."""
+    import ctypes
+    import torch
+    from paper_2606_21410_amd import _lib as L
+    lib = L.load()
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream(dev)
+    h = ctypes.c_void_p(stream.cuda_stream)
+    for _ in range(3):
+        L.check(lib.cheb_debug_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, h))
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        L.check(lib.cheb_debug_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, h))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    ok = bool(torch.equal(src, dst))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1), "bytes_moved": 2 * n * 8, "ms": round(ms, 4),
+            "copy_checked": ok}
+
+
+def apply_257(dev, steps=40, warmup=5, rot=4):
+    """FP64 reduced apply on the 257^3 two-phase grid (the FFT route: the
+    matrix-core route covers N <= 128), rotating buffers, event-timed."""
+    import numpy as np
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan
+    P = W.two_phase_problem(257, seed=1002, n_finest=257)
+    shape = P.grid.n
+    plan = Plan(shape, P.grid.lo, P.grid.hi, P.grid.bc, "f64", device=dev)
+    K = torch.from_numpy(P.K).to(dev)
+    us = [torch.from_numpy(W.random_field(shape, 200 + i)).to(dev) for i in range(rot)]
+    ys = [torch.empty_like(us[0]) for _ in range(rot)]
+    for i in range(warmup):
+        plan.apply(K, us[i % rot], ys[i % rot], "reduced")
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(steps):
+        plan.apply(K, us[i % rot], ys[i % rot], "reduced")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    npts = float(np.prod(shape))
+    alg = (24.0 + 32.0 + 32.0) * npts / (ms * 1e-3) / 1e9
+    del us, ys, K, plan
+    torch.cuda.empty_cache()
+    return {"ms_per_apply": round(ms, 4), "gdofs": round(npts / (ms * 1e-3) / 1e9, 3),
+            "algorithmic_gbs": round(alg, 1), "frac": round(alg / HBM_PEAK_GBS, 4), "route": "fft"}
+
+
 def robin_section(dev, P, steps=100, warmup=10):
     """Robin rows on the metric workload: the 129^3 two-phase K with
     du/dn + u = 0 on its four former zero-flux faces (sigma = 1), reduced FP64
@@ -582,6 +646,12 @@ def main():
         flops = 2 * 2 * 2 * (nn // 2) * (nn // 2 + 1) * (nn - 2) ** 2
         roofline["mfma_tflops"] = round(flops / launch_s / 1e12, 2)
         roofline["mfma_frac"] = round(flops / launch_s / 78.6e12, 4)
+    _log("stream-copy reference and the 257^3 apply")
+    copy = copy_reference(dev)
+    roofline["copy_gbs"] = copy["gbs"]
+    roofline["frac_of_copy"] = round(achieved / copy["gbs"], 4)
+    a257 = apply_257(dev)
+    _log(f"copy {copy}; apply 257^3 {a257}")
     solve = None
     if not args.no_solve and n == 129:
         solve = solve_section(P, d, dev, shape)
@@ -642,6 +712,8 @@ def main():
         "picard_chain": chain,
         "inclusion_contrast_sweep": inclusion,
         "thermal_newton_chain": thermal,
+        "stream_copy": copy,
+        "apply_257": a257,
         "robin_rows": robin_rows,
     }
     print(json.dumps(out), flush=True)

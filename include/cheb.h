@@ -284,6 +284,13 @@ int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis);
  * Uses 4 fields of workspace.  Synchronises. */
 int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[3]);
 
+/* Copy of n doubles, src -> dst (device arrays, 16-byte aligned, not
+ * overlapping), by the library's stream-copy kernel: 16-byte loads and stores
+ * in a grid-stride loop.  The attainable HBM bandwidth the operator's roofline
+ * fraction is also quoted against (2 n * 8 bytes moved).  Asynchronous on
+ * `stream`. */
+int cheb_debug_copy(const void* src, void* dst, size_t n, void* stream);
+
 /* Dense GEMM on the matrix cores, D (I x C) = A (I x K) B (K x C), row-major
  * device arrays (double for CHEB_F64, float for CHEB_F32).  This is the
  * contraction kernel of the preconditioner, exposed so its MFMA lane layout can

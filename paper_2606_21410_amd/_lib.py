@@ -83,6 +83,7 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_int32)]),
     "cheb_derivative": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "cheb_flux_average": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "cheb_debug_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "cheb_debug_gemm": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp]),
     "cheb_batch_create": (ctypes.c_int, [ctypes.POINTER(cheb_grid), ctypes.c_int32, ctypes.c_int32, _vp,

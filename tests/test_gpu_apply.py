@@ -185,3 +185,23 @@ def test_apply_polynomial_exact():
     y = to_host(plan.apply(to_dev(P.K, torch.float64), to_dev(P.u_exact, torch.float64), mode="full"))
     F = O.full_rhs(G, P.f, P.g)
     assert np.max(np.abs(y - F)) <= 1e-9 * np.max(np.abs(F))
+
+
+def test_stream_copy_kernel():
+    """cheb_debug_copy (the bandwidth reference): exact copy with an odd length
+    (16-byte body plus a one-element tail); unaligned buffers are refused on the
+    host before any launch."""
+    require_gpu()
+    import ctypes
+    import torch
+    from paper_2606_21410_amd import _lib as L
+    lib = L.load()
+    n = 1_000_003
+    src = torch.randn(n + 2, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    L.check(lib.cheb_debug_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, None))
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n], src[:n]) and bool((dst[n:] == 0).all())
+    with pytest.raises(L.ChebError):
+        L.check(lib.cheb_debug_copy(ctypes.c_void_p(src.data_ptr() + 8), ctypes.c_void_p(dst.data_ptr()), 10,
+                                    None))
