@@ -239,7 +239,8 @@ int cheb_picard(cheb_plan* plan, const void* K0, const void* f, const void* g_fa
  * aligned, holding k(T), c_a = k'(T) D_a T (a = 0, 1, 2) and three scratch
  * fields; its contents are not kept between calls.  Every call fails with
  * CHEB_ERR_BAD_INPUT when k(T) is not finite and positive at some node
- * (1 + alpha T <= 0, or K0 <= 0). */
+ * (1 + alpha T <= 0, or K0 <= 0); cheb_newton checks this also at the cold
+ * start lift(0, g), which sets its residual scale, when a warm start is given. */
 int cheb_newton_work_bytes(const cheb_plan* plan, size_t* bytes);
 
 /* r = R(T) = sum_a D_a (k(T) D_a T) - f on interior nodes, 0 on boundary nodes
