@@ -455,10 +455,12 @@ namespace {
 
 // Stream copy with 16-byte accesses: the attainable-bandwidth reference the
 // operator's HBM roofline fraction is quoted against.
+// One 16-byte element per thread and one workgroup per 4 KiB: every wave
+// issues its load at launch, with no loop-carried address arithmetic.
 __global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
                                                      size_t n2) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) dst[i] = src[i];
 }
 
 __global__ void k_copy_tail(const double* src, double* dst, size_t from, size_t n) {
@@ -482,10 +484,13 @@ extern "C" int cheb_debug_copy(const void* src, void* dst, size_t n, void* strea
   hipStream_t s = (hipStream_t)stream;
   const size_t n2 = n / 2;
   if (n2) {
-    // eight resident 256-thread workgroups per CU on 256 CUs, grid-stride beyond
-    const size_t want = (n2 + 255) / 256;
-    const int blocks = (int)(want < 2048 ? want : 2048);
-    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, s, (const double2*)src, (double2*)dst, n2);
+    const size_t blocks = (n2 + 255) / 256;
+    if (blocks > 0x7fffffffULL) {
+      set_error("cheb_debug_copy: too many elements for one launch");
+      return CHEB_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const double2*)src, (double2*)dst,
+                       n2);
   }
   if (n & 1) hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, (const double*)src, (double*)dst, 2 * n2, n);
   return hip_check(hipGetLastError(), "cheb_debug_copy");
