@@ -236,8 +236,8 @@ int cheb_picard(cheb_plan* plan, const void* K0, const void* f, const void* g_fa
  * only (CHEB_ERR_UNSUPPORTED otherwise); the linear solves run in FP64.
  *
  * work: caller device buffer of cheb_newton_work_bytes() bytes, 256-byte
- * aligned, holding k(T), c_a = k'(T) D_a T (a = 0, 1, 2) and three scratch
- * fields; its contents are not kept between calls.  Every call fails with
+ * aligned, holding k(T), c_a = k'(T) D_a T (a = 0, 1, 2) and one scratch
+ * field; its contents are not kept between calls.  Every call fails with
  * CHEB_ERR_BAD_INPUT when k(T) is not finite and positive at some node
  * (1 + alpha T <= 0, or K0 <= 0); cheb_newton checks this also at the cold
  * start lift(0, g), which sets its residual scale, when a warm start is given. */

@@ -78,7 +78,8 @@ inline const float* dconst32(const cheb_plan* p, int a, int s) {
 }
 
 // ---- operator passes (pass_f64.hip / pass_f32.hip) ----
-// mode: 0 FULL, 1 REDUCED, 2 TRANSPOSE (reduced), 3 DERIV, 4 DERIV_T
+// mode: 0 FULL, 1 REDUCED, 2 TRANSPOSE (reduced), 3 DERIV, 4 DERIV_T,
+// 5 DERIV_ACC (y += D_a (K u) on interior nodes)
 template <typename T>
 int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T* K, const T* u, T* y,
                      hipStream_t s);

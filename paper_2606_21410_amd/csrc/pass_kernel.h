@@ -28,7 +28,10 @@
 
 namespace cheb {
 
-enum PassMode { MODE_FULL = 0, MODE_REDUCED = 1, MODE_TRANSPOSE = 2, MODE_DERIV = 3, MODE_DERIV_T = 4 };
+// MODE_DERIV_ACC: y += D_a (K * u) on the interior nodes of interior-transverse
+// pencils (the Newton Jacobian's k'(T) term, K standing for k'(T) D_a T)
+enum PassMode { MODE_FULL = 0, MODE_REDUCED = 1, MODE_TRANSPOSE = 2, MODE_DERIV = 3, MODE_DERIV_T = 4,
+                MODE_DERIV_ACC = 5 };
 
 template <typename T>
 struct PassArgs {
@@ -373,8 +376,9 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
   constexpr int EPT = NC > 0 ? (P * (NC + 1) + NT - 1) / NT : 8;
   constexpr int CHK = EPT < 24 ? EPT : 24;
   constexpr bool ONE = NC > 0 && CHK * NT >= P * (NC + 1);
-  constexpr bool NEEDK = (MODE != MODE_DERIV && MODE != MODE_DERIV_T);
-  constexpr bool ACC = (MODE == MODE_FULL || MODE == MODE_REDUCED || MODE == MODE_TRANSPOSE);
+  constexpr bool NEEDK = (MODE != MODE_DERIV && MODE != MODE_DERIV_T && MODE != MODE_DERIV_ACC);
+  constexpr bool ACC = (MODE == MODE_FULL || MODE == MODE_REDUCED || MODE == MODE_TRANSPOSE ||
+                        MODE == MODE_DERIV_ACC);
   constexpr bool PRE_K = ONE && NEEDK && CHK <= 12;  // K held in registers through the first derivative
   constexpr bool PRE_Y = ONE && ACC && CHK <= 12;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -436,8 +440,10 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
         const int fl = flags[pl];
         if (fl & PF_VALID) {
           const int ad = base[pl] + m * stride;
-          const bool ld = (MODE == MODE_FULL || MODE == MODE_DERIV || MODE == MODE_DERIV_T) || (fl & PF_TIN);
-          if (ld) v[c] = a.u[ad];
+          const bool ld = (MODE == MODE_FULL || MODE == MODE_DERIV || MODE == MODE_DERIV_T ||
+                           MODE == MODE_DERIV_ACC) || (fl & PF_TIN);
+          if (MODE == MODE_DERIV_ACC) v[c] = a.u[ad] * a.K[ad];
+          else if (ld) v[c] = a.u[ad];
           if (PRE_K) kv[PRE_K ? c : 0] = a.K[ad];
           if (PRE_Y && !a.first && (fl & PF_TIN) && m != 0 && m != N) yv[c] = a.y[ad];
         }
@@ -593,6 +599,8 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
         a.y[ad] = x;
       } else if (MODE == MODE_DERIV_T) {
         a.y[ad] = isend ? x : T(2) * x;
+      } else if (MODE == MODE_DERIV_ACC) {
+        if ((fl & PF_TIN) && !isend) a.y[ad] = a.first ? x : yold + x;
       } else if (MODE == MODE_FULL) {
         if (!isend) {
           if (fl & PF_TIN) a.y[ad] = a.first ? x : yold + x;

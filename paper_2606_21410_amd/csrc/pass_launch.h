@@ -39,6 +39,7 @@ static int launch_pass_mode(const PassArgs<T>& a, int mode, hipStream_t s) {
     case MODE_TRANSPOSE: return launch_pass_inst<T, NC, MODE_TRANSPOSE>(a, s);
     case MODE_DERIV: return launch_pass_inst<T, NC, MODE_DERIV>(a, s);
     case MODE_DERIV_T: return launch_pass_inst<T, NC, MODE_DERIV_T>(a, s);
+    case MODE_DERIV_ACC: return launch_pass_inst<T, NC, MODE_DERIV_ACC>(a, s);
     default: set_error("bad pass mode"); return CHEB_ERR_INVALID_ARG;
   }
 }

@@ -458,12 +458,12 @@ int solve_plain(cheb_plan* p, const T* K, const T* bt, T* x, T* r, KrylovWS<T>& 
 
 // Newton iteration for k(x, T) = K0(x) / (1 + alpha T) (Section 3.4).  Fields of
 // the caller's work array, each padded to 256 bytes: k(T), c_a = k'(T) D_a T for
-// a = 0, 1, 2, three scratch fields (lifted direction, product, derivative) and
-// a 256-byte flag slot.
-constexpr int kNewtonFields = 7;
+// a = 0, 1, 2, the lifted direction (also k'(T) while linearising) and a
+// 256-byte flag slot.
+constexpr int kNewtonFields = 5;
 
 struct NewtonWS {
-  double *k, *c[3], *V, *tw, *td;
+  double *k, *c[3], *V;
   int* flag;
 };
 
@@ -473,8 +473,6 @@ NewtonWS newton_ws(const cheb_plan* p, void* work) {
   w.k = c.take<double>(p->npts);
   for (int a = 0; a < 3; ++a) w.c[a] = c.take<double>(p->npts);
   w.V = c.take<double>(p->npts);
-  w.tw = c.take<double>(p->npts);
-  w.td = c.take<double>(p->npts);
   w.flag = c.take<int>(64);
   return w;
 }
@@ -502,19 +500,16 @@ int newton_linearise(cheb_plan* p, const double* K0, double alpha, const double*
 }
 
 // y = J(T) v on interior rows (boundary rows 0): the reduced operator with
-// coefficient k(T), plus sum_a D_a (c_a V) with V the homogeneous lift of v.
+// coefficient k(T), plus sum_a D_a (c_a V) with V the homogeneous lift of v;
+// each axis' term is one accumulating derivative pass that multiplies by c_a
+// as it loads V.
 int newton_jv(cheb_plan* p, NewtonWS& w, const double* v, double* y) {
   hipStream_t s = p->stream;
   int rc = apply_t<double>(p, w.k, v, y, 1, s);
   if (!rc) rc = copy_scale<double>(w.V, v, 1.0, p->npts, s);
   if (!rc) rc = mask_interior<double>(w.V, p->g.n, s);
   if (!rc) rc = lift_full<double>(p, w.V, nullptr, s);
-  for (int a = 0; a < 3 && !rc; ++a) {
-    rc = vmul(w.tw, w.c[a], w.V, p->npts, s);
-    if (!rc) rc = launch_axis_pass<double>(p, a, 3, 1, nullptr, w.tw, w.td, s);
-    if (!rc) rc = axpby<double>(y, w.td, 1.0, 1.0, p->npts, s);
-  }
-  if (!rc) rc = mask_interior<double>(y, p->g.n, s);
+  for (int a = 0; a < 3 && !rc; ++a) rc = launch_axis_pass<double>(p, a, 5, 0, w.c[a], w.V, y, s);
   return rc;
 }
 
