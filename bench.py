@@ -76,6 +76,39 @@ def cpu_baseline(P, seconds_budget=15.0):
                       f"{el:.1f} s wall"}
 
 
+def cpu_detail(P, seconds_budget=4.0):
+    """More oracle timings on the host: the same 129^3 reduced apply with one
+    BLAS thread (bounded sample), and the oracle's solve of the 33^3 two-phase
+    problem (spheres R = 0.15, vf 0.2, contrast 10, seed 1002; FDM-preconditioned
+    GMRES to 1e-13), median of three, with all threads."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import cheb_oracle as O
+    from paper_2606_21410_amd import workloads as W
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc)
+    u = W.random_field(P.grid.n, 3)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            O.apply_reduced(G, P.K, u)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > seconds_budget or reps >= 200:
+                break
+    one = float(np.prod(P.grid.n)) * reps / el / 1e9
+    Q = W.two_phase_problem(33, seed=1002, n_finest=33)
+    Gq = O.Grid3(Q.grid.n, Q.grid.lo, Q.grid.hi, Q.grid.bc)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        O.solve(Gq, Q.K, Q.f, Q.g, tol=1e-13)
+        times.append(time.perf_counter() - t0)
+    return {"apply_1thread_gdofs": one, "apply_1thread_sample": f"{reps} applies, {el:.1f} s",
+            "solve_33_seconds_median": round(sorted(times)[1], 3),
+            "solve_33_kind": "oracle FDM-preconditioned GMRES to 1e-13, all threads"}
+
+
 def _solve_once(P, shape, prec, opts, K, f, g, u0, dev):
     """One timed solve on a fresh plan (plan set-up, preconditioner set-up and
     the solve are inside the timed region; the workspace is allocated before)."""
@@ -682,9 +715,12 @@ def main():
         batch = homogenisation_section(dev)
 
     cpu = None
+    cpu_more = None
     if not args.no_cpu:
         _log("cpu baseline (oracle)")
         cpu = cpu_baseline(P)
+        cpu_more = cpu_detail(P)
+        _log(f"cpu detail {cpu_more}")
 
     out = {
         "metric": "GDOF/s operator apply + time-to-1e-8 solve @129^3, mixed vs FP64, 1 GPU",
@@ -707,6 +743,7 @@ def main():
                              if kk != "wall_s"} for k, v in res.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_detail": cpu_more,
         "time_to_1e-8_129": solve,
         "homogenisation_batch": batch,
         "picard_chain": chain,
