@@ -205,3 +205,30 @@ def test_stream_copy_kernel():
     with pytest.raises(L.ChebError):
         L.check(lib.cheb_debug_copy(ctypes.c_void_p(src.data_ptr() + 8), ctypes.c_void_p(dst.data_ptr()), 10,
                                     None))
+
+
+@pytest.mark.parametrize("n", [(513, 3, 3), (3, 513, 4), (5, 3, 513), (3, 3, 3)])
+def test_extreme_shapes(n):
+    """The largest axis the ABI accepts (513 nodes, a length-1024 transform on
+    the generic path) and the smallest (3 nodes), FULL, REDUCED and transposed
+    applies against the oracle, and a preconditioned solve against dense LU."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    d = lambda a: to_dev(a, torch.float64)
+    bc = BC_SETS["NDNNDN"]
+    G, u, K = _case(n, bc, 700)
+    plan = Plan(n, G.lo, G.hi, bc, "f64")
+    for mode, fn in (("full", O.apply_full), ("reduced", O.apply_reduced),
+                     ("transpose", O.apply_reduced_transpose)):
+        y = to_host(plan.apply(d(K), d(u), mode=mode))
+        assert rel_l2(y, fn(G, K, u)) <= 1e-12, mode
+    f = W.random_field(n, 701)
+    g = W.random_faces(W.Grid(n, G.lo, G.hi, bc), 702)
+    U = O.solve_dense(G, K, f, g)
+    x, info = plan.solve(d(K), d(f), d(g), opts=SolveOptions(rtol=1e-10, precond=True, maxiter=4000))
+    e = rel_l2(to_host(x), U)
+    log(f"extreme {n}: {info['matvecs']} matvecs, rel diff to LU {e:.2e}")
+    # a 513-node axis puts the condition number near N^4 ~ 7e10: FP64 rounding
+    # alone, in either solution, moves it by ~1e-16 * 7e10, so the bar is 1e-5
+    assert info["rc"] == 0 and e <= 1e-5
