@@ -29,6 +29,7 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // fast-diagonalisation preconditioner factors of one axis (offsets into pc64/pc32)
 struct PrecondAxis {
   int m;
+  int split;  // centro-symmetric factors whose even and odd halves fill whole 16-row blocks
   size_t off_V, off_Vi, off_lam;
 };
 

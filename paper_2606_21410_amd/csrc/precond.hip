@@ -419,9 +419,21 @@ struct FdmArgs {
 enum { FDM_XFULL = 1, FDM_YFULL = 2, FDM_SCALE = 4 };
 constexpr int kFdmMaxNb = 256;  // blocks whose offsets and Kc a workgroup keeps in LDS
 
-template <typename T, int MP, int MODE>
+// SPLIT (axes whose 1-D operator is centro-symmetric, so that the factors are
+// V = Q diag(Vs, Vw) and V^{-1} = diag(Vs^{-1}, Vw^{-1}) Q^T with Q the
+// symmetric / antisymmetric node-pair basis; modes ordered symmetric first):
+//   1  the input enters through Q^T: the tile is restaged as pair sums
+//      x_j + x_{m-1-j} (rows j < ps, the middle node kept) and differences
+//      (rows ps + j), and each output row contracts with one half only;
+//   2  the output leaves through Q: rows i < ps hold the symmetric part a_i,
+//      rows ps + i the antisymmetric part b_i, and node k receives a_k + b_k,
+//      a_i - b_i (k = m-1-i) or a_p (the middle node).
+// Either way every row does half the multiply-adds.  Needs ps = ceil(m/2) to
+// be a multiple of 16, so that a wave's 16 rows are all of one half.
+template <typename T, int MP, int MODE, int SPLIT>
 __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
   constexpr int NW = MP / 16, NT = 64 * NW, C = 16, SC = C + 1, KS = MP / 4;
+  constexpr int KSE = SPLIT ? MP / 8 : KS;  // k-steps each row block runs
   constexpr int EPT = MP * C / NT;  // = 4
   constexpr bool XF = MODE & FDM_XFULL, YF = MODE & FDM_YFULL, SCL = MODE & FDM_SCALE;
   constexpr bool FULL = XF || YF;
@@ -519,13 +531,25 @@ __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
   T v[EPT];
   load(0, v);
   // fragments of M: rows 16 wave + li, the whole K range (zero past m)
-  T a[KS];
+  T a[KSE];
   const int row = 16 * wave + li;
+  const int ps = (m + 1) / 2, ph = m / 2;       // symmetric / antisymmetric halves
+  const bool anti = SPLIT && 16 * wave >= ps;   // uniform per wave
+  const int xoff = anti ? ps : 0;               // first LDS row of the operand half
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
+  for (int ks = 0; ks < KSE; ++ks) {
     const int k = 4 * ks + lk;
-    const size_t at = g.trans ? (size_t)k * m + row : (size_t)row * m + k;
-    a[ks] = (row < m && k < m) ? M[at] : T(0);
+    int r = row, col = k;
+    bool ok = row < m && k < m;
+    if (SPLIT == 1) {
+      ok = row < m && k < (anti ? ph : ps);
+    } else if (SPLIT == 2) {
+      r = anti ? row - ps : row;
+      col = anti ? ps + k : k;
+      ok = r < (anti ? ph : ps) && k < (anti ? ph : ps);
+    }
+    const size_t at = g.trans ? (size_t)col * m + r : (size_t)r * m + col;
+    a[ks] = ok ? M[at] : T(0);
   }
   for (int e = tid; e < (MP - m) * SC; e += NT) Xs[m * SC + e] = T(0);
   for (; tile < ntiles; tile += gridDim.x, slot ^= 1) {
@@ -541,9 +565,34 @@ __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
     cols(tile + gridDim.x, slot ^ 1);
     __syncthreads();
     load(slot ^ 1, v);  // the next tile, in flight during this one
+    if (SPLIT == 1) {
+      // node pairs (j, m-1-j), j < ph, into sums (row j) and differences (row ps + j)
+      constexpr int PPT = (MP / 2 * C + NT - 1) / NT;
+      T xa[PPT], xb[PPT];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int e = tid + q * NT;
+        if (e < ph * C) {
+          const int j = e / C, c = e - j * C;
+          xa[q] = Xs[j * SC + c];
+          xb[q] = Xs[(m - 1 - j) * SC + c];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int e = tid + q * NT;
+        if (e < ph * C) {
+          const int j = e / C, c = e - j * C;
+          Xs[j * SC + c] = xa[q] + xb[q];
+          Xs[(ps + j) * SC + c] = xa[q] - xb[q];
+        }
+      }
+      __syncthreads();
+    }
     V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) acc = Mfma<T>::mac(a[ks], Xs[(4 * ks + lk) * SC + li], acc);
+    for (int ks = 0; ks < KSE; ++ks) acc = Mfma<T>::mac(a[ks], Xs[(xoff + 4 * ks + lk) * SC + li], acc);
     __syncthreads();  // every wave has read the tile
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -558,7 +607,14 @@ __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
         const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
         const int b = pby[slot][c];
         if (b >= 0) {
-          T val = Xs[k * SC + c];
+          T val;
+          if (SPLIT == 2) {
+            if (k < ph) val = Xs[k * SC + c] + Xs[(ps + k) * SC + c];
+            else if (k >= m - ph) val = Xs[(m - 1 - k) * SC + c] - Xs[(ps + m - 1 - k) * SC + c];
+            else val = Xs[k * SC + c];  // the middle node of odd m
+          } else {
+            val = Xs[k * SC + c];
+          }
           if (SCL)
             val = T(double(val) * pik[SCL ? slot : 0][c] / (psc[SCL ? slot : 0][c] + double(lam_s[SCL ? axis : 0][k])));
           Y[b + k * sya] = val;
@@ -742,6 +798,11 @@ int precond_setup(cheb_plan* p) {
     const std::vector<double>& V = Vv[src[a]];
     const std::vector<double>& Vi = Viv[src[a]];
     ax[a].m = m;
+    // the even-odd contraction needs the centro-symmetric factors and whole
+    // 16-row halves
+    const int sa = src[a];
+    const bool centro_a = p->g.bc[2 * sa] == p->g.bc[2 * sa + 1] && p->g.robin[2 * sa] == p->g.robin[2 * sa + 1];
+    ax[a].split = centro_a && m <= 128 && ((m + 1) / 2) % 16 == 0 ? 1 : 0;
     ax[a].off_V = off64;
     host.insert(host.end(), V.begin(), V.end());
     off64 += (size_t)m * m;
@@ -777,7 +838,7 @@ const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
 
 // persistent launch: as many workgroups as the device holds at once (queried
 // once per instantiation), at most one per tile
-template <typename T, int MP, int MODE>
+template <typename T, int MP, int MODE, int SPLIT>
 static int launch_fdm(const FdmArgs& f, hipStream_t s) {
   static int resident = 0;
   if (resident == 0) {
@@ -785,7 +846,8 @@ static int launch_fdm(const FdmArgs& f, hipStream_t s) {
     int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
     if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     if (!rc)
-      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fdm_contract<T, MP, MODE>,
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                                  (const void*)k_fdm_contract<T, MP, MODE, SPLIT>,
                                                                   4 * MP, 0),
                      "occupancy query");
     if (rc) return rc;
@@ -794,31 +856,55 @@ static int launch_fdm(const FdmArgs& f, hipStream_t s) {
   const long long npen = (long long)f.m0 * f.m1 * f.m2 / f.m * f.nb;
   const long long tiles = (npen + 15) / 16;
   const int grid = (int)(tiles < resident ? (tiles > 0 ? tiles : 1) : resident);
-  hipLaunchKernelGGL((k_fdm_contract<T, MP, MODE>), dim3(grid), dim3(4 * MP), 0, s, f);
+  hipLaunchKernelGGL((k_fdm_contract<T, MP, MODE, SPLIT>), dim3(grid), dim3(4 * MP), 0, s, f);
   return hip_check(hipGetLastError(), "axis contraction");
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int SPLIT>
 static int launch_fdm_mode(const FdmArgs& f, hipStream_t s) {
-  switch ((f.m + 15) / 16) {
-    case 1: return launch_fdm<T, 16, MODE>(f, s);
-    case 2: return launch_fdm<T, 32, MODE>(f, s);
-    case 3: return launch_fdm<T, 48, MODE>(f, s);
-    case 4: return launch_fdm<T, 64, MODE>(f, s);
-    case 5: return launch_fdm<T, 80, MODE>(f, s);
-    case 6: return launch_fdm<T, 96, MODE>(f, s);
-    case 7: return launch_fdm<T, 112, MODE>(f, s);
-    default: return launch_fdm<T, 128, MODE>(f, s);
+  if constexpr (SPLIT != 0) {
+    // only the widths whose halves are whole 16-row blocks
+    switch ((f.m + 15) / 16) {
+      case 2: return launch_fdm<T, 32, MODE, SPLIT>(f, s);
+      case 4: return launch_fdm<T, 64, MODE, SPLIT>(f, s);
+      case 6: return launch_fdm<T, 96, MODE, SPLIT>(f, s);
+      case 8: return launch_fdm<T, 128, MODE, SPLIT>(f, s);
+      default: set_error("even-odd contraction: unsupported width"); return CHEB_ERR_INVALID_ARG;
+    }
+  } else {
+    switch ((f.m + 15) / 16) {
+      case 1: return launch_fdm<T, 16, MODE, 0>(f, s);
+      case 2: return launch_fdm<T, 32, MODE, 0>(f, s);
+      case 3: return launch_fdm<T, 48, MODE, 0>(f, s);
+      case 4: return launch_fdm<T, 64, MODE, 0>(f, s);
+      case 5: return launch_fdm<T, 80, MODE, 0>(f, s);
+      case 6: return launch_fdm<T, 96, MODE, 0>(f, s);
+      case 7: return launch_fdm<T, 112, MODE, 0>(f, s);
+      default: return launch_fdm<T, 128, MODE, 0>(f, s);
+    }
   }
 }
 
+// split: 0 plain, 1 input through Q^T (the V^{-1} half), 2 output through Q
+// (the V half); see k_fdm_contract
 template <typename T>
-static int launch_fdm_m(const FdmArgs& f, int mode, hipStream_t s) {
+static int launch_fdm_m(const FdmArgs& f, int mode, int split, hipStream_t s) {
+  if (split == 1) {
+    switch (mode) {
+      case FDM_XFULL: return launch_fdm_mode<T, FDM_XFULL, 1>(f, s);
+      case FDM_SCALE: return launch_fdm_mode<T, FDM_SCALE, 1>(f, s);
+      default: return launch_fdm_mode<T, 0, 1>(f, s);
+    }
+  }
+  if (split == 2) {
+    if (mode == FDM_YFULL) return launch_fdm_mode<T, FDM_YFULL, 2>(f, s);
+    return launch_fdm_mode<T, 0, 2>(f, s);
+  }
   switch (mode) {
-    case FDM_XFULL: return launch_fdm_mode<T, FDM_XFULL>(f, s);
-    case FDM_YFULL: return launch_fdm_mode<T, FDM_YFULL>(f, s);
-    case FDM_SCALE: return launch_fdm_mode<T, FDM_SCALE>(f, s);
-    default: return launch_fdm_mode<T, 0>(f, s);
+    case FDM_XFULL: return launch_fdm_mode<T, FDM_XFULL, 0>(f, s);
+    case FDM_YFULL: return launch_fdm_mode<T, FDM_YFULL, 0>(f, s);
+    case FDM_SCALE: return launch_fdm_mode<T, FDM_SCALE, 0>(f, s);
+    default: return launch_fdm_mode<T, 0, 0>(f, s);
   }
 }
 
@@ -839,7 +925,7 @@ static int axis_contract(const T* M, bool trans, int axis, const int* m, const T
     f.m0 = m[0];
     f.m1 = m[1];
     f.m2 = m[2];
-    return launch_fdm_m<T>(f, 0, s);
+    return launch_fdm_m<T>(f, 0, 0, s);
   }
   GemmArgs g;
   const long long msz = m[axis];
@@ -912,7 +998,7 @@ static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bu
       f.sys = sys;
       f.kc = kc;
     }
-    return launch_fdm_m<T>(f, mode, s);
+    return launch_fdm_m<T>(f, mode, p->pc_ax[a].split ? (fwd ? 1 : 2) : 0, s);
   };
   int rc = run(0, true, in, bufA, FDM_XFULL);
   if (!rc) rc = run(1, true, bufA, bufB, 0);
