@@ -159,3 +159,47 @@ def test_rejections():
     Plan((9, 9, 9), bc=(N_,) * 6, robin=(0, 0, 0, 0, 0, 0.5)).close()
     with pytest.raises(L.ChebError):
         Batch([((9, 9, 9), (0, 0, 0), (1, 1, 1), (D_, N_, N_, N_, N_, N_), (0, 1.0, 0, 0, 0, 0))])
+
+
+@pytest.mark.parametrize("name", ["mixed", "allrobin"])
+def test_f32_solve_vs_oracle(name):
+    """FP32 plan with Robin rows: the solve against the oracle's dense LU, at
+    FP32 accuracy (rtol 1e-5 on the reduced system)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import SolveOptions
+    n = (17, 17, 17)
+    plan, G = _plan(n, name, "f32")
+    K = W.random_conductivity(n, 450, 0.5)
+    f = W.random_field(n, 451)
+    g = W.random_faces(W.Grid(n, LO, HI, G.bc), 452)
+    Uo = O.solve_dense(G, K, f, g)
+    d = lambda a: to_dev(a, torch.float32)
+    u, info = plan.solve(d(K), d(f), d(g), opts=SolveOptions(rtol=1e-5, precond=True))
+    e = rel_l2(to_host(u), Uo)
+    log(f"robin f32 {name}: {info['matvecs']} matvecs, rel {e:.2e}")
+    assert info["rc"] == 0 and e <= 1e-3
+
+
+def test_graph_replay_matches_eager():
+    """Reduced applies with Robin rows captured in a HIP graph and replayed three
+    times, with eager work in between: every replay equals the eager result."""
+    require_gpu()
+    import torch
+    n = (33, 33, 33)
+    plan, G = _plan(n, "allrobin", "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    K = d(W.random_conductivity(n, 460, 0.5))
+    us = [d(W.random_field(n, 461 + i)) for i in range(3)]
+    ys = [torch.empty_like(us[0]) for _ in range(3)]
+    ref = [to_host(plan.apply(K, u, mode="reduced")) for u in us]
+    graph = plan.capture_applies(K, us, ys, "reduced")
+    for rep in range(3):
+        for y in ys:
+            y.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        for y, r in zip(ys, ref):
+            assert np.array_equal(to_host(y), r), rep
+        plan.apply(K, us[0], mode="full")  # eager work between replays
+        torch.cuda.synchronize()
