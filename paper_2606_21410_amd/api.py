@@ -52,7 +52,10 @@ _ROUTE = {"auto": L.CHEB_ROUTE_AUTO, "fft": L.CHEB_ROUTE_FFT, "matrix": L.CHEB_R
 
 
 class Plan:
-    """One grid: sizes, box, face types, precision ('f64', 'f32', 'mixed')."""
+    """One grid: sizes, box, face types, precision ('f64', 'f32', 'mixed').
+
+    ``robin``: six coefficients sigma, one per face; a Neumann face with sigma != 0
+    carries the Robin row du/dn + sigma u = g (cheb_grid.robin)."""
 
     def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0,) * 6, precision="f64",
                  device="cuda", route: str = "auto", robin=None):
