@@ -738,9 +738,9 @@ def newton(G: Grid3, K0, alpha: float, f, g, tol=1e-10, max_steps=50, U0=None, l
     T_m = lift(x_m, g); stop once ||R(T_m)|| <= tol r_ref, r_ref = ||R(lift(0, g))||
     (the paper states no stopping rule; this one judges warm and cold starts on
     the same scale); otherwise solve J(T_m) dx = -R(T_m) by GMRES (preconditioned
-    by the constant-coefficient inverse at the mean of k(T_m)) to a relative
-    residual max(lin_tol, tol r_ref / (10 ||R(T_m)||)) and set x_{m+1} = x_m + dx.
-    Returns (T, steps, gmres iterations per step)."""
+    by the constant-coefficient inverse at the mean of k(T_m)) to the relative
+    residual lin_tol -- an exact Newton step up to that tolerance -- and set
+    x_{m+1} = x_m + dx.  Returns (T, steps, gmres iterations per step)."""
     K0 = np.broadcast_to(np.asarray(K0, dtype=np.float64), G.n)
     rref = float(np.linalg.norm(newton_residual(G, K0, alpha, lift(G, np.zeros(G.n), g), f)))
     x = np.zeros(G.n) if U0 is None else np.where(G.interior, U0, 0.0)
@@ -763,7 +763,7 @@ def newton(G: Grid3, K0, alpha: float, f, g, tol=1e-10, max_steps=50, U0=None, l
         def pc(v):
             return fdm.solve(v.reshape(G.n)).ravel()
 
-        dx, it, _ = gmres(mv, (-R).ravel(), pc, tol=max(lin_tol, 0.1 * tol * rref / rn))
+        dx, it, _ = gmres(mv, (-R).ravel(), pc, tol=lin_tol)
         its.append(it)
         x = x + np.where(G.interior, dx.reshape(G.n), 0.0)
         T = lift(G, x, g)

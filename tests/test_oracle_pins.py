@@ -296,6 +296,26 @@ def test_prolong_injection_and_polynomials():
     assert O.e_ref(Uf, Uf) == 0.0
 
 
+def test_e_ref_normalisation_hand_computed():
+    """e_ref = ||U_f - P U_c||_2 / ||U_f||_2 over the fine nodes (Section 2.3.3,
+    refinement indicator), on pairs worked out by hand: the solved fine field
+    carries the denominator (3-4-5 triangle: 3/5, not 3/4 with the prolonged
+    field's norm), and the norm is the Euclidean one over all nodes (1/2, where a
+    max norm would give 1)."""
+    Uf = np.zeros((2, 2, 2))
+    Up = np.zeros((2, 2, 2))
+    Uf[0, 0, 0], Uf[1, 1, 1] = 3.0, 4.0
+    Up[1, 1, 1] = 4.0
+    assert O.e_ref(Uf, Up) == pytest.approx(0.6, rel=1e-15)
+    # the argument order matters: normalised by the other field it would be 3/4
+    assert O.e_ref(Up, Uf) == pytest.approx(0.75, rel=1e-15)
+    A = np.ones((1, 2, 2))
+    B = A.copy()
+    B[0, 0, 0] = 0.0
+    assert O.e_ref(A, B) == pytest.approx(0.5, rel=1e-15)
+    assert O.e_ref(Uf, np.zeros_like(Uf)) == 1.0
+
+
 # ------------------------------------------------------ quadrature / Keff ---
 
 @pytest.mark.parametrize("N", [4, 16, 64])
