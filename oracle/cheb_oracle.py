@@ -678,11 +678,13 @@ def adjoint_reduced(G: Grid3, K, U, dLdU, tol=1e-13):
 
 def picard(G: Grid3, K0, f, g, tol=1e-10, max_steps=100, U0=None, lin_tol=1e-13):
     """Lagged-coefficient Picard: solve div(K0 (1 + u_m^2/2) grad u_{m+1}) = f
-    until ||u_{m+1} - u_m|| / ||u_{m+1}|| <= tol.  Returns (U, steps)."""
+    until ||u_{m+1} - u_m|| / ||u_{m+1}|| <= tol.  Each linear solve starts its
+    GMRES from the previous iterate (the solution of each linear system does not
+    depend on the starting guess).  Returns (U, steps)."""
     U = np.zeros(G.n) if U0 is None else U0.copy()
     for step in range(1, max_steps + 1):
         K = K0 * (1.0 + 0.5 * U * U)
-        Un = solve(G, K, f, g, tol=lin_tol)
+        Un = solve(G, K, f, g, tol=lin_tol, x0=U)
         rel = np.linalg.norm(Un - U) / max(np.linalg.norm(Un), 1e-300)
         U = Un
         if rel <= tol:

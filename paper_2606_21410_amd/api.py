@@ -522,13 +522,28 @@ def prolong(coarse: Plan, fine: Plan, uc, uf=None, uf_solved=None):
     return uf, (e.value if uf_solved is not None else None)
 
 
+class SolveNotConverged(L.ChebError):
+    """A solve inside autograd ended with a soft status (not converged or
+    stagnated): its output is the best iterate, not the solution, so neither
+    it nor a gradient computed from it is returned.  ``info`` holds the
+    solver's report."""
+
+    def __init__(self, what: str, info: dict):
+        super().__init__(info["status"], f"{what} ended with status {info['status']} "
+                                         f"(relres {info['relres_final']:.3e}, {info['matvecs']} matvecs)")
+        self.info = info
+
+
 class ChebSolveFn(torch.autograd.Function):
-    """u = solve(K = exp(logK)); backward: dL/dlogK through cheb_adjoint."""
+    """u = solve(K = exp(logK)); backward: dL/dlogK through cheb_adjoint.
+    Both solves must converge (status 0); otherwise SolveNotConverged is raised."""
 
     @staticmethod
     def forward(ctx, logK, plan: Plan, f, g, opts):
         K = torch.exp(logK).contiguous()
-        u, _ = plan.solve(K, f, g, opts=opts)
+        u, info = plan.solve(K, f, g, opts=opts)
+        if info["status"] != 0:
+            raise SolveNotConverged("forward solve", info)
         ctx.plan, ctx.opts = plan, opts
         ctx.save_for_backward(K, u)
         return u
@@ -536,7 +551,9 @@ class ChebSolveFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         K, u = ctx.saved_tensors
-        _, grad, _ = ctx.plan.adjoint(K, u, grad_u.contiguous(), ctx.opts)
+        _, grad, info = ctx.plan.adjoint(K, u, grad_u.contiguous(), ctx.opts)
+        if info["status"] != 0:
+            raise SolveNotConverged("adjoint solve", info)
         return grad, None, None, None, None
 
 

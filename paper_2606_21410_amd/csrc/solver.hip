@@ -715,6 +715,10 @@ int cheb_adjoint(cheb_plan* plan, const void* K, const void* u, const void* dLdu
   }
   cheb_plan* p = plan;
   SolveParams sp = params_from(opts);
+  if (sp.m < 1 || sp.m > 64 || sp.k < 0 || sp.k > 6) {
+    set_error("inner_m must be in [1, 64] and outer_k in [0, 6]");
+    return CHEB_ERR_INVALID_ARG;
+  }
   sp.warm = false;
   SolveWS64 w;
   const size_t need = carve64(p, sp, nullptr, w);

@@ -299,11 +299,26 @@ def sphere_conductivity(grid: Grid, centres: np.ndarray, radius: float, k_inc: f
     if width is None:
         nf = n_finest if n_finest is not None else grid.n[0]
         width = 2.0 * (grid.hi[0] - grid.lo[0]) / (nf - 1)
-    X, Y, Z = grid.mesh()
-    chi = np.zeros_like(X)
+    xs = grid.coords()
+    chi = np.zeros(grid.n)
+    # tanh(t) rounds to 1 in FP64 for t > 19.1, so chi_s is exactly 0 farther
+    # than R + 20 w from the centre: each sphere only touches the nodes of its
+    # bounding box (the same values as evaluating it everywhere)
+    reach = radius + 20.0 * width
     for c in centres:
-        d = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
-        chi = np.maximum(chi, 0.5 * (1.0 - np.tanh((d - radius) / width)))
+        sl = []
+        for a in range(3):
+            i0 = int(np.searchsorted(xs[a], c[a] - reach, side="left"))
+            i1 = int(np.searchsorted(xs[a], c[a] + reach, side="right"))
+            sl.append(slice(i0, i1))
+        if any(s_.stop <= s_.start for s_ in sl):
+            continue
+        dx = (xs[0][sl[0]] - c[0]) ** 2
+        dy = (xs[1][sl[1]] - c[1]) ** 2
+        dz = (xs[2][sl[2]] - c[2]) ** 2
+        d = np.sqrt(dx[:, None, None] + dy[None, :, None] + dz[None, None, :])
+        blk = chi[sl[0], sl[1], sl[2]]
+        np.maximum(blk, 0.5 * (1.0 - np.tanh((d - radius) / width)), out=blk)
     return k_mat + (k_inc - k_mat) * chi
 
 

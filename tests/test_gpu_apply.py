@@ -101,20 +101,53 @@ def test_apply_transpose_dot_identity(n):
 
 @pytest.mark.parametrize("n", [(129, 129, 129)])
 def test_apply_129_full(n):
-    """The metric grid: full parity at 129^3 (FP64 and FP32)."""
+    """The metric grid: every output element at 129^3 against the oracle, in
+    all three modes (FULL, REDUCED, REDUCED|TRANSPOSE) in FP64, REDUCED in FP32."""
     require_gpu()
     import torch
     from paper_2606_21410_amd.api import Plan
     bc = W.MIXED_X_BC
-    log(f"apply 129^3")
     G, u, K = _case(n, bc, 500, (0, 0, 0), (1, 1, 1))
-    ref = O.apply_reduced(G, K, u)
     plan = Plan(n, G.lo, G.hi, bc, "f64")
-    y = to_host(plan.apply(to_dev(K, torch.float64), to_dev(u, torch.float64), mode="reduced"))
-    assert rel_l2(y, ref) <= F64_TOL
+    Kd, ud = to_dev(K, torch.float64), to_dev(u, torch.float64)
+    for mode, fn in (("full", O.apply_full), ("reduced", O.apply_reduced),
+                     ("transpose", O.apply_reduced_transpose)):
+        log(f"apply 129^3 {mode}")
+        ref = fn(G, K, u)
+        y = to_host(plan.apply(Kd, ud, mode=mode))
+        assert rel_l2(y, ref) <= F64_TOL, mode
+        if mode == "reduced":
+            ref_r = ref
     p32 = Plan(n, G.lo, G.hi, bc, "f32")
     y32 = to_host(p32.apply(to_dev(K, torch.float32), to_dev(u, torch.float32), mode="reduced"))
-    assert rel_l2(y32, ref) <= F32_TOL
+    assert rel_l2(y32, ref_r) <= F32_TOL
+
+
+@pytest.mark.timeout(600)
+def test_apply_257_full_vs_oracle():
+    """257^3, the largest level of the refinement chain (FFT route, transform
+    length 512): every element of the REDUCED and REDUCED|TRANSPOSE applies
+    against the oracle's dense-D tensor contractions, on the two-phase K of the
+    129^3 workload's generator and a random input."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    n = (257, 257, 257)
+    bc = W.MIXED_X_BC
+    P = W.two_phase_problem(257, seed=1002, n_finest=257)
+    G = O.Grid3(n, (0, 0, 0), (1, 1, 1), bc)
+    u = W.random_field(n, 700)
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
+    Kd, ud = to_dev(P.K, torch.float64), to_dev(u, torch.float64)
+    for mode, fn in (("reduced", O.apply_reduced), ("transpose", O.apply_reduced_transpose)):
+        log(f"apply 257^3 {mode}")
+        y = to_host(plan.apply(Kd, ud, mode=mode))
+        ref = fn(G, P.K, u)
+        e = rel_l2(y, ref)
+        log(f"  rel err {e:.2e}")
+        assert e <= F64_TOL, mode
+        assert np.all(y[~G.interior] == 0.0)
+        del y, ref
 
 
 def test_apply_257_sampled():

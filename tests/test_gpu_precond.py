@@ -119,3 +119,40 @@ def test_precond_exact_for_constant_K_shapes(shape, bcname, prec):
         _, _, ainfo = plan.adjoint(d(K), u, d(r), SolveOptions(rtol=1e-11, precond=True))
         log(f"adjoint const K {shape} {bcname}: {ainfo}")
         assert ainfo["status"] == 0 and ainfo["matvecs"] <= 4
+
+
+@pytest.mark.parametrize("shape,robin", [
+    ((34, 66, 98), None),                          # interior sizes 32, 64, 96
+    ((130, 97, 129), None),                        # 128, 95, 127
+    ((66, 130, 34), (0.0, 0.0, 0.7, 0.7, 0.0, 0.0)),  # Robin pair of equal sigma on the y faces
+])
+def test_precond_exact_even_split_widths(shape, robin):
+    """Same face type at both ends of every axis, so every axis takes the
+    preconditioner's even-odd split contraction, on interior sizes m = 32, 64,
+    96 and 128 (no middle node) next to 95 and 127 (a middle node): with
+    constant K the preconditioner is the exact inverse, so the forward solve
+    (FP64 and FP32) and the adjoint solve, which applies the transposed
+    contractions, stop after a few applications."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    D_, N_ = 0, 1
+    bc = (D_, D_, N_, N_, D_, D_)
+    LO, HI = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+    K = np.full(shape, 1.3)
+    f = W.random_field(shape, 81)
+    g = W.random_faces(W.Grid(shape, LO, HI, bc), 82)
+    for prec in ("f64", "f32"):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        d = lambda a: to_dev(a, dt)
+        plan = Plan(shape, LO, HI, bc, prec, robin=robin)
+        log(f"even split {shape} robin={robin} {prec}")
+        u, info = plan.solve(d(K), d(f), d(g),
+                             opts=SolveOptions(rtol=1e-5 if prec == "f32" else 1e-11, precond=True))
+        log(f"  forward {info}")
+        assert info["status"] == 0 and info["matvecs"] <= 4
+        if prec == "f64":
+            r = W.random_field(shape, 83)
+            _, _, ainfo = plan.adjoint(d(K), u, d(r), SolveOptions(rtol=1e-11, precond=True))
+            log(f"  adjoint {ainfo}")
+            assert ainfo["status"] == 0 and ainfo["matvecs"] <= 4

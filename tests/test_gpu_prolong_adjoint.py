@@ -116,6 +116,113 @@ def test_adjoint_finite_differences_33():
     _fd_check((33, 33, 33), 4, {1e-6: 1e-5})
 
 
+def _fd_check_corrections(n, ndir, h, bar, seed_k=1005, seed_t=1006, seed_v=1007):
+    """Central differences at step h with the perturbed states solved as
+    corrections of the converged state U: K_pm = K exp(+-h v), and
+    u_pm = U + delta_pm with
+        A(K_pm) delta_pm = (f - A(K) U) - A(K expm1(+-h v)) U,
+    zero face data (U already meets the boundary rows).  A is linear in K, so
+    this is the same linear system as solving for u_pm outright; but the common
+    part f - A(K) U is evaluated once and the O(h) part with its own relative
+    rounding, and each delta_pm carries the solve's relative error on an O(h)
+    vector instead of on u.  The difference quotient then loses no digits to the
+    O(kappa u_64 ||u||) floor of two independent solves, and h = 1e-6 meets the
+    1e-5 agreement bar."""
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    bc = W.MIXED_X_BC
+    grid = W.Grid(n, (0, 0, 0), (1, 1, 1), bc)
+    G = O.Grid3(n, (0, 0, 0), (1, 1, 1), bc)
+    logK = np.log(W.lognormal_conductivity(grid, seed_k, 1.0, 0.2))
+    K = np.exp(logK)
+    t = np.exp(0.5 * W.gaussian_field_rff(grid, seed_t, 0.3))
+    g = W.dirichlet_x_faces(grid, -1.0, 1.0)
+    f = np.zeros(n)
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
+    d = lambda a: to_dev(a, torch.float64)
+    opts = SolveOptions(rtol=1e-15, maxiter=4000, precond=True)
+    log(f"adjoint FD (corrections) n={n[0]}: base solve")
+    Ud, info = plan.solve(d(K), d(f), d(g), opts=opts)
+    assert info["status"] in (0, 2), info
+    U = to_host(Ud)
+    _, grad, ainfo = plan.adjoint(d(K), Ud, d(U - t), opts)
+    assert ainfo["status"] in (0, 2), ainfo
+    gh = to_host(grad)
+    r0 = f - to_host(plan.apply(d(K), Ud, mode="full"))
+    r0[~G.interior] = 0.0
+    g0 = np.zeros_like(g)
+    r = np.random.default_rng(seed_v)
+    worst = 0.0
+    for s in range(ndir):
+        v = r.standard_normal(n)
+        delta = []
+        for sgn in (1.0, -1.0):
+            dK = K * np.expm1(sgn * h * v)
+            rd = to_host(plan.apply(d(dK), Ud, mode="full"))
+            rhs = r0 - rd
+            rhs[~G.interior] = 0.0
+            dl, di = plan.solve(d(K * np.exp(sgn * h * v)), d(rhs), d(g0),
+                                opts=SolveOptions(rtol=1e-14, maxiter=4000, precond=True))
+            assert di["status"] in (0, 2), di
+            delta.append(to_host(dl))
+        dp, dm = delta
+        fd = 0.5 * np.sum((dp - dm) * (2.0 * (U - t) + dp + dm)) / (2 * h)
+        ad = float(np.sum(gh * v))
+        rel = abs(fd - ad) / abs(ad)
+        worst = max(worst, rel)
+        log(f"  n={n[0]} h={h:g} dir {s}: FD {fd:.12e} adjoint {ad:.12e} rel {rel:.2e}")
+    assert worst <= bar, worst
+
+
+def test_adjoint_finite_differences_129_h1e6():
+    """The adjoint-sensitivity workload at its stated step: 129^3, log-normal K
+    (sigma 1, l 0.2), target from a log-normal field (sigma 0.5, l 0.3), 8
+    random node directions, central differences with h = 1e-6 in FP64, held to
+    1e-5 relative agreement, with the perturbed states solved as corrections of
+    the converged state."""
+    require_gpu()
+    _fd_check_corrections((129, 129, 129), 8, 1e-6, 1e-5)
+
+
+def test_autograd_raises_when_a_solve_fails():
+    """ChebSolveFn refuses to return the best iterate of a solve that did not
+    converge: forward with a matvec cap too small raises SolveNotConverged,
+    and so does backward when the adjoint solve is capped."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveNotConverged, SolveOptions, solve_logk
+    n = (9, 9, 9)
+    bc = W.MIXED_X_BC
+    grid = W.Grid(n, (0, 0, 0), (1, 1, 1), bc)
+    K = W.random_conductivity(n, 31, 0.5)
+    g = to_dev(W.dirichlet_x_faces(grid, -1.0, 1.0), torch.float64)
+    f = torch.zeros(n, dtype=torch.float64, device="cuda")
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), bc, "f64")
+    logK = torch.tensor(np.log(K), device="cuda", requires_grad=True)
+    with pytest.raises(SolveNotConverged) as ei:
+        solve_logk(plan, logK, f, g, SolveOptions(rtol=1e-13, maxiter=3))
+    assert ei.value.info["status"] == 1
+    u = solve_logk(plan, logK, f, g, SolveOptions(rtol=1e-13))
+    u.grad_fn.opts = SolveOptions(rtol=1e-13, maxiter=2)
+    with pytest.raises(SolveNotConverged):
+        (u * u).sum().backward()
+
+
+def test_adjoint_rejects_bad_krylov_dims():
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd._lib import ChebError
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    n = (9, 9, 9)
+    plan = Plan(n, (0, 0, 0), (1, 1, 1), W.MIXED_X_BC, "f64")
+    K = torch.ones(n, dtype=torch.float64, device="cuda")
+    u = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for o in (SolveOptions(inner_m=65), SolveOptions(outer_k=7)):
+        with pytest.raises(ChebError) as ei:
+            plan.adjoint(K, u, u, o)
+        assert ei.value.code == -1
+
+
 def test_adjoint_finite_differences_129():
     """The adjoint-sensitivity workload: 129^3, log-normal K (sigma 1, l 0.2),
     target from a log-normal field (sigma 0.5, l 0.3), 8 random node directions.
