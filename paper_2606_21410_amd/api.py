@@ -223,7 +223,7 @@ class Plan:
         self.ensure_workspace(opts)
         lam = torch.empty_like(u)
         grad = torch.empty_like(u)
-        o, _ = opts.to_c(False)
+        o, hist = opts.to_c(False)
         info = L.cheb_solve_info()
         rc = L.check(self.lib.cheb_adjoint(self._h, self._field(K, "K"), self._field(u, "u"),
                                            self._field(dLdu, "dLdu"), self._field(lam, "lambda"),
@@ -231,6 +231,8 @@ class Plan:
                                            ctypes.byref(info)))
         d = info.as_dict()
         d["rc"] = rc
+        if hist is not None:
+            d["history"] = [hist[i] for i in range(info.history_used)]
         return lam, grad, d
 
     def picard(self, K0, f, g, u0=None, tol=1e-10, max_steps=50, opts: SolveOptions | None = None):

@@ -93,7 +93,10 @@ def _fd_check(n, ndir, hs, seed_k=1005, seed_t=1006, seed_v=1007):
 
     Ud = solve(logK)
     U = to_host(Ud)
-    _, grad, _ = plan.adjoint(d(np.exp(logK)), d(U), d(U - t), opts)
+    _, grad, ainfo = plan.adjoint(d(np.exp(logK)), d(U), d(U - t),
+                                  SolveOptions(rtol=1e-11, maxiter=4000, precond=True))
+    log(f"  adjoint: {ainfo['matvecs']} matvecs, relres {ainfo['relres_final']:.2e}")
+    assert ainfo["status"] == 0, ainfo
     gh = to_host(grad)
     r = np.random.default_rng(seed_v)
     vs = [r.standard_normal(n) for _ in range(ndir)]
@@ -145,8 +148,13 @@ def _fd_check_corrections(n, ndir, h, bar, seed_k=1005, seed_t=1006, seed_v=1007
     Ud, info = plan.solve(d(K), d(f), d(g), opts=opts)
     assert info["status"] in (0, 2), info
     U = to_host(Ud)
-    _, grad, ainfo = plan.adjoint(d(K), Ud, d(U - t), opts)
-    assert ainfo["status"] in (0, 2), ainfo
+    # the adjoint right-hand side r_k + G^T r_r carries the boundary residuals
+    # through the Neumann lift; 1e-11 is far below what the 1e-5 bar needs
+    _, grad, ainfo = plan.adjoint(d(K), Ud, d(U - t), SolveOptions(rtol=1e-11, maxiter=4000, precond=True,
+                                                                   history_len=64))
+    log(f"  adjoint: {ainfo['matvecs']} matvecs, relres {ainfo['relres_final']:.2e}, "
+        f"history {ainfo.get('history')}")
+    assert ainfo["status"] == 0, ainfo
     gh = to_host(grad)
     r0 = f - to_host(plan.apply(d(K), Ud, mode="full"))
     r0[~G.interior] = 0.0
@@ -162,8 +170,8 @@ def _fd_check_corrections(n, ndir, h, bar, seed_k=1005, seed_t=1006, seed_v=1007
             rhs = r0 - rd
             rhs[~G.interior] = 0.0
             dl, di = plan.solve(d(K * np.exp(sgn * h * v)), d(rhs), d(g0),
-                                opts=SolveOptions(rtol=1e-14, maxiter=4000, precond=True))
-            assert di["status"] in (0, 2), di
+                                opts=SolveOptions(rtol=1e-13, maxiter=4000, precond=True))
+            assert di["status"] == 0, di
             delta.append(to_host(dl))
         dp, dm = delta
         fd = 0.5 * np.sum((dp - dm) * (2.0 * (U - t) + dp + dm)) / (2 * h)
