@@ -94,7 +94,7 @@ def _fd_check(n, ndir, hs, seed_k=1005, seed_t=1006, seed_v=1007):
     Ud = solve(logK)
     U = to_host(Ud)
     _, grad, ainfo = plan.adjoint(d(np.exp(logK)), d(U), d(U - t),
-                                  SolveOptions(rtol=1e-11, maxiter=4000, precond=True))
+                                  SolveOptions(rtol=1e-10, maxiter=4000, precond=True))
     log(f"  adjoint: {ainfo['matvecs']} matvecs, relres {ainfo['relres_final']:.2e}")
     assert ainfo["status"] == 0, ainfo
     gh = to_host(grad)
@@ -149,8 +149,10 @@ def _fd_check_corrections(n, ndir, h, bar, seed_k=1005, seed_t=1006, seed_v=1007
     assert info["status"] in (0, 2), info
     U = to_host(Ud)
     # the adjoint right-hand side r_k + G^T r_r carries the boundary residuals
-    # through the Neumann lift; 1e-11 is far below what the 1e-5 bar needs
-    _, grad, ainfo = plan.adjoint(d(K), Ud, d(U - t), SolveOptions(rtol=1e-11, maxiter=4000, precond=True,
+    # through the Neumann lift, and the transposed solve's attainable relative
+    # residual at 129^3 is ~1.6e-11 (measured: it stagnates there); 1e-10 is
+    # far below what the 1e-5 bar needs
+    _, grad, ainfo = plan.adjoint(d(K), Ud, d(U - t), SolveOptions(rtol=1e-10, maxiter=4000, precond=True,
                                                                    history_len=64))
     log(f"  adjoint: {ainfo['matvecs']} matvecs, relres {ainfo['relres_final']:.2e}, "
         f"history {ainfo.get('history')}")
