@@ -210,6 +210,23 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
 int cheb_prolong(const cheb_plan* coarse, const cheb_plan* fine, const void* u_c, void* u_f,
                  const void* u_f_solved, double* e_ref);
 
+/* Allocation-free prolongation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same result as cheb_prolong(coarse, fine, u_c, u_f,
+ * NULL, NULL), bit for bit, with the two intermediate fields of its three axis
+ * passes held in the library's file-scope device scratch array (128 MiB per
+ * GPU, allocated with the library's code object and held until the process
+ * ends) instead of the fine plan's workspace.  Needs no workspace, calls no
+ * allocating routine and does not synchronise: asynchronous on the fine plan's
+ * stream.  The intermediates take round_up(nc0*nc1*nf2*e, 256) +
+ * round_up(nc0*nf1*nf2*e, 256) bytes (e = 8 for FP64, 4 for FP32; nc = coarse,
+ * nf = fine sizes); larger requests fail with CHEB_ERR_WORKSPACE before any
+ * work is enqueued (FP64 129^3 -> 257^3 fits).  Both plans must live on the
+ * same device.  Every call on a GPU shares that GPU's scratch array: calls
+ * that overlap in time on one GPU (other streams, other host threads) race on
+ * it and must be serialised by the caller.  Other errors as cheb_prolong. */
+int cheb_prolong_noalloc(const cheb_plan* coarse, const cheb_plan* fine, const void* u_c, void* u_f);
+
 /* Adjoint sensitivity: given the converged state u of cheb_solve for K and
  * dL/du at every node, solves A^T lambda = dL/du through the reduced transpose
  * (interior rows: (A_kk + A_kr G)^T lambda_k = r_k + G^T r_r) and writes

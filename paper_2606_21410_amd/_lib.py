@@ -69,6 +69,7 @@ _SIGS = {
     "cheb_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(cheb_solve_opts),
                                   ctypes.POINTER(cheb_solve_info)]),
     "cheb_prolong": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "cheb_prolong_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cheb_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(cheb_solve_opts),
                                     ctypes.POINTER(cheb_solve_info)]),
     "cheb_picard": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,

@@ -238,6 +238,10 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
     }
   }
   for (size_t i = 0; i < cnt; ++i) h32[i] = float(h64[i]);
+  if (hip_check(hipGetDevice(&p->device), "hipGetDevice")) {
+    delete p;
+    return CHEB_ERR_DEVICE;
+  }
   int rc = hip_check(hipMalloc((void**)&p->dconst64, cnt * sizeof(double)), "hipMalloc(plan constants)");
   if (!rc) rc = hip_check(hipMalloc((void**)&p->dconst32, cnt * sizeof(float)), "hipMalloc(plan constants)");
   if (!rc)

@@ -38,6 +38,7 @@ struct PrecondAxis {
 struct cheb_plan {
   cheb_grid g;
   int prec;
+  int device;  // HIP device current at creation (holds the plan's constants)
   hipStream_t stream;
   size_t npts;
   cheb::AxisConst ax[3];

@@ -5,6 +5,7 @@
 // Both transforms are evaluated as direct cosine sums from LDS tables; the
 // prolongation runs once per refinement level, far off the solver's hot loop.
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -199,4 +200,86 @@ extern "C" int cheb_prolong(const cheb_plan* coarse, const cheb_plan* fine, cons
     *e_ref = pf->hpinned[1] > 0 ? std::sqrt(pf->hpinned[0] / pf->hpinned[1]) : 0.0;
   }
   return CHEB_OK;
+}
+
+// ---- allocation-free prolongation ------------------------------------------
+// The two intermediate fields of the three axis passes live in a file-scope
+// device array instead of the fine plan's workspace.  Every GPU that runs this
+// library holds one copy of it (at its own address) until the process ends.
+namespace cheb {
+namespace {
+
+constexpr size_t kScratchBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// device address of `scratch` on `dev`, looked up once per device with that
+// device current (the array's name is a host-side stand-in, not an address)
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= 64) {
+    set_error("device index out of range");
+    return CHEB_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    int rc = hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (rc) return rc;
+    if (cur != dev && (rc = hip_check(hipSetDevice(dev), "hipSetDevice"))) return rc;
+    void* ptr = nullptr;
+    rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (cur != dev) {
+      const int rc2 = hip_check(hipSetDevice(cur), "hipSetDevice");
+      if (!rc) rc = rc2;
+    }
+    if (rc) return rc;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHEB_OK;
+}
+
+}  // namespace
+}  // namespace cheb
+
+extern "C" int cheb_prolong_noalloc(const cheb_plan* coarse, const cheb_plan* fine, const void* u_c, void* u_f) {
+  if (!coarse || !fine || !u_c || !u_f || u_c == u_f) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (coarse->prec != fine->prec || coarse->device != fine->device) {
+    set_error("coarse and fine plans must have the same precision and device");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (fine->g.n[a] < coarse->g.n[a]) {
+      set_error("fine grid must not be smaller than the coarse grid");
+      return CHEB_ERR_INVALID_ARG;
+    }
+    if (std::fabs(fine->g.lo[a] - coarse->g.lo[a]) > 0 || std::fabs(fine->g.hi[a] - coarse->g.hi[a]) > 0) {
+      set_error("coarse and fine plans must describe the same box");
+      return CHEB_ERR_INVALID_ARG;
+    }
+  }
+  // intermediates after the z pass (nc0, nc1, nf2) and the y pass (nc0, nf1, nf2)
+  const size_t esz = fine->prec == CHEB_F32 ? sizeof(float) : sizeof(double);
+  const size_t nc0 = coarse->g.n[0], nc1 = coarse->g.n[1], nf1 = fine->g.n[1], nf2 = fine->g.n[2];
+  const size_t b1 = round_up(nc0 * nc1 * nf2 * esz, 256);
+  const size_t b2 = round_up(nc0 * nf1 * nf2 * esz, 256);
+  if (b1 + b2 > kScratchBytes) {
+    set_error("prolongation intermediates (" + std::to_string(b1 + b2) + " bytes) exceed the " +
+              std::to_string(kScratchBytes) + "-byte static scratch of cheb_prolong_noalloc");
+    return CHEB_ERR_WORKSPACE;
+  }
+  void* base = nullptr;
+  int rc = scratch_address(fine->device, &base);
+  if (rc) return rc;
+  char* ws = (char*)base;
+  if (fine->prec == CHEB_F32)
+    return prolong_t<float>(coarse, fine, (const float*)u_c, (float*)u_f, (float*)ws, (float*)(ws + b1),
+                            fine->stream);
+  return prolong_t<double>(coarse, fine, (const double*)u_c, (double*)u_f, (double*)ws, (double*)(ws + b1),
+                           fine->stream);
 }
