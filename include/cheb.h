@@ -182,7 +182,8 @@ int cheb_plan_set_tile_shape(cheb_plan* plan, int32_t field_precision, int32_t s
 int cheb_plan_destroy(cheb_plan* plan);
 
 /* Operator application (Algorithm 3 with the rows of Section 2.3.1).
- *   K : conductivity at every node (> 0), u : input field, y : output field
+ *   K : coefficient at every node (the solves require K > 0; the apply is
+ *   linear in K and evaluates any finite values), u : input field, y : output field
  *   (y must not alias u or K).  flags: CHEB_APPLY_FULL, CHEB_APPLY_REDUCED or
  *   CHEB_APPLY_REDUCED|CHEB_APPLY_TRANSPOSE.  In REDUCED modes boundary entries
  *   of u are ignored and boundary entries of y are set to 0.  Asynchronous.
