@@ -36,7 +36,8 @@ constexpr int kGroup = 4;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, size_t ld, int nv,
                                                        const T* __restrict__ w, size_t npts,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials, const int* gate) {
+  if (gate && !*gate) return;  // device-side predicate (the Arnoldi re-orthogonalisation pass)
   __shared__ double red[kThreads / 64][kMaxDots];
   const size_t b0 = (size_t)blockIdx.x * kChunk;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -84,7 +85,9 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const T* __restrict__ V, 
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restrict__ partials, int rows,
-                                                         int cols, double* __restrict__ out) {
+                                                         int cols, double* __restrict__ out,
+                                                         const int* gate = nullptr) {
+  if (gate && !*gate) return;
   __shared__ double red[kThreads / 64];
   const int c = blockIdx.x, tid = threadIdx.x;
   double s = 0.0;
@@ -106,7 +109,10 @@ constexpr int kUE = 4;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update_scale(const T* __restrict__ V, size_t ld, int nv,
                                                            const double* __restrict__ h, const T* w, T* out,
-                                                           double scale, size_t npts) {
+                                                           double scale, size_t npts, const double* dscale,
+                                                           const int* gate) {
+  if (gate && !*gate) return;
+  if (dscale) scale = *dscale;
   __shared__ double hs[kMaxDots];
   for (int v = threadIdx.x; v < nv; v += kThreads) hs[v] = h[v];
   __syncthreads();
@@ -307,30 +313,30 @@ size_t multidot_partials_len(size_t npts, int nv) {
 
 template <typename T>
 int multidot(const T* V, size_t ld, int nv, const T* w, size_t npts, double* partials, double* out,
-             hipStream_t s) {
+             hipStream_t s, const int* gate) {
   if (nv + 1 > kMaxDots) {
     set_error("too many vectors in multi-dot");
     return CHEB_ERR_INVALID_ARG;
   }
   if (npts == 0) {  // every dot product is empty: zero rows reduce to 0
-    hipLaunchKernelGGL(k_reduce_cols, dim3(nv + 1), dim3(kThreads), 0, s, partials, 0, nv + 1, out);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nv + 1), dim3(kThreads), 0, s, partials, 0, nv + 1, out, gate);
     return hip_check(hipGetLastError(), "multidot");
   }
   const int blocks = (int)((npts + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_multidot<T>, dim3(blocks), dim3(kThreads), 0, s, V, ld, nv, w, npts, partials);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(nv + 1), dim3(kThreads), 0, s, partials, blocks, nv + 1, out);
+  hipLaunchKernelGGL(k_multidot<T>, dim3(blocks), dim3(kThreads), 0, s, V, ld, nv, w, npts, partials, gate);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nv + 1), dim3(kThreads), 0, s, partials, blocks, nv + 1, out, gate);
   return hip_check(hipGetLastError(), "multidot");
 }
 
 template <typename T>
 int update_scale(const T* V, size_t ld, int nv, const double* h, const T* w, T* out, double scale,
-                 size_t npts, hipStream_t s) {
+                 size_t npts, hipStream_t s, const double* dscale, const int* gate) {
   if (nv > kMaxDots) {
     set_error("too many vectors in update");
     return CHEB_ERR_INVALID_ARG;
   }
   hipLaunchKernelGGL(k_update_scale<T>, dim3(grid_for(npts)), dim3(kThreads), 0, s, V, ld, nv, h, w, out,
-                     scale, npts);
+                     scale, npts, dscale, gate);
   return hip_check(hipGetLastError(), "update_scale");
 }
 
@@ -435,9 +441,10 @@ int cc_dot(const double* a, const double* b, const double* wx, const double* wy,
 }
 
 #define CHEB_INST(T)                                                                                  \
-  template int multidot<T>(const T*, size_t, int, const T*, size_t, double*, double*, hipStream_t);   \
+  template int multidot<T>(const T*, size_t, int, const T*, size_t, double*, double*, hipStream_t,    \
+                           const int*);                                                               \
   template int update_scale<T>(const T*, size_t, int, const double*, const T*, T*, double, size_t,    \
-                               hipStream_t);                                                          \
+                               hipStream_t, const double*, const int*);                               \
   template int lincomb<T>(const T*, size_t, int, const double*, T*, int, size_t, hipStream_t);        \
   template int axpby<T>(T*, const T*, double, double, size_t, hipStream_t);                           \
   template int copy_scale<T>(T*, const T*, double, size_t, hipStream_t);                              \

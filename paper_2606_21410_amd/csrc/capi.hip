@@ -328,6 +328,10 @@ int cheb_plan_destroy(cheb_plan* plan) {
   if (plan->dconst32) (void)hipFree(plan->dconst32);
   if (plan->dd64) (void)hipFree(plan->dd64);
   if (plan->dd32) (void)hipFree(plan->dd32);
+  if (plan->kev_ok) {
+    (void)hipEventDestroy(plan->kev[0]);
+    (void)hipEventDestroy(plan->kev[1]);
+  }
   if (plan->hpinned) (void)hipHostFree(plan->hpinned);
   if (plan->pc64) (void)hipFree(plan->pc64);
   if (plan->pc32) (void)hipFree(plan->pc32);

@@ -70,6 +70,7 @@ template <typename T>
 static int launch_dense_common(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u,
                                T* y, const DenseSys* sys, const int* act, int nact, hipStream_t s) {
   DenseArgs<T> a;
+  a.gate = sys ? nullptr : p->gate;
   a.u = u;
   a.K = K;
   a.y = y;

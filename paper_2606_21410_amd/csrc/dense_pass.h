@@ -154,6 +154,7 @@ __device__ inline DenseSys dense_sys_at(const DenseArgs<T>& a, int i) {
 
 template <typename T>
 struct DenseArgs {
+  const int* gate;  // null, or a device flag: the pass does nothing while it reads 0
   const T* u;  // single system (sys == nullptr)
   const T* K;
   T* y;
@@ -363,6 +364,7 @@ struct DenseArgs {
 // clears the pencils that lie in a face (all their nodes are boundary nodes).
 template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(DenseArgs<T> a) {
+  if (a.gate && !*a.gate) return;
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int N = NC, n = NC + 1;
   constexpr int NT = 64 * S.NW;

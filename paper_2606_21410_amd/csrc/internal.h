@@ -64,6 +64,13 @@ struct cheb_plan {
   size_t dd_off[3][2];
   int dense_var[3][2];  // tile shape of the matrix-core pass, [axis][f64, f32]
   int auto_fft[2];      // CHEB_ROUTE_AUTO resolved to the FFT route, [f64, f32] (autotuner)
+  hipEvent_t kev[2];    // LGMRES: completion of the last two enqueued Arnoldi steps (created on first use)
+  int kev_ok;
+  // device flag the operator and preconditioner kernels check first (they do
+  // nothing while it reads 0); set by LGMRES around each Arnoldi step so that
+  // a step enqueued past the end of a restart cycle costs only its launches;
+  // null otherwise
+  const int* gate;
   double* dd64;
   float* dd32;
 };
@@ -111,16 +118,57 @@ inline bool use_dense(const cheb_plan* p, int axis, int pi) {
 // Arnoldi: a second Gram-Schmidt pass runs when ||w - V h||^2 <= kReorthEta2 ||w||^2
 constexpr double kReorthEta2 = 0.01;
 
+// ---- device-resident LGMRES restart cycle (krylov.hip) ----
+constexpr int kMaxKrylovCols = 70;  // inner_m + outer_k <= 64 + 6
+// the part of the state the host reads back once per Arnoldi step
+struct ArnoldiHead {
+  double beta;      // ||r|| at the start of the cycle
+  double est;       // residual estimate |g[jend]| after the last column
+  double tol;       // absolute tolerance on ||r||
+  double stall;     // stagnation factor (0: off)
+  double bprev;     // beta of the previous cycle
+  double inv_beta, hn, inv_hn;
+  int active;       // 1 while the cycle is to continue
+  int jend;         // columns built in this cycle
+  int reorth;       // the cycle is paused at column jend for a second Gram-Schmidt pass
+  int breakdown;
+  int stagnated;    // beta > stall * bprev
+  int direct;       // the next update forms v_{jend} (the last column was finalised and the cycle goes on)
+  int pad_[2];
+};
+struct ArnoldiState : ArnoldiHead {
+  double cs[kMaxKrylovCols], sn[kMaxKrylovCols], g[kMaxKrylovCols + 1], y[kMaxKrylovCols];
+  double H[(kMaxKrylovCols + 1) * kMaxKrylovCols];  // row-major, rotated to upper triangular
+};
+int arnoldi_init(ArnoldiState* st, double tol, double stall, hipStream_t s);
+// beta = sqrt(dots[0]); g = beta e_1; active = beta > tol and not stagnated
+int arnoldi_begin(ArnoldiState* st, const double* dots, hipStream_t s);
+// one Gram-Schmidt pass of Arnoldi step j against V_0..V_j and the Hessenberg
+// column it gives (pass 0 while the cycle is active; pass 1, the
+// re-orthogonalisation, only while pass 0 has paused the cycle for it: it
+// first sets w <- w - V h0 with h0 the pass-0 coefficients); dots[0..j+1]
+// receive the pass's coefficients and ||w||^2; partials:
+// multidot_partials_len(npts, j + 1)
+template <typename T>
+int gram_schmidt(const T* V, size_t ld, int j, T* w, size_t npts, const double* h0, double* partials,
+                 double* dots, ArnoldiState* st, int pass, hipStream_t s);
+// st->y = R^{-1} g over the cycle's columns
+int arnoldi_solve(ArnoldiState* st, hipStream_t s);
+template <typename T>
+int scale_by(T* v, const double* dscale, size_t npts, hipStream_t s);  // v *= *dscale
+
 // ---- vector kernels (blas.hip) ----
 size_t multidot_partials_len(size_t npts, int nv);
-// out[i] = <V_i, w> for i < nv, out[nv] = <w, w>  (double accumulation)
+// out[i] = <V_i, w> for i < nv, out[nv] = <w, w>  (double accumulation); with
+// a gate, the kernels do nothing unless *gate != 0 when they run
 template <typename T>
 int multidot(const T* V, size_t ld, int nv, const T* w, size_t npts, double* partials, double* out,
-             hipStream_t s);
-// out = (w - sum_i h_i V_i) * scale   (h on device, nv entries; out may alias w)
+             hipStream_t s, const int* gate = nullptr);
+// out = (w - sum_i h_i V_i) * scale   (h on device, nv entries; out may alias w);
+// dscale (device) replaces scale when given; gated as multidot
 template <typename T>
 int update_scale(const T* V, size_t ld, int nv, const double* h, const T* w, T* out, double scale,
-                 size_t npts, hipStream_t s);
+                 size_t npts, hipStream_t s, const double* dscale = nullptr, const int* gate = nullptr);
 // out (+)= sum_i c_i V_i  (c on device)
 template <typename T>
 int lincomb(const T* V, size_t ld, int nv, const double* c, T* out, int accumulate, size_t npts,

@@ -35,6 +35,7 @@ enum PassMode { MODE_FULL = 0, MODE_REDUCED = 1, MODE_TRANSPOSE = 2, MODE_DERIV 
 
 template <typename T>
 struct PassArgs {
+  const int* gate;  // null, or a device flag: the pass does nothing while it reads 0
   const T* u;
   const T* K;
   T* y;
@@ -367,6 +368,7 @@ __device__ __forceinline__ void pass_recur(T* pen, int N, T c, int g) {
 
 template <typename T, int NC, int MODE>
 __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
+  if (a.gate && !*a.gate) return;
   constexpr int P = pass_pencils(NC);
   constexpr int NT = pass_threads(NC);
   constexpr int G = NT / P;

@@ -74,6 +74,7 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
   if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && use_dense(p, axis, sizeof(T) == sizeof(double) ? 0 : 1))
     return launch_dense_pass<T>(p, axis, mode == MODE_TRANSPOSE ? 1 : 0, first, K, u, y, s);
   PassArgs<T> a;
+  a.gate = p->gate;
   a.u = u;
   a.K = K;
   a.y = y;

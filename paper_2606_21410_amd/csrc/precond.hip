@@ -401,6 +401,7 @@ __global__ __launch_bounds__(256) void k_axis_gemm(GemmArgs g) {
 // lam2[i2]): the eigenvalue scaling between the two halves of the
 // preconditioner.
 struct FdmArgs {
+  const int* gate;            // null, or a device flag: the contraction does nothing while it reads 0
   const void* M;
   const void* X;
   void* Y;
@@ -432,6 +433,7 @@ constexpr int kFdmMaxNb = 256;  // blocks whose offsets and Kc a workgroup keeps
 // be a multiple of 16, so that a wave's 16 rows are all of one half.
 template <typename T, int MP, int MODE, int SPLIT>
 __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
+  if (g.gate && !*g.gate) return;
   constexpr int NW = MP / 16, NT = 64 * NW, C = 16, SC = C + 1, KS = MP / 4;
   constexpr int KSE = SPLIT ? MP / 8 : KS;  // k-steps each row block runs
   constexpr int EPT = MP * C / NT;  // = 4
@@ -626,7 +628,9 @@ __global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
 
 // zero the boundary nodes of field blockIdx.y (at offs[y], or y * n0*n1*n2)
 template <typename T>
-__global__ void k_zero_faces(T* __restrict__ out, const long long* __restrict__ offs, int n0, int n1, int n2) {
+__global__ void k_zero_faces(T* __restrict__ out, const long long* __restrict__ offs, int n0, int n1, int n2,
+                             const int* gate) {
+  if (gate && !*gate) return;
   T* o = out + (offs ? offs[blockIdx.y] : (long long)blockIdx.y * n0 * n1 * n2);
   const long long fxy = (long long)n1 * n2, fxz = (long long)n0 * n2, fyz = (long long)n0 * n1;
   const long long tot = 2 * (fxy + fxz + fyz);
@@ -979,6 +983,7 @@ static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bu
   auto Vi = [&](int a) { return base + p->pc_ax[a].off_Vi; };
   auto run = [&](int a, bool fwd, const T* X, T* Y, int mode) {
     FdmArgs f{};
+    f.gate = offs ? nullptr : p->gate;
     f.M = fwd ? (transpose ? V(a) : Vi(a)) : (transpose ? Vi(a) : V(a));
     f.trans = transpose ? 1 : 0;
     f.X = X;
@@ -1009,7 +1014,8 @@ static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bu
   if (rc) return rc;
   const long long faces = 2LL * ((long long)n1 * n2 + (long long)n0 * n2 + (long long)n0 * n1);
   const int fb = (int)std::min<long long>((faces + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_zero_faces<T>, dim3(fb, nb), dim3(256), 0, s, out, offs, n0, n1, n2);
+  hipLaunchKernelGGL(k_zero_faces<T>, dim3(fb, nb), dim3(256), 0, s, out, offs, n0, n1, n2,
+                     offs ? nullptr : p->gate);
   return hip_check(hipGetLastError(), "boundary zero");
 }
 

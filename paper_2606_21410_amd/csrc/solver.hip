@@ -1,7 +1,9 @@
 // Solvers behind the C ABI: LGMRES on the reduced system (Algorithm 2), FP32
 // LGMRES inside FP64 iterative refinement, the adjoint solve and gradient, and
-// the Picard loop.  All arithmetic on fields runs in device kernels; the host
-// keeps the (m+k+1) x (m+k) Hessenberg matrix and its Givens rotations in FP64.
+// the Picard loop.  All arithmetic runs in device kernels, the (m+k+1) x (m+k)
+// Hessenberg matrix, its Givens rotations and the convergence test of each
+// Arnoldi step included (krylov.hip); the host enqueues the steps and reads
+// one small status record per step, one step behind the GPU.
 //
 // LGMRES (Baker, Jessup & Manteuffel, SIAM J. Matrix Anal. Appl. 26(4), 2005):
 // each restart cycle builds an Arnoldi basis from the residual and then
@@ -64,9 +66,10 @@ SolveParams params_from(const cheb_solve_opts* o) {
 template <typename T>
 struct KrylovWS {
   T* V = nullptr;   // m + k + 1 basis vectors
-  T* Z = nullptr;   // k augmentation vectors
-  T* w = nullptr;   // work vector
-  T* wp = nullptr;  // preconditioned search direction (only with a preconditioner)
+  T* Z = nullptr;   // k augmentation vectors (corrections of earlier cycles, solution space)
+  T* w = nullptr;   // work vectors: A d_j of even and odd steps (a step enqueued past a pause
+  T* w2 = nullptr;  // of the cycle must not overwrite the paused step's vector)
+  T* D = nullptr;   // m preconditioned directions M^{-1} v_j (flexible form; only with a preconditioner)
   T* pa = nullptr;  // packed-interior scratch of the preconditioner
   T* pb = nullptr;
   size_t ld = 0;    // elements between vectors
@@ -78,6 +81,7 @@ struct Scratch {
   double* dots = nullptr;   // device, 2 x 80
   double* coef = nullptr;   // device, 80
   int* flag = nullptr;
+  ArnoldiState* ast = nullptr;  // device state of the restart cycle
 };
 
 template <typename T>
@@ -89,9 +93,10 @@ void carve_krylov(Carver& c, const cheb_plan* p, int m, int k, bool prec, Krylov
   kw.V = c.take<T>(kw.ld * (m + k + 1));
   kw.Z = c.take<T>(kw.ld * (k > 0 ? k : 1));
   kw.w = c.take<T>(kw.ld);
+  kw.w2 = c.take<T>(kw.ld);
   if (prec) {
     const size_t inner = (size_t)(p->g.n[0] - 2) * (p->g.n[1] - 2) * (p->g.n[2] - 2);
-    kw.wp = c.take<T>(kw.ld);
+    kw.D = c.take<T>(kw.ld * m);
     kw.pa = c.take<T>(inner);
     kw.pb = c.take<T>(inner);
   }
@@ -102,6 +107,7 @@ void carve_scratch(Carver& c, size_t npts, int maxv, Scratch& s) {
   s.dots = c.take<double>(160);
   s.coef = c.take<double>(80);
   s.flag = c.take<int>(64);
+  s.ast = c.take<ArnoldiState>(1);
 }
 
 struct Stats {
@@ -133,11 +139,39 @@ int vnorm(cheb_plan* p, const T* v, Scratch& s, double* out) {
   return CHEB_OK;
 }
 
+// completion events of the last two Arnoldi steps (created once per plan)
+int ensure_events(cheb_plan* p) {
+  if (p->kev_ok) return CHEB_OK;
+  int rc = hip_check(hipEventCreateWithFlags(&p->kev[0], hipEventDisableTiming), "hipEventCreate");
+  if (rc) return rc;
+  rc = hip_check(hipEventCreateWithFlags(&p->kev[1], hipEventDisableTiming), "hipEventCreate");
+  if (rc) {
+    (void)hipEventDestroy(p->kev[0]);
+    return rc;
+  }
+  p->kev_ok = 1;
+  return CHEB_OK;
+}
+
 // LGMRES on  A x = b  with absolute tolerance tol_abs on ||b - A x||.
 // Returns CHEB_OK when converged, CHEB_NOT_CONVERGED when maxmv was reached.
 // stall > 0: stop with CHEB_STAGNATED when a restart cycle reduces the true
 // residual by less than that factor (used by the FP32 inner solves, whose
 // attainable accuracy is bounded by the FP32 operator).
+//
+// With a preconditioner the cycle is the flexible form of right
+// preconditioning: the directions d_j = M^{-1} v_j are kept, and the update is
+// sum_j y_j d_j, so the minimised residual is that of the directions actually
+// applied (the preconditioner need not be the same linear map at every step;
+// with one that is, this is ordinary right preconditioning).  Augmentation
+// vectors are earlier corrections x_i - x_{i-1}, used as directions directly.
+//
+// Every Arnoldi step is enqueued without a host wait: the Hessenberg column,
+// the rotations and the convergence predicate run on the device
+// (krylov.hip), the re-orthogonalisation kernels run or not by a device flag,
+// and the host reads the step's status record one step later, so at most one
+// step is enqueued past the end of a cycle (its column kernel then does
+// nothing).
 struct NoPrec {
   template <typename T>
   int operator()(const T*, T*) const { return CHEB_OK; }
@@ -150,17 +184,18 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
   const size_t npts = p->npts;
   hipStream_t s = p->stream;
   const int m = kw.m, kmax = kw.k;
-  const int cols = m + kmax;
-  std::vector<double> H((cols + 1) * cols), cs(cols), sn(cols), g(cols + 1), y(cols), dots(cols + 2);
-  auto Hm = [&](int i, int j) -> double& { return H[(size_t)i * cols + j]; };
+  const size_t ld = kw.ld;
   std::vector<int> zslot;  // augmentation vectors, most recent first
-  int zhead = 0;
   T* w = kw.w;
-  int rc;
+  ArnoldiState* ast = sc.ast;
+  double* dots2 = sc.dots + 80;
+  ArnoldiHead* ring = (ArnoldiHead*)(p->hpinned + 4 * 256);  // two pinned status slots
+  int rc = ensure_events(p);
+  if (!rc) rc = arnoldi_init(ast, tol_abs, stall, s);
+  if (rc) return rc;
   bool first = true;
-  double beta = 0.0, beta_prev = HUGE_VAL;
   for (;;) {
-    // true residual r = b - A x  into V_0 (unnormalised)
+    // true residual r = b - A x into V_0, then v_0 = r / ||r|| (device scale)
     T* v0 = kw.V;
     if (first && x_zero) {
       rc = copy_scale<T>(v0, b, 1.0, npts, s);
@@ -169,120 +204,110 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
       if (!rc) rc = axpby<T>(v0, b, 1.0, -1.0, npts, s);
       st.matvecs++;
     }
-    if (rc) return rc;
     first = false;
-    rc = vnorm<T>(p, v0, sc, &beta);
+    if (!rc) rc = multidot<T>(nullptr, 0, 0, v0, npts, sc.partials, sc.dots, s);
+    if (!rc) rc = arnoldi_begin(ast, sc.dots, s);
+    if (!rc) rc = scale_by<T>(v0, &ast->inv_beta, npts, s);
     if (rc) return rc;
+    int jmax = m + (int)zslot.size();
+    if (jmax > maxmv - st.matvecs) jmax = maxmv - st.matvecs;
+    // one Arnoldi step: direction, operator, Gram-Schmidt pass 0 and column j
+    // on the device, v_{j+1} unless the column ended or paused the cycle
+    auto step = [&](int j) -> int {
+      // the operator and preconditioner kernels of the step do nothing once
+      // the cycle has ended (or paused) on the device
+      struct Gate {
+        cheb_plan* p;
+        ~Gate() { p->gate = nullptr; }
+      } gate{p};
+      p->gate = &ast->active;
+      const T* dir;
+      if (j >= m) {
+        dir = kw.Z + (size_t)zslot[j - m] * ld;
+      } else if (use_prec) {
+        T* dj = kw.D + (size_t)j * ld;
+        int r = Mi(kw.V + (size_t)j * ld, dj);
+        if (r) return r;
+        dir = dj;
+      } else {
+        dir = kw.V + (size_t)j * ld;
+      }
+      T* wj = (j & 1) ? kw.w2 : w;
+      int r = A(dir, wj);
+      p->gate = nullptr;
+      if (!r) r = gram_schmidt<T>(kw.V, ld, j, wj, npts, nullptr, sc.partials, sc.dots, ast, 0, s);
+      if (!r)
+        r = update_scale<T>(kw.V, ld, j + 1, sc.dots, wj, kw.V + (size_t)(j + 1) * ld, 1.0, npts, s, &ast->inv_hn,
+                            &ast->direct);
+      return r;
+    };
+    auto fetch_now = [&](ArnoldiHead* out) -> int {
+      int r = hip_check(hipMemcpyAsync(&ring[0], ast, sizeof(ArnoldiHead), hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync(D2H)");
+      if (!r) r = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      if (!r) *out = ring[0];
+      return r;
+    };
+    ArnoldiHead h;
+    int jnext = 0;
+    bool any = false;
+    for (;;) {
+      // enqueue steps jnext.. with the status of each read one step later
+      int last = -1;
+      for (int j = jnext; j < jmax; ++j) {
+        rc = step(j);
+        if (!rc)
+          rc = hip_check(hipMemcpyAsync(&ring[j & 1], ast, sizeof(ArnoldiHead), hipMemcpyDeviceToHost, s),
+                         "hipMemcpyAsync(D2H)");
+        if (!rc) rc = hip_check(hipEventRecord(p->kev[j & 1], s), "hipEventRecord");
+        if (rc) return rc;
+        last = j;
+        any = true;
+        if (j > jnext) {
+          rc = hip_check(hipEventSynchronize(p->kev[(j - 1) & 1]), "hipEventSynchronize");
+          if (rc) return rc;
+          if (!ring[(j - 1) & 1].active) break;
+        }
+      }
+      if (last >= 0) {
+        rc = hip_check(hipEventSynchronize(p->kev[last & 1]), "hipEventSynchronize");
+        if (rc) return rc;
+        h = ring[last & 1];
+      } else {
+        rc = fetch_now(&h);
+        if (rc) return rc;
+      }
+      if (!(h.reorth && h.beta > tol_abs && !h.stagnated)) break;
+      // paused at column jc by cancellation: the second Gram-Schmidt pass for
+      // it (any step enqueued after it ran on a stale vector and is redone)
+      const int jc = h.jend;
+      T* wc = (jc & 1) ? kw.w2 : w;
+      rc = gram_schmidt<T>(kw.V, ld, jc, wc, npts, sc.dots, sc.partials, dots2, ast, 1, s);
+      if (!rc)
+        rc = update_scale<T>(kw.V, ld, jc + 1, dots2, wc, kw.V + (size_t)(jc + 1) * ld, 1.0, npts, s,
+                             &ast->inv_hn, &ast->direct);
+      if (!rc) rc = fetch_now(&h);
+      if (rc) return rc;
+      jnext = jc + 1;
+      if (!h.active || jnext >= jmax) break;
+    }
+    const int enq = any ? 1 : 0;
+    const double beta = h.beta;
     if (hist && st.hist_used < hist_len) hist[st.hist_used++] = bnorm > 0 ? beta / bnorm : beta;
     *resid_out = beta;
     if (!(beta > tol_abs)) return std::isfinite(beta) ? CHEB_OK : CHEB_NOT_CONVERGED;
-    if (st.matvecs >= maxmv) return CHEB_NOT_CONVERGED;
-    if (stall > 0.0 && beta > stall * beta_prev) return CHEB_STAGNATED;
-    beta_prev = beta;
-    rc = copy_scale<T>(v0, v0, 1.0 / beta, npts, s);
-    if (rc) return rc;
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    const int jmax = m + (int)zslot.size();
-    int jend = 0;
-    for (int j = 0; j < jmax; ++j) {
-      const T* u = j < m ? kw.V + (size_t)j * kw.ld : kw.Z + (size_t)zslot[j - m] * kw.ld;
-      if (use_prec) {
-        rc = Mi(u, kw.wp);  // right preconditioning: search direction M^{-1} u
-        if (rc) return rc;
-        u = kw.wp;
-      }
-      rc = A(u, w);
-      if (rc) return rc;
-      st.matvecs++;
-      // one-pass classical Gram-Schmidt against v_0..v_j
-      rc = multidot<T>(kw.V, kw.ld, j + 1, w, npts, sc.partials, sc.dots, s);
-      if (rc) return rc;
-      rc = readback(p, sc.dots, j + 2, dots.data());
-      if (rc) return rc;
-      double hh2 = dots[j + 1];
-      for (int i = 0; i <= j; ++i) {
-        Hm(i, j) = dots[i];
-        hh2 -= dots[i] * dots[i];
-      }
-      T* vnext = kw.V + (size_t)(j + 1) * kw.ld;
-      if (!(hh2 > kReorthEta2 * dots[j + 1])) {
-        // cancellation: orthogonalise again
-        rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots, w, w, 1.0, npts, s);
-        if (rc) return rc;
-        rc = multidot<T>(kw.V, kw.ld, j + 1, w, npts, sc.partials, sc.dots + 80, s);
-        if (rc) return rc;
-        rc = readback(p, sc.dots + 80, j + 2, dots.data(), 1);
-        if (rc) return rc;
-        hh2 = dots[j + 1];
-        for (int i = 0; i <= j; ++i) {
-          Hm(i, j) += dots[i];
-          hh2 -= dots[i] * dots[i];
-        }
-        const double hn = hh2 > 0 ? std::sqrt(hh2) : 0.0;
-        if (hn > 0) {
-          rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots + 80, w, vnext, 1.0 / hn, npts, s);
-          if (rc) return rc;
-        }
-        Hm(j + 1, j) = hn;
-      } else {
-        const double hn = std::sqrt(hh2);
-        rc = update_scale<T>(kw.V, kw.ld, j + 1, sc.dots, w, vnext, 1.0 / hn, npts, s);
-        if (rc) return rc;
-        Hm(j + 1, j) = hn;
-      }
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        const double a = Hm(i, j), bb = Hm(i + 1, j);
-        Hm(i, j) = cs[i] * a + sn[i] * bb;
-        Hm(i + 1, j) = -sn[i] * a + cs[i] * bb;
-      }
-      const double a = Hm(j, j), bb = Hm(j + 1, j);
-      const double r = std::hypot(a, bb);
-      if (r == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        cs[j] = a / r;
-        sn[j] = bb / r;
-      }
-      Hm(j, j) = r;
-      Hm(j + 1, j) = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      jend = j + 1;
-      const double est = std::fabs(g[j + 1]);
-      const bool breakdown = !(bb > 1e-300) || !(r > 0);
-      if (est <= tol_abs || st.matvecs >= maxmv || breakdown) break;
-    }
-    // y = R^{-1} g
-    for (int i = jend - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int l = i + 1; l < jend; ++l) t -= Hm(i, l) * y[l];
-      y[i] = Hm(i, i) != 0.0 ? t / Hm(i, i) : 0.0;
-    }
-    // dx = sum_{i<m} y_i v_i + sum_{i>=m} y_i z_{i-m}  (into w)
-    double* hc = p->hpinned + 2 * 256;
-    for (int i = 0; i < jend; ++i) hc[i] = y[i];
-    rc = hip_check(hipMemcpyAsync(sc.coef, hc, jend * sizeof(double), hipMemcpyHostToDevice, s),
-                   "hipMemcpyAsync(H2D)");
-    if (rc) return rc;
+    if (h.stagnated) return CHEB_STAGNATED;
+    if (enq == 0) return CHEB_NOT_CONVERGED;
+    const int jend = h.jend;
+    st.matvecs += jend;
+    // dx = sum_{j<m} y_j d_j + sum_{j>=m} y_j z_{j-m}  (into w), x += dx
+    rc = arnoldi_solve(ast, s);
     const int nv = jend < m ? jend : m;
-    rc = lincomb<T>(kw.V, kw.ld, nv, sc.coef, w, 0, npts, s);
-    if (rc) return rc;
-    for (int i = m; i < jend; ++i) {
-      rc = lincomb<T>(kw.Z + (size_t)zslot[i - m] * kw.ld, kw.ld, 1, sc.coef + i, w, 1, npts, s);
-      if (rc) return rc;
-    }
-    if (use_prec) {
-      rc = Mi(w, kw.wp);
-      if (!rc) rc = axpby<T>(x, kw.wp, 1.0, 1.0, npts, s);
-    } else {
-      rc = axpby<T>(x, w, 1.0, 1.0, npts, s);
-    }
-    if (rc) return rc;
-    if (kmax > 0) {
+    if (!rc) rc = lincomb<T>(use_prec ? kw.D : kw.V, ld, nv, ast->y, w, 0, npts, s);
+    for (int i = m; i < jend && !rc; ++i)
+      rc = lincomb<T>(kw.Z + (size_t)zslot[i - m] * ld, ld, 1, ast->y + i, w, 1, npts, s);
+    if (!rc) rc = axpby<T>(x, w, 1.0, 1.0, npts, s);
+    if (!rc && kmax > 0) {
       // store the correction as the newest augmentation vector
       int slot;
       if ((int)zslot.size() < kmax) {
@@ -291,13 +316,9 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
         slot = zslot.back();
         zslot.pop_back();
       }
-      rc = copy_scale<T>(kw.Z + (size_t)slot * kw.ld, w, 1.0, npts, s);
-      if (rc) return rc;
+      rc = copy_scale<T>(kw.Z + (size_t)slot * ld, w, 1.0, npts, s);
       zslot.insert(zslot.begin(), slot);
-      (void)zhead;
     }
-    // the host coefficient buffer must not be rewritten before the copy ran
-    rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (rc) return rc;
     st.restarts++;
   }
