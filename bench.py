@@ -421,6 +421,74 @@ def thermal_newton_section(dev, levels=(8, 16, 32, 64, 128, 256), tol=1e-11, max
     return out
 
 
+def thermal_newton_cold(dev, levels=(128, 256), tol=1e-11, max_steps=20, maxiter=2000):
+    """The Section 3.4 problem solved by Newton-LGMRES from a cold start
+    (T_0 = lift(0, g)) at the large levels, so that their time is Newton work
+    (the refinement chain reaches them with the prolonged solution already at
+    the stopping rule)."""
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan, SolveOptions
+    opts = SolveOptions(rtol=1e-10, maxiter=maxiter, precond=True)
+    out = []
+    for N in levels:
+        P = W.thermal_nonlinear(N + 1)
+        K0 = torch.from_numpy(P.K).to(dev)
+        f = torch.from_numpy(P.f).to(dev)
+        g = torch.from_numpy(P.g).to(dev)
+        plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev)
+        plan.ensure_workspace(opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info = plan.newton(K0, f, g, alpha=P.meta["alpha"], tol=tol, max_steps=max_steps, opts=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        err = float((u - torch.from_numpy(P.u_exact).to(dev)).abs().max().item())
+        rec = {"N": N, "start": "cold", "newton_steps": info["newton_steps"],
+               "lgmres_total": sum(info["mv_per_step"]), "lgmres_per_step": info["mv_per_step"],
+               "max_error": err, "seconds": round(el, 4), "status": info["rc"]}
+        _log(f"thermal newton cold {rec}")
+        out.append(rec)
+        del K0, f, g, u, plan
+        torch.cuda.empty_cache()
+    return out
+
+
+def refinement_stop_section(dev, levels=(33, 65, 129, 257), tol=1e-3):
+    """Hierarchical refinement with its stopping rule (Algorithm 4) on the
+    two-phase generator (spheres R 0.15, vf 0.2, contrast 10, width 2/256):
+    preconditioned FP64 solves level by level until the refinement indicator
+    e_ref <= tol, then the prolongation alone; against the same chain with
+    every level solved."""
+    import numpy as np
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan, SolveOptions, refine
+    probs = [W.two_phase_problem(n, seed=1002, n_finest=levels[-1]) for n in levels]
+    plans = [Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev) for P in probs]
+    d = lambda a: torch.from_numpy(a).to(dev)
+    Ks, fs, gs = [d(P.K) for P in probs], [d(P.f) for P in probs], [d(P.g) for P in probs]
+    opts = SolveOptions(rtol=1e-10, maxiter=5000, precond=True, inner_m=20)
+    out = {"levels": list(levels), "tol": tol}
+    for label, t in (("every_level", 0.0), ("with_stop", tol)):
+        refine(plans, Ks, fs, gs, t, opts)  # warm-up (plans, preconditioner set-up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        us, e, solved, infos = refine(plans, Ks, fs, gs, t, opts)
+        torch.cuda.synchronize()
+        out[label] = {"seconds": round(time.perf_counter() - t0, 4), "solved": solved,
+                      "e_ref": [None if np.isnan(v) else float(v) for v in e],
+                      "matvecs": [i["matvecs"] for i in infos]}
+        if label == "every_level":
+            ufull = us[-1].clone()
+        else:
+            out[label]["finest_rel_diff_to_every_level"] = float((us[-1] - ufull).norm() / ufull.norm())
+        _log(f"refinement {label}: {out[label]}")
+    del us, ufull, Ks, fs, gs, plans
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_reference(dev, n=64 * 1024 * 1024, reps=20):
     """Attainable HBM bandwidth: the library's stream-copy kernel (cheb_debug_copy)
     moving n doubles (512 MiB read + 512 MiB written, far beyond the 256 MB
@@ -755,9 +823,17 @@ def main():
         robin_rows = robin_section(dev, P)
 
     thermal = None
+    thermal_cold = None
     if not args.no_solve and n == 129:
         _log("nonlinear thermal problem, Newton-LGMRES chain N = 8 .. 256")
         thermal = thermal_newton_section(dev)
+        _log("nonlinear thermal problem, cold-start Newton at N = 128 and 256")
+        thermal_cold = thermal_newton_cold(dev)
+
+    refinement = None
+    if not args.no_solve and n == 129:
+        _log("hierarchical refinement with the e_ref stop, 33 -> 257")
+        refinement = refinement_stop_section(dev)
 
     batch = None
     if not args.no_batch and not args.profile_apply:
@@ -791,6 +867,8 @@ def main():
         "picard_chain": chain,
         "inclusion_contrast_sweep": inclusion,
         "thermal_newton_chain": thermal,
+        "thermal_newton_cold": thermal_cold,
+        "refinement_stop": refinement,
         "stream_copy": copy,
         "apply_257": a257,
         "robin_rows": robin_rows,

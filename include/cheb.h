@@ -228,6 +228,26 @@ int cheb_prolong(const cheb_plan* coarse, const cheb_plan* fine, const void* u_c
  * it and must be serialised by the caller.  Other errors as cheb_prolong. */
 int cheb_prolong_noalloc(const cheb_plan* coarse, const cheb_plan* fine, const void* u_c, void* u_f);
 
+/* Hierarchical refinement with its stopping rule (Section 2.3.3, Algorithm 4):
+ * levels l = 0 .. nlev-1 on plans[l] (same box, face types and precision;
+ * sizes non-decreasing; the last level the largest), each with its own data
+ * K[l], f[l], g_faces[l] (device fields of that level, as in cheb_solve) and
+ * output u[l].  Level 0 is solved by cheb_solve with opts (bit 0 of
+ * opts->flags: u[0] holds the initial guess).  Every later level starts from
+ * the modal prolongation of the previous level's result into u[l].  While the
+ * refinement has not converged the level is solved from that start and
+ * e_ref[l] = ||U_l - P U_{l-1}||_2 / ||U_l||_2 (the refinement indicator) is
+ * recorded; once some e_ref[l] <= tol the refinement has converged and every
+ * finer level is the prolongation alone, with no solve (solved[l] = 0,
+ * e_ref[l] = NaN).  tmp: device scratch field of the last level's size.  Each
+ * plan needs the workspace of cheb_solve with these opts.  e_ref, solved (nlev
+ * entries each) and infos (per level; zeroed for levels not solved) are host
+ * arrays and may be NULL.  Returns the worst soft status of the solves, or a
+ * negative error.  Synchronises. */
+int cheb_refine(cheb_plan* const* plans, int32_t nlev, const void* const* K, const void* const* f,
+                const void* const* g_faces, void* const* u, void* tmp, const cheb_solve_opts* opts, double tol,
+                double* e_ref, int32_t* solved, cheb_solve_info* infos);
+
 /* Adjoint sensitivity: given the converged state u of cheb_solve for K and
  * dL/du at every node, solves A^T lambda = dL/du through the reduced transpose
  * (interior rows: (A_kk + A_kr G)^T lambda_k = r_k + G^T r_r) and writes

@@ -70,6 +70,10 @@ _SIGS = {
                                   ctypes.POINTER(cheb_solve_info)]),
     "cheb_prolong": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "cheb_prolong_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cheb_refine": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                   ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(cheb_solve_opts),
+                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(cheb_solve_info)]),
     "cheb_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(cheb_solve_opts),
                                     ctypes.POINTER(cheb_solve_info)]),
     "cheb_picard": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,

@@ -524,6 +524,49 @@ def prolong(coarse: Plan, fine: Plan, uc, uf=None, uf_solved=None):
     return uf, (e.value if uf_solved is not None else None)
 
 
+def refine(plans, Ks, fs, gs, tol, opts: SolveOptions | None = None, u0=None):
+    """Hierarchical refinement with its stopping rule (Section 2.3.3,
+    Algorithm 4) through cheb_refine: plans[l] are the levels (same box and
+    faces, growing sizes), Ks/fs/gs their data.  Level 0 is solved (from u0 if
+    given); each later level starts from the modal prolongation of the previous
+    one and is solved until the refinement indicator e_ref <= tol, after which
+    finer levels are the prolongation alone.  Returns (list of per-level
+    results, e_ref per level (nan where not solved or level 0), solved flags,
+    per-level info dicts)."""
+    opts = opts or SolveOptions()
+    n = len(plans)
+    assert n >= 1 and len(Ks) == len(fs) == len(gs) == n
+    lib = plans[0].lib
+    for pl in plans:
+        pl._sync_stream()
+        pl.ensure_workspace(opts)
+    us = [torch.zeros(pl.n, dtype=pl.dtype, device=pl.device) for pl in plans]
+    if u0 is not None:
+        us[0].copy_(u0)
+    tmp = torch.empty(plans[-1].n, dtype=plans[-1].dtype, device=plans[-1].device)
+    for pl, g in zip(plans, gs):
+        if g.dtype != pl.dtype or g.numel() != pl.face_count() or not g.is_contiguous():
+            raise ValueError("g: packed face data of the plan's dtype expected")
+    arr = lambda xs: (L._vp * n)(*xs)
+    hp = arr([pl.handle for pl in plans])
+    kp = arr([pl._field(K, "K") for pl, K in zip(plans, Ks)])
+    fp = arr([pl._field(f, "f") for pl, f in zip(plans, fs)])
+    gp = arr([ctypes.c_void_p(g.data_ptr()) for g in gs])
+    up = arr([pl._field(u, "u") for pl, u in zip(plans, us)])
+    o, _ = opts.to_c(u0 is not None)
+    e = (ctypes.c_double * n)()
+    solved = (ctypes.c_int32 * n)()
+    infos = (L.cheb_solve_info * n)()
+    rc = L.check(lib.cheb_refine(hp, n, kp, fp, gp, up, ctypes.c_void_p(tmp.data_ptr()), ctypes.byref(o),
+                                 float(tol), e, solved, infos))
+    out_infos = []
+    for i in range(n):
+        d = infos[i].as_dict()
+        d["rc"] = rc
+        out_infos.append(d)
+    return us, [e[i] for i in range(n)], [int(solved[i]) for i in range(n)], out_infos
+
+
 class SolveNotConverged(L.ChebError):
     """A solve inside autograd ended with a soft status (not converged or
     stagnated): its output is the best iterate, not the solution, so neither

@@ -997,4 +997,95 @@ int cheb_newton(cheb_plan* plan, const void* K0, double alpha, const void* f, co
   return status;
 }
 
+// Hierarchical refinement with its stopping rule (Section 2.3.3, Algorithm 4).
+int cheb_refine(cheb_plan* const* plans, int32_t nlev, const void* const* K, const void* const* f,
+                const void* const* g_faces, void* const* u, void* tmp, const cheb_solve_opts* opts, double tol,
+                double* e_ref, int32_t* solved, cheb_solve_info* infos) {
+  if (!plans || nlev < 1 || !K || !f || !g_faces || !u || (nlev > 1 && !tmp) || !(tol >= 0.0)) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  for (int l = 0; l < nlev; ++l) {
+    if (!plans[l] || !K[l] || !f[l] || !g_faces[l] || !u[l]) {
+      set_error("null plan or field");
+      return CHEB_ERR_INVALID_ARG;
+    }
+    if (l == 0) continue;
+    const cheb_plan *pc = plans[l - 1], *pf = plans[l];
+    if (pc->prec != pf->prec) {
+      set_error("every level must have the same precision");
+      return CHEB_ERR_INVALID_ARG;
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (pf->g.n[a] < pc->g.n[a] || pf->g.lo[a] != pc->g.lo[a] || pf->g.hi[a] != pc->g.hi[a]) {
+        set_error("levels must share the box and grow in size");
+        return CHEB_ERR_INVALID_ARG;
+      }
+    }
+    for (int q = 0; q < 6; ++q) {
+      if (pf->g.bc[q] != pc->g.bc[q] || pf->g.robin[q] != pc->g.robin[q]) {
+        set_error("levels must share the face conditions");
+        return CHEB_ERR_INVALID_ARG;
+      }
+    }
+    if (pf->npts > plans[nlev - 1]->npts) {
+      set_error("tmp holds the last level; the last level must be the largest");
+      return CHEB_ERR_INVALID_ARG;
+    }
+  }
+  cheb_solve_opts o{};
+  if (opts) o = *opts;
+  int worst = CHEB_OK;
+  bool converged = false;
+  for (int l = 0; l < nlev; ++l) {
+    cheb_plan* p = plans[l];
+    if (e_ref) e_ref[l] = std::nan("");
+    if (solved) solved[l] = 0;
+    cheb_solve_info inf{};
+    if (l > 0) {
+      // the modal prolongation of the previous level: the initial guess, or
+      // -- once the refinement has converged -- the level's result
+      int rc = cheb_prolong(plans[l - 1], p, u[l - 1], u[l], nullptr, nullptr);
+      if (rc) return rc;
+      if (converged) {
+        rc = hip_check(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+        if (rc) return rc;
+        if (infos) infos[l] = inf;
+        continue;
+      }
+      rc = p->prec == CHEB_F32 ? copy_scale<float>((float*)tmp, (const float*)u[l], 1.0, p->npts, p->stream)
+                               : copy_scale<double>((double*)tmp, (const double*)u[l], 1.0, p->npts, p->stream);
+      if (rc) return rc;
+      o.flags |= 1;
+    }
+    const int st = cheb_solve(p, K[l], f[l], g_faces[l], u[l], &o, &inf);
+    if (st < 0) return st;
+    if (st > worst) worst = st;
+    if (solved) solved[l] = 1;
+    if (infos) infos[l] = inf;
+    if (l > 0) {
+      // e_ref = ||U_l - P U_{l-1}|| / ||U_l|| over the level's nodes
+      double* part = (double*)p->ws;
+      double* res = part + multidot_partials_len(p->npts, 1);
+      int rc;
+      if (p->prec == CHEB_F32) {
+        rc = axpby<float>((float*)tmp, (const float*)u[l], -1.0, 1.0, p->npts, p->stream);
+        if (!rc) rc = multidot<float>(nullptr, 0, 0, (const float*)tmp, p->npts, part, res, p->stream);
+        if (!rc) rc = multidot<float>(nullptr, 0, 0, (const float*)u[l], p->npts, part, res + 1, p->stream);
+      } else {
+        rc = axpby<double>((double*)tmp, (const double*)u[l], -1.0, 1.0, p->npts, p->stream);
+        if (!rc) rc = multidot<double>(nullptr, 0, 0, (const double*)tmp, p->npts, part, res, p->stream);
+        if (!rc) rc = multidot<double>(nullptr, 0, 0, (const double*)u[l], p->npts, part, res + 1, p->stream);
+      }
+      double nn[2] = {0.0, 0.0};
+      if (!rc) rc = readback(p, res, 2, nn);
+      if (rc) return rc;
+      const double e = nn[1] > 0 ? std::sqrt(nn[0] / nn[1]) : 0.0;
+      if (e_ref) e_ref[l] = e;
+      if (e <= tol) converged = true;
+    }
+  }
+  return worst;
+}
+
 }  // extern "C"
