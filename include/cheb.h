@@ -101,8 +101,10 @@ typedef struct cheb_solve_opts {
   int32_t maxiter;       /* maximum operator applications (0 = 10000) */
   int32_t inner_m;       /* LGMRES Krylov dimension per restart cycle (0 = 30) */
   int32_t outer_k;       /* LGMRES augmentation vectors (0 = 3, negative = none, max 6) */
-  double ir_inner_rtol;  /* MIXED: relative tolerance of each FP32 inner solve (0 = 1e-3); an inner
-                            solve also stops when a restart cycle gains less than 10% */
+  double ir_inner_rtol;  /* MIXED: smallest relative tolerance of an FP32 inner solve (0 = 1e-3);
+                            each inner solve targets max(ir_inner_rtol, 0.3 x the reduction the
+                            outer residual still needs) and also stops when a restart cycle gains
+                            less than 10% (the FP32 operator's floor) */
   int32_t ir_max_outer;  /* MIXED: maximum FP64 refinement steps (0 = 50) */
   int32_t flags;         /* bit 0: use the initial guess in u_inout (else start from 0);
                             bit 1: right-precondition LGMRES by fast diagonalisation of the

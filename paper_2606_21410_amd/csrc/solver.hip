@@ -180,12 +180,17 @@ struct NoPrec {
 template <typename T, typename ApplyFn, typename PrecFn = NoPrec>
 int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_abs, int maxmv,
            KrylovWS<T>& kw, Scratch& sc, Stats& st, double* resid_out, double bnorm, double* hist,
-           int hist_len, double stall = 0.0, bool use_prec = false, PrecFn&& Mi = PrecFn()) {
+           int hist_len, double stall = 0.0, bool use_prec = false, PrecFn&& Mi = PrecFn(),
+           std::vector<int>* zkeep = nullptr) {
   const size_t npts = p->npts;
   hipStream_t s = p->stream;
   const int m = kw.m, kmax = kw.k;
   const size_t ld = kw.ld;
-  std::vector<int> zslot;  // augmentation vectors, most recent first
+  // augmentation vectors, most recent first; with zkeep they persist across
+  // calls on the same operator (the corrections of earlier solves stay search
+  // directions of the next one)
+  std::vector<int> zlocal;
+  std::vector<int>& zslot = zkeep ? *zkeep : zlocal;
   T* w = kw.w;
   ArnoldiState* ast = sc.ast;
   double* dots2 = sc.dots + 80;
@@ -663,6 +668,7 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
     int slow = 0;
     status = CHEB_NOT_CONVERGED;
     int f32mv = 0;
+    std::vector<int> zkeep;  // the inner solves share their augmentation vectors
     for (int it = 0; !rc; ++it) {
       rc = A64(w.x, w.r);
       if (!rc) rc = axpby<double>(w.r, w.bt, 1.0, -1.0, p->npts, p->stream);
@@ -696,8 +702,11 @@ int cheb_solve(cheb_plan* plan, const void* K, const void* f, const void* g_face
       int budget = sp.maxiter - st.matvecs;
       const int cap = 40 * (sp.m + sp.k + 1);
       if (budget > cap) budget = cap;
-      const int r2 = lgmres<float>(p, A32, w.b32, w.d32, true, sp.ir_rtol, budget > 1 ? budget : 1, w.kw,
-                                   w.sc, si, &res32, 1.0, nullptr, 0, 0.9, sp.precond, M32);
+      // the inner solve targets the reduction still needed (with a margin),
+      // but not below ir_inner_rtol: a deep first solve, a short last one
+      const double itol = std::fmax(sp.ir_rtol, 0.3 * tol / rho);
+      const int r2 = lgmres<float>(p, A32, w.b32, w.d32, true, itol, budget > 1 ? budget : 1, w.kw,
+                                   w.sc, si, &res32, 1.0, nullptr, 0, 0.9, sp.precond, M32, &zkeep);
       if (r2 < 0) {
         rc = r2;
         break;
