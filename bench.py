@@ -274,13 +274,15 @@ def homogenisation_section(dev, n_struct=32, rtol=1e-10):
     for label, prec in (("batched_mixed", "mixed"), ("batched_fp64", "f64")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Kapp, infos, _ = homogenize(Ks, precision=prec, opts=opts)
+        det = {}
+        Kapp, infos, _ = homogenize(Ks, precision=prec, opts=opts, details=det)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[label] = {"seconds": round(el, 3), "max_matvecs": max(i["matvecs"] for i in infos),
                       "matvecs_per_system": [i["matvecs"] for i in infos],
                       "all_converged": all(i["status"] == 0 for i in infos),
                       "max_relres": max(i["relres_final"] for i in infos)}
+        out[label]["tile_shapes"] = det
         if label == "batched_mixed":
             out["K_app_first"] = [[round(v, 6) for v in row] for row in Kapp[0]]
         _log(f"homogenisation {label}: {el:.3f} s")

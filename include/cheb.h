@@ -375,6 +375,17 @@ int cheb_batch_set_stream(cheb_batch* batch, void* stream);
 int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const* f, const void* const* g_faces,
                      void* const* u_inout, const cheb_solve_opts* opts, cheb_solve_info* infos);
 
+/* Tile shapes the batch's autotuner chose.  On its first solve in each field
+ * precision a batch times the three-pass matrix-core apply of every size group
+ * over all the group's members with both tile shapes (see
+ * cheb_plan_set_tile_shape; 4 applies each, HIP events on the batch's stream)
+ * and keeps the faster one for that group.  out (host) receives 4 values per
+ * matrix-core group, up to len entries: nodes per axis, chosen shape (-1 if
+ * not tuned yet), nanoseconds per apply with shape 0 and with shape 1.
+ * field_precision: CHEB_F64 (FP64 passes) or CHEB_F32 (the FP32 passes of
+ * MIXED batches).  Returns the number of groups written, or a negative error. */
+int cheb_batch_tile_shapes(const cheb_batch* batch, int32_t field_precision, int32_t* out, int32_t len);
+
 int cheb_batch_destroy(cheb_batch* batch);
 
 #ifdef __cplusplus

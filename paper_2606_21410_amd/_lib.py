@@ -100,6 +100,7 @@ _SIGS = {
     "cheb_batch_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                         ctypes.POINTER(_vp), ctypes.POINTER(cheb_solve_opts),
                                         ctypes.POINTER(cheb_solve_info)]),
+    "cheb_batch_tile_shapes": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "cheb_batch_destroy": (ctypes.c_int, [_vp]),
     "cheb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cheb_last_error": (ctypes.c_char_p, []),

@@ -374,6 +374,15 @@ class Batch:
                                                       ctypes.c_size_t(need)))
         return self._ws
 
+    def tile_shapes(self, precision="f64"):
+        """The autotuner's choice per matrix-core size group after a solve:
+        list of dicts {n, shape, us_shape0, us_shape1} (shape -1: not tuned)."""
+        buf = (ctypes.c_int32 * 256)()
+        prec = L.CHEB_F64 if precision == "f64" else L.CHEB_F32
+        ng = L.check(self.lib.cheb_batch_tile_shapes(self._h, prec, buf, 256))
+        return [{"n": buf[4 * i], "shape": buf[4 * i + 1], "us_shape0": buf[4 * i + 2] / 1e3,
+                 "us_shape1": buf[4 * i + 3] / 1e3} for i in range(ng)]
+
     def solve(self, Ks, fs, gs, us=None, opts=None):
         """Solve every system; returns (list of full-grid solutions, list of info dicts)."""
         opts = opts or SolveOptions()
@@ -465,12 +474,14 @@ def solve_1d(K, f, g, lo=-1.0, hi=1.0, bc=(L.CHEB_DIRICHLET,) * 2, precision="f6
     return u3[:, 1, 1].contiguous(), info
 
 
-def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", opts=None, device="cuda"):
+def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", opts=None, device="cuda",
+               details=None):
     """Apparent conductivity tensors of several microstructures (Section 3.3):
     three load cases per microstructure (unit mean gradient along x, y, z
     through Dirichlet faces, zero flux elsewhere) solved together in one batch,
     then K_app[b][a] = <K du^(a)/dx_b>_CC / G_a with Clenshaw-Curtis volume
-    averages.  Returns (list of 3x3 nested lists, per-system infos, solutions)."""
+    averages.  Returns (list of 3x3 nested lists, per-system infos, solutions);
+    a dict passed as `details` receives the batch's tuned tile shapes."""
     grids, KK, ff, gg = [], [], [], []
     for K in Ks:
         n = tuple(K.shape)
@@ -482,6 +493,10 @@ def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", op
             gg.append(g)
     batch = Batch(grids, precision, device)
     us, infos = batch.solve(KK, ff, gg, opts=opts)
+    if details is not None:
+        details["tile_shapes_f64"] = batch.tile_shapes("f64")
+        if precision == "mixed":
+            details["tile_shapes_f32"] = batch.tile_shapes("f32")
     out = []
     for s, K in enumerate(Ks):
         n = tuple(K.shape)

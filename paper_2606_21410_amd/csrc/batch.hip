@@ -33,6 +33,8 @@ constexpr int kMaxCoef = 80;  // per-system coefficient slots (m + k + 2 <= 72)
 struct ApplyGroup {
   int rep;                    // system whose plan supplies N, box and tables
   bool dense;                 // matrix-core route (else per-system FFT passes)
+  int shape[2] = {-1, -1};    // tile shape the autotuner chose, [FP64, FP32] (-1: not yet tuned)
+  float tuned_us[2][2] = {{-1.f, -1.f}, {-1.f, -1.f}};  // its timings per shape
   std::vector<int> members;   // system ids
   DenseSys* dsys = nullptr;   // device table, one entry per member
   int* dact = nullptr;        // device list of active member indices
@@ -439,6 +441,64 @@ int bprec(cheb_batch* B, const T* in, T* out, T* pa, T* pb) {
     if (rc) return rc;
   }
   return CHEB_OK;
+}
+
+// Autotuner of the batched operator: for every matrix-core size group not yet
+// tuned in this precision, time the group's three-pass apply over all its
+// members with each tile shape (HIP events, 4 applies after a warm-up) and
+// keep the faster shape for the group's launches.
+template <typename T>
+int btune(cheb_batch* B, const T* K, const T* x, T* y) {
+  const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
+  bool need = false;
+  for (auto& g : B->groups) need = need || (g.dense && g.shape[pi] < 0);
+  if (!need) return CHEB_OK;
+  int rc = set_active(B, std::vector<char>(B->nprob, 1));
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  rc = hip_check(hipEventCreate(&e0), "hipEventCreate");
+  if (rc) return rc;
+  rc = hip_check(hipEventCreate(&e1), "hipEventCreate");
+  if (rc) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  for (auto& g : B->groups) {
+    if (!g.dense || g.shape[pi] >= 0 || rc) continue;
+    cheb_plan* rep = B->plans[g.rep];
+    const int nm = (int)g.hact.size();
+    auto run = [&]() -> int {
+      for (int pass = 0; pass < 3; ++pass) {
+        const int r = launch_dense_batch<T>(rep, 2 - pass, pass == 0, K, x, y, g.dsys, g.dact, nm, B->stream);
+        if (r) return r;
+      }
+      return CHEB_OK;
+    };
+    float best = 1e30f;
+    int bv = 0;
+    for (int v = 0; v < 2 && !rc; ++v) {
+      for (int a = 0; a < 3; ++a) rep->dense_var[a][pi] = v;
+      rc = run();
+      if (!rc) rc = hip_check(hipEventRecord(e0, B->stream), "hipEventRecord");
+      for (int r = 0; r < 4 && !rc; ++r) rc = run();
+      if (!rc) rc = hip_check(hipEventRecord(e1, B->stream), "hipEventRecord");
+      if (!rc) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (rc) break;
+      g.tuned_us[pi][v] = 1e3f * ms / 4.f;
+      if (ms < best) {
+        best = ms;
+        bv = v;
+      }
+    }
+    if (rc) break;
+    for (int a = 0; a < 3; ++a) rep->dense_var[a][pi] = bv;
+    g.shape[pi] = bv;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 enum { RUN = -100 };
@@ -938,12 +998,18 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
     tol[s] = std::fmax(bp.rtol * bnorm[s], bp.atol);
     if (bnorm[s] == 0.0) state[s] = CHEB_OK;
   }
+  // tile shapes of the size groups (timed on the first solve in each precision;
+  // the outputs land in scratch fields that are rewritten before use)
+  rc = btune<double>(B, w.K64, w.bt, w.t1);
+  if (rc) return rc;
   if (B->prec == CHEB_F64) {
     rc = blgmres<double>(B, w.K64, w.bt, w.x, !bp.warm, tol, bp.maxiter, w.kw64, w.sc, state, resid, mv, restarts,
                          0.0, bp.precond);
   } else {
     // FP64 refinement around lockstep FP32 inner solves
     rc = cast_f64_f32(w.K32, w.K64, 1.0, round_up(B->P, 64), st);
+    if (!rc) rc = cast_f64_f32(w.b32, w.bt, 1.0, round_up(B->P, 64), st);
+    if (!rc) rc = btune<float>(B, w.K32, w.b32, w.d32);
     std::vector<double> prev(ns, HUGE_VAL), rho(ns, 0.0), scal((size_t)ns * 8, 0.0);
     std::vector<int> slow(ns, 0);
     std::vector<char> on(ns, 0);
@@ -998,6 +1064,9 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
           istate[s] = RUN;
           irs[s]++;
           budget = std::min(budget, bp.maxiter - mv[s]);
+          // as the single-system refinement: the reduction still needed, not
+          // below ir_inner_rtol
+          itol[s] = std::fmax(bp.ir_rtol, 0.3 * tol[s] / rho[s]);
         }
       const int cap = 40 * (bp.m + bp.k + 1);
       budget = std::max(1, std::min(budget, cap));
@@ -1046,6 +1115,23 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
     worst = std::max(worst, stt);
   }
   return worst;
+}
+
+int cheb_batch_tile_shapes(const cheb_batch* batch, int32_t field_precision, int32_t* out, int32_t len) {
+  if (!batch || (len > 0 && !out) || (field_precision != CHEB_F64 && field_precision != CHEB_F32)) {
+    set_error("invalid argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  const int pi = field_precision == CHEB_F64 ? 0 : 1;
+  int k = 0;
+  for (const auto& g : batch->groups) {
+    if (!g.dense) continue;
+    const int vals[4] = {batch->plans[g.rep]->g.n[0], g.shape[pi], (int)(g.tuned_us[pi][0] * 1000.f),
+                         (int)(g.tuned_us[pi][1] * 1000.f)};
+    for (int q = 0; q < 4; ++q)
+      if (k < len) out[k++] = vals[q];
+  }
+  return k / 4;
 }
 
 int cheb_batch_destroy(cheb_batch* batch) {

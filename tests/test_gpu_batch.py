@@ -122,3 +122,30 @@ def test_homogenize_vs_oracle():
         log(f"K_app n={n[0]}: {np.array(Ka)} ref {ref}")
         np.testing.assert_allclose(np.array(Ka), ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
     np.testing.assert_allclose(np.array(Kapp[2]), 2.5 * np.eye(3), atol=1e-10)
+
+
+def test_batch_autotuned_tile_shapes():
+    """The batch times both tile shapes of every matrix-core size group on its
+    first solve in each precision and keeps the faster; the choice is reported
+    and the solves with it match the oracle (the other tests run with it too)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Batch, SolveOptions
+    systems = _systems([17, 33], 40)
+    d = lambda a: to_dev(a, torch.float64)
+    B = Batch([(n, BOX[0], BOX[1], bc) for n, bc, _, _, _ in systems], "mixed")
+    assert all(t["shape"] == -1 for t in B.tile_shapes("f64"))
+    us, infos = B.solve([d(s[2]) for s in systems], [d(s[3]) for s in systems], [d(s[4]) for s in systems],
+                        opts=SolveOptions(rtol=1e-11, maxiter=4000, precond=True))
+    for prec in ("f64", "f32"):
+        shapes = B.tile_shapes(prec)
+        log(f"tuned {prec}: {shapes}")
+        assert sorted(t["n"] for t in shapes) == [17, 33]
+        for t in shapes:
+            assert t["shape"] in (0, 1) and t["us_shape0"] > 0 and t["us_shape1"] > 0
+            best = min(t["us_shape0"], t["us_shape1"])
+            assert (t["us_shape0"], t["us_shape1"])[t["shape"]] == best
+    for (n, bc, K, f, g), u, info in zip(systems, us, infos):
+        assert info["status"] == 0
+        ref = O.solve(O.Grid3(n, BOX[0], BOX[1], bc), K, f, g, tol=1e-14)
+        assert rel_l2(to_host(u), ref) <= 1e-8
