@@ -456,7 +456,7 @@ def thermal_newton_cold(dev, levels=(128, 256), tol=1e-11, max_steps=20, maxiter
     return out
 
 
-def refinement_stop_section(dev, levels=(33, 65, 129, 257), tol=1e-3):
+def refinement_stop_section(dev, levels=(33, 65, 129, 257), tol=2e-3):
     """Hierarchical refinement with its stopping rule (Algorithm 4) on the
     two-phase generator (spheres R 0.15, vf 0.2, contrast 10, width 2/256):
     preconditioned FP64 solves level by level until the refinement indicator
@@ -768,6 +768,12 @@ def main():
                 "traffic_unit": "MB per apply (rocprofv3 TCC request counters, copy-calibrated, "
                                 f"{LAUNCHES_PER_APPLY} launches)",
                 "traffic_over_algorithmic": round(traffic / bytes_per_apply, 3) if traffic else None,
+                # what three separate axis passes must move (u and K each pass,
+                # y read back by the two accumulating passes): the measured
+                # traffic against it shows whether the kernels re-read anything
+                "traffic_over_three_pass_minimum": (round(rec["traffic_bytes_per_launch"]
+                                                          / rec["design_min_bytes_per_launch"], 3)
+                                                    if rec and "design_min_bytes_per_launch" in rec else None),
                 "algorithmic_mb_per_apply": round(bytes_per_apply / 1e6, 2),
                 "algorithmic_bytes_per_point": ALG_BYTES_PER_POINT_F64,
                 "kernel": kname + f"; {LAUNCHES_PER_APPLY} launches per apply)",
