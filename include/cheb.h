@@ -325,6 +325,30 @@ int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis);
  * Uses 4 fields of workspace.  Synchronises. */
 int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[3]);
 
+/* Fast-diagonalisation preconditioner, the one the preconditioned solves use
+ * (an addition to the paper's plain LGMRES).  With constant K = kc the reduced
+ * operator of Section 2.3.1 is kc (A_x (+) A_y (+) A_z), a Kronecker sum of the
+ * 1-D reduced second-derivative operators (boundary rows eliminated per axis);
+ * this call applies its exact inverse,
+ *     out = (V_x V_y V_z) diag(1 / (kc (lx_i + ly_j + lz_k))) (V_x V_y V_z)^{-1} in,
+ * A_a = V_a diag(l_a) V_a^{-1}, as six axis contractions on the matrix cores
+ * (even-odd split on axes with the same face type at both ends), or its
+ * transpose with CHEB_APPLY_TRANSPOSE in flags (the adjoint solves use it).
+ *   field_precision: CHEB_F64 or CHEB_F32, the type of in and out (any plan
+ *     precision: the plan keeps the factors in both);
+ *   in, out: device fields of n0 n1 n2 values; boundary values of in are
+ *     ignored, those of out are set to 0; out may equal in;
+ *   kc: positive and finite.
+ * Needs two interior blocks of workspace (2 (n0-2)(n1-2)(n2-2) values of
+ * field_precision, each rounded up to 256 bytes; a preconditioned solve's
+ * workspace always holds them).  The first call on a plan computes the 1-D
+ * eigen-decompositions on the host and synchronises; later calls are
+ * asynchronous.  Errors: CHEB_ERR_INVALID_ARG (null pointer, precision, flags,
+ * kc), CHEB_ERR_WORKSPACE, CHEB_ERR_UNSUPPORTED (an eigen-decomposition
+ * failed). */
+int cheb_precond_apply(cheb_plan* plan, int32_t field_precision, double kc, const void* in, void* out,
+                       uint32_t flags);
+
 /* Copy of n doubles, src -> dst (device arrays, 16-byte aligned, not
  * overlapping), by the library's stream-copy kernel: 16-byte loads and stores
  * in a grid-stride loop.  The attainable HBM bandwidth the operator's roofline

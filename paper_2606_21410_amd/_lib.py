@@ -88,6 +88,7 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_int32)]),
     "cheb_derivative": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "cheb_flux_average": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "cheb_precond_apply": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp, ctypes.c_uint32]),
     "cheb_debug_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "cheb_debug_gemm": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp]),

@@ -311,6 +311,30 @@ class Plan:
             d["history"] = [hist[i] for i in range(min(steps.value + 1, opts.history_len))]
         return u, d
 
+    def precond(self, r, kc: float, out=None, transpose: bool = False):
+        """Fast-diagonalisation inverse of the constant-coefficient reduced
+        operator (cheb_precond_apply): out = (kc (A_x + A_y + A_z))^{-1} r on
+        the interior, 0 on the boundary; r is float64 or float32."""
+        self._sync_stream()
+        prec = {torch.float64: L.CHEB_F64, torch.float32: L.CHEB_F32}.get(r.dtype)
+        if prec is None:
+            raise ValueError("r: expected float64 or float32")
+        m = [d - 2 for d in self.n]
+        es = 8 if prec == L.CHEB_F64 else 4
+        pb = -(-m[0] * m[1] * m[2] * es // 256) * 256
+        need = max(self.workspace_bytes(), 2 * pb)
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws_bytes = need
+            L.check(self.lib.cheb_plan_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()),
+                                                     ctypes.c_size_t(need)))
+        if out is None:
+            out = torch.empty_like(r)
+        L.check(self.lib.cheb_precond_apply(self._h, prec, float(kc), self._field(r, "r", r.dtype),
+                                            self._field(out, "out", r.dtype),
+                                            L.CHEB_APPLY_TRANSPOSE if transpose else 0))
+        return out
+
     def flux_average(self, K, u):
         self._sync_stream()
         self.ensure_workspace()

@@ -31,6 +31,8 @@ struct PrecondAxis {
   int m;
   int split;  // centro-symmetric factors whose even and odd halves fill whole 16-row blocks
   size_t off_V, off_Vi, off_lam;
+  // matrix-core fragment tables (m <= 128): [0: the V^{-1} side, 1: the V side][transposed]
+  size_t off_tab[2][2];
 };
 
 }  // namespace cheb

@@ -386,26 +386,37 @@ __global__ __launch_bounds__(256) void k_axis_gemm(GemmArgs g) {
 }
 
 // Contraction of packed blocks along one axis with a dense m x m matrix,
-// y_i = sum_k M[i][k] x_k per pencil (M^T with trans), for m <= MP <= 128.
-// A tile of 16 pencils is staged in LDS by coalesced loads, multiplied on the
-// matrix cores by register-resident 16-row fragments of M (one wave per 16
-// output rows, the whole K range per wave, rows and columns past m zero), and
-// written back through LDS so that the stores coalesce as well.  Workgroups
-// walk the tiles of all nb blocks.
+// y_i = sum_k M[i][k] x_k per pencil (M^T with trans), for m <= MP <= 128, on
+// the matrix cores (MFMA 16x16x4).  One wave owns a task of 16 pencils and
+// computes every output row of them: the pencils' values are the B operand,
+// loaded once from memory straight into registers in MFMA layout; the A
+// operand -- M cut into 16-row blocks and 4-wide k-steps, zero past m -- comes
+// from a fragment table that the workgroup copies into LDS once (written on
+// the host at setup, one table per axis, side and transposition).  Nothing is
+// exchanged between waves, so a workgroup synchronises only after the table
+// copy; each wave streams its tasks (loads, 8 x KS matrix-core steps, stores).
+//
+// The k order of the steps is the row order of the accumulator layout of the
+// same type (fdm_kmap), so that the output of one contraction, held in
+// registers, is the B operand of another: the middle pair -- the last forward
+// and the first backward contraction, both along the same axis, with the
+// eigenvalue scaling between them -- runs as one kernel.
 //
 // Input and output are each either packed interior blocks (nb blocks of
 // m0 x m1 x m2 back to back) or full fields (n_a = m_a + 2 nodes per axis, the
 // interior block at node offset (1,1,1), field b at offs[b]), so the packing
 // of the first contraction and the unpacking of the last one are part of
-// them.  With lam set, the output is divided by Kc (lam0[i0] + lam1[i1] +
+// them; the last one (full output) also zeroes the boundary nodes of its
+// fields.  With lam set, the output is divided by Kc (lam0[i0] + lam1[i1] +
 // lam2[i2]): the eigenvalue scaling between the two halves of the
 // preconditioner.
 struct FdmArgs {
   const int* gate;            // null, or a device flag: the contraction does nothing while it reads 0
-  const void* M;
+  const void* tab;            // fragment table of the (first) contraction
+  const void* tab2;           // fragment table of the middle pair's second contraction
   const void* X;
   void* Y;
-  int m, axis, trans, nb;
+  int m, axis, nb;
   int m0, m1, m2;             // dims of one packed block
   const long long* offs;      // full layouts: field b starts at offs[b] (null: b * n0 n1 n2)
   const void* lam0;           // eigenvalues per axis (scaling)
@@ -416,245 +427,295 @@ struct FdmArgs {
   const double* kc;
 };
 
-// fusion modes: X is a full field / Y is a full field / Y is scaled
-enum { FDM_XFULL = 1, FDM_YFULL = 2, FDM_SCALE = 4 };
-constexpr int kFdmMaxNb = 256;  // blocks whose offsets and Kc a workgroup keeps in LDS
+// fusion modes: X is a full field / Y is a full field / Y is scaled / the
+// middle pair (first table, scaling, second table)
+enum { FDM_XFULL = 1, FDM_YFULL = 2, FDM_SCALE = 4, FDM_MID = 8 };
 
-// SPLIT (axes whose 1-D operator is centro-symmetric, so that the factors are
-// V = Q diag(Vs, Vw) and V^{-1} = diag(Vs^{-1}, Vw^{-1}) Q^T with Q the
-// symmetric / antisymmetric node-pair basis; modes ordered symmetric first):
-//   1  the input enters through Q^T: the tile is restaged as pair sums
-//      x_j + x_{m-1-j} (rows j < ps, the middle node kept) and differences
-//      (rows ps + j), and each output row contracts with one half only;
-//   2  the output leaves through Q: rows i < ps hold the symmetric part a_i,
-//      rows ps + i the antisymmetric part b_i, and node k receives a_k + b_k,
-//      a_i - b_i (k = m-1-i) or a_p (the middle node).
-// Either way every row does half the multiply-adds.  Needs ps = ceil(m/2) to
-// be a multiple of 16, so that a wave's 16 rows are all of one half.
+// KIND of one contraction (axes whose 1-D operator is centro-symmetric, so
+// that the factors are V = Q diag(Vs, Vw) and V^{-1} = diag(Vs^{-1}, Vw^{-1}) Q^T
+// with Q the symmetric / antisymmetric node-pair basis; modes ordered
+// symmetric first):
+//   0  plain: every row block runs the whole k range;
+//   1  the input enters through Q^T: the operand is the pair sums
+//      x_j + x_{m-1-j} (the middle node of odd m kept) for the symmetric row
+//      blocks and the differences for the antisymmetric ones;
+//   2  the output leaves through Q: row i of the symmetric blocks is a_i, of
+//      the antisymmetric ones b_i (same lane and register), and node i
+//      receives a_i + b_i, node m-1-i a_i - b_i, the middle node a_p.
+// Kinds 1 and 2 do half the multiply-adds; they need ps = ceil(m/2) to be a
+// multiple of 16, and then ps = MP/2.  The middle pair takes SPLIT 3: kind 1
+// for the first table, kind 2 for the second (SPLIT 0: both plain).
+
+// k-index of MFMA step ks for lane group lk (lane / 16): the row that the
+// accumulator of the same type holds in register ks % 4 of row block ks / 4
+__host__ __device__ constexpr int fdm_kmap(int ks, int lk, bool f32) {
+  return f32 ? 16 * (ks / 4) + 4 * lk + (ks % 4) : 4 * ks + lk;
+}
+
+// linear offset of boundary node u of an n0 x n1 x n2 field (faces x, y, z)
+__device__ inline long long face_node(long long u, int n0, int n1, int n2) {
+  const long long fxy = (long long)n1 * n2, fxz = (long long)n0 * n2, fyz = (long long)n0 * n1;
+  int i, j, k;
+  if (u < 2 * fxy) {  // x faces
+    i = u < fxy ? 0 : n0 - 1;
+    u %= fxy;
+    j = (int)(u / n2);
+    k = (int)(u % n2);
+  } else if ((u -= 2 * fxy) < 2 * fxz) {  // y faces
+    j = u < fxz ? 0 : n1 - 1;
+    u %= fxz;
+    i = (int)(u / n2);
+    k = (int)(u % n2);
+  } else {  // z faces
+    u -= 2 * fxz;
+    k = u < fyz ? 0 : n2 - 1;
+    u %= fyz;
+    i = (int)(u / n1);
+    j = (int)(u % n1);
+  }
+  return ((long long)i * n1 + j) * n2 + k;
+}
+
+// fragment-table sizes (elements) of one contraction of padded width MP
+__host__ __device__ constexpr int fdm_tab_elems(int MP, int kind) { return (MP / 16) * (kind ? MP / 8 : MP / 4) * 64; }
+
+constexpr int kFdmWaves = 4;  // waves per workgroup
+
+template <typename T>
+__host__ __device__ constexpr int fdm_lds_bytes(int MP, int MODE, int SPLIT) {
+  const bool mid = MODE & FDM_MID;
+  const int ka = mid ? (SPLIT ? 1 : 0) : SPLIT, kb = mid ? (SPLIT ? 2 : 0) : 0;
+  return (fdm_tab_elems(MP, ka) + (mid ? fdm_tab_elems(MP, kb) : 0) + ((MODE & FDM_SCALE) ? 3 * 128 : 0)) *
+         (int)sizeof(T);
+}
+
+// N 16-byte words from global memory into LDS by the workgroup, in rounds of
+// at most 16 loads per lane that are all issued before the first store
+template <int N>
+__device__ __forceinline__ void copy_to_lds(const int4* __restrict__ src, int4* dst, int tid) {
+  static_assert(N > 0, "empty table");
+  constexpr int NT = 64 * kFdmWaves, PER = (N + NT - 1) / NT, R = PER < 16 ? PER : 16;
+#pragma unroll
+  for (int base = 0; base < PER; base += R) {
+    int4 v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = tid + (base + i) * NT;
+      v[i] = src[e < N ? e : N - 1];  // unconditional: the loads stay in registers
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = tid + (base + i) * NT;
+      if (e < N) dst[e] = v[i];
+    }
+  }
+}
+
+// acc[rb] (16 rows of row block rb, every rb) = table x B, k-step by k-step
+// (KIND 0: KF steps over B[ks]; kinds 1, 2: KH steps, the symmetric blocks
+// over B[ks], the antisymmetric ones over B[KH + ks])
+template <typename T, int KIND, int NB, int KF, int KH>
+__device__ __forceinline__ void contract(const T* __restrict__ tab, int lane, const T (&B)[KF],
+                                         typename Mfma<T>::v4 (&acc)[NB]) {
+  constexpr int NKS = KIND ? KH : KF;
+#pragma unroll
+  for (int rb = 0; rb < NB; ++rb) acc[rb] = typename Mfma<T>::v4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) {
+    // one step's table reads at a time: hoisting more only costs registers
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int rb = 0; rb < NB; ++rb)
+      acc[rb] = Mfma<T>::mac(tab[(rb * NKS + ks) * 64 + lane], B[(KIND && rb >= NB / 2) ? KH + ks : ks], acc[rb]);
+  }
+}
+
 template <typename T, int MP, int MODE, int SPLIT>
-__global__ __launch_bounds__(4 * MP, 4) void k_fdm_contract(FdmArgs g) {
+__global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
   if (g.gate && !*g.gate) return;
-  constexpr int NW = MP / 16, NT = 64 * NW, C = 16, SC = C + 1, KS = MP / 4;
-  constexpr int KSE = SPLIT ? MP / 8 : KS;  // k-steps each row block runs
-  constexpr int EPT = MP * C / NT;  // = 4
-  constexpr bool XF = MODE & FDM_XFULL, YF = MODE & FDM_YFULL, SCL = MODE & FDM_SCALE;
+  constexpr int NB = MP / 16, KF = MP / 4, KH = MP / 8;
+  constexpr bool F32 = sizeof(T) == sizeof(float);
+  constexpr bool XF = MODE & FDM_XFULL, YF = MODE & FDM_YFULL, SCL = MODE & FDM_SCALE, MID = MODE & FDM_MID;
   constexpr bool FULL = XF || YF;
+  constexpr int SA = MID ? (SPLIT ? 1 : 0) : SPLIT;  // kind of the first (or only) contraction
+  constexpr int SB = MID ? (SPLIT ? 2 : 0) : 0;      // kind of the second one
+  constexpr int TA = fdm_tab_elems(MP, SA), TB = MID ? fdm_tab_elems(MP, SB) : 0;
+  static_assert(!MID || SCL, "the middle pair scales between its contractions");
+  static_assert(!MID || SPLIT == 0 || SPLIT == 3, "middle pair: SPLIT 0 or 3");
+  static_assert(MID || SPLIT <= 2, "SPLIT 3 is the middle pair's");
+  static_assert(SPLIT == 0 || MP >= 32, "split contractions need two row blocks");
   typedef typename Mfma<T>::v4 V4;
-  __shared__ T Xs[MP * SC];
-  __shared__ int pbx[2][C], pby[2][C];    // first element of each pencil in X and Y (-1 past the last)
-  __shared__ double psc[SCL ? 2 : 1][C];  // the pencil's transverse eigenvalues and 1 / Kc (scaling)
-  __shared__ double pik[SCL ? 2 : 1][C];
-  __shared__ T lam_s[SCL ? 3 : 1][SCL ? 128 : 1];  // every axis' eigenvalues (the fused path has m <= 128)
-  __shared__ int boff[FULL ? kFdmMaxNb : 1];
-  __shared__ double bik[SCL ? kFdmMaxNb : 1];
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tabA = (T*)smem;
+  T* tabB = tabA + TA;
+  T* lam_s = tabB + TB;  // SCL: every axis' eigenvalues, 128 each
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m = g.m, axis = g.axis;
-  const T* M = (const T*)g.M;
   const T* X = (const T*)g.X;
   T* Y = (T*)g.Y;
-  const int n1 = g.m1 + 2, n2 = g.m2 + 2;
+  const int n0 = g.m0 + 2, n1 = g.m1 + 2, n2 = g.m2 + 2;
   const int plane = g.m1 * g.m2, bsz = plane * g.m0;
-  const int fplane = n1 * n2, fsz = fplane * (g.m0 + 2);
+  const int fplane = n1 * n2, fsz = fplane * n0;
   const int pstride = axis == 2 ? 1 : axis == 1 ? g.m2 : plane;  // packed
   const int fstride = axis == 2 ? 1 : axis == 1 ? n2 : fplane;   // full
   const int sxa = XF ? fstride : pstride, sya = YF ? fstride : pstride;
   const int ppb = bsz / m;  // pencils per block
   const int npen = ppb * g.nb;
-  const int ntiles = (npen + C - 1) / C;
-  const bool contig = axis == 2;
-  const int tot = m * C;  // tile elements
-  // per-workgroup tables: eigenvalues, field offsets and 1 / Kc of the blocks
-  if (SCL) {
+  const int ntasks = (npen + 15) / 16;
+  const int ps = (m + 1) / 2, ph = m / 2;  // symmetric / antisymmetric halves (split kinds: ps = MP/2)
+
+  // this lane's pencil of a task: its first element in X and Y, and (scaling)
+  // the block's 1 / Kc and the pencil's indices across the axis
+  bool valid = false;
+  long long bx = 0, by = 0;
+  int ia = 0, ib = 0, bi = 0;
+  auto locate = [&](int task) {
+    const int q = task * 16 + li;
+    valid = q < npen;
+    if (!valid) return;
+    bi = q / ppb;
+    const int qq = q - bi * ppb;
+    int i0 = 0, i1 = 0, i2 = 0;  // interior indices (axis index 0)
+    if (axis == 0) {
+      i1 = qq / g.m2;
+      i2 = qq - i1 * g.m2;
+    } else if (axis == 1) {
+      i0 = qq / g.m2;
+      i2 = qq - i0 * g.m2;
+    } else {
+      i0 = qq / g.m1;
+      i1 = qq - i0 * g.m1;
+    }
+    const long long pk = (long long)bi * bsz + ((long long)i0 * g.m1 + i1) * g.m2 + i2;
+    long long fk = 0;
+    if (FULL) fk = (g.offs ? g.offs[bi] : (long long)bi * fsz) + ((long long)(i0 + 1) * n1 + (i1 + 1)) * n2 + (i2 + 1);
+    bx = XF ? fk : pk;
+    by = YF ? fk : pk;
+    ia = axis == 0 ? i1 : i0;  // the first transverse axis' index
+    ib = axis == 2 ? i1 : i2;  // the second one's
+  };
+  // the B operand: row fdm_kmap(ks, lk) of the pencil at step ks (kind 1: the
+  // pair sums for the symmetric blocks, then the differences; kind 2: the
+  // first ps rows, then the rest)
+  T B[KF];
+  auto load = [&]() {
+    if (SA == 1) {
+#pragma unroll
+      for (int ks = 0; ks < KH; ++ks) {
+        const int j = fdm_kmap(ks, lk, F32);  // < ps
+        const T xj = valid ? X[bx + (long long)j * sxa] : T(0);
+        const T xr = valid && j < ph ? X[bx + (long long)(m - 1 - j) * sxa] : T(0);
+        B[ks] = j < ph ? xj + xr : xj;  // j = ph: the middle node of odd m
+        B[KH + ks] = j < ph ? xj - xr : T(0);
+      }
+    } else if (SA == 2) {
+#pragma unroll
+      for (int ks = 0; ks < KH; ++ks) {
+        const int j = fdm_kmap(ks, lk, F32);
+        B[ks] = valid ? X[bx + (long long)j * sxa] : T(0);
+        B[KH + ks] = valid && ps + j < m ? X[bx + (long long)(ps + j) * sxa] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KF; ++ks) {
+        const int j = fdm_kmap(ks, lk, F32);
+        B[ks] = valid && j < m ? X[bx + (long long)j * sxa] : T(0);
+      }
+    }
+  };
+  // the fragment tables (and eigenvalues) into LDS, 16 bytes per lane, the
+  // loads of a table in flight together (a load-store loop would pay the L2
+  // latency once per iteration); before the first task's operand loads, which
+  // would hold the table's loads back behind memory latency
+  copy_to_lds<TA * (int)sizeof(T) / 16>((const int4*)g.tab, (int4*)tabA, tid);
+  if constexpr (MID) copy_to_lds<TB * (int)sizeof(T) / 16>((const int4*)g.tab2, (int4*)tabB, tid);
+  if constexpr (SCL) {
     const T* lp[3] = {(const T*)g.lam0, (const T*)g.lam1, (const T*)g.lam2};
     const int md[3] = {g.m0, g.m1, g.m2};
-    for (int a = 0; a < 3; ++a)
-      for (int i = tid; i < 128; i += NT) lam_s[SCL ? a : 0][SCL ? i : 0] = i < md[a] ? lp[a][i] : T(0);
-    for (int b = tid; b < g.nb; b += NT) bik[SCL ? b : 0] = g.sys ? 1.0 / g.kc[g.sys[b]] : g.inv_k;
+    for (int e = tid; e < 3 * 128; e += 64 * kFdmWaves) {
+      const int a = e / 128, i = e - a * 128;
+      lam_s[e] = i < md[a] ? lp[a][i] : T(0);
+    }
   }
-  if (FULL)
-    for (int b = tid; b < g.nb; b += NT) boff[FULL ? b : 0] = g.offs ? (int)g.offs[b] : b * fsz;
-  __syncthreads();
-  // pencil bookkeeping of tile TL into slot SL
-  auto cols = [&](int tl, int sl) {
-    if (tid < C) {
-      const int q = tl * C + tid;
-      int bx = -1, by = -1;
-      double sc = 0.0, ik = 0.0;
-      if (tl < ntiles && q < npen) {
-        const int bi = q / ppb, qq = q - bi * ppb;
-        // the pencil's interior indices (axis index 0)
-        int i0 = 0, i1 = 0, i2 = 0;
-        if (axis == 0) {
-          i1 = qq / g.m2;
-          i2 = qq - i1 * g.m2;
-        } else if (axis == 1) {
-          i0 = qq / g.m2;
-          i2 = qq - i0 * g.m2;
-        } else {
-          i0 = qq / g.m1;
-          i1 = qq - i0 * g.m1;
-        }
-        const int pk = bi * bsz + (i0 * g.m1 + i1) * g.m2 + i2;
-        const int fk = FULL ? boff[FULL ? bi : 0] + ((i0 + 1) * n1 + (i1 + 1)) * n2 + (i2 + 1) : 0;
-        bx = XF ? fk : pk;
-        by = YF ? fk : pk;
-        if (SCL) {
-          const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;
-          const int ia = a0 == 0 ? i0 : i1, ib = a1 == 1 ? i1 : i2;
-          sc = double(lam_s[SCL ? a0 : 0][ia]) + double(lam_s[SCL ? a1 : 0][ib]);
-          ik = bik[SCL ? bi : 0];
-        }
-      }
-      pbx[sl][tid] = bx;
-      pby[sl][tid] = by;
-      if (SCL) {
-        psc[SCL ? sl : 0][tid] = sc;
-        pik[SCL ? sl : 0][tid] = ik;
-      }
-    }
-  };
-  // element e of a tile -> (node k, pencil c): pencil-contiguous along the
-  // unit-stride axis, pencil-fastest otherwise.  Loads of the tile in slot SL
-  // (element 0 off the tile; every load is issued).
-  auto load = [&](int sl, T* v) {
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT < tot ? tid + q * NT : tot - 1;
-      const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
-      const int b = pbx[sl][c];
-      v[q] = X[b >= 0 ? b + k * sxa : 0];
-    }
-  };
-  int tile = blockIdx.x;
-  int slot = 0;
-  cols(tile, 0);
-  __syncthreads();
-  T v[EPT];
-  load(0, v);
-  // fragments of M: rows 16 wave + li, the whole K range (zero past m)
-  T a[KSE];
-  const int row = 16 * wave + li;
-  const int ps = (m + 1) / 2, ph = m / 2;       // symmetric / antisymmetric halves
-  const bool anti = SPLIT && 16 * wave >= ps;   // uniform per wave
-  const int xoff = anti ? ps : 0;               // first LDS row of the operand half
-#pragma unroll
-  for (int ks = 0; ks < KSE; ++ks) {
-    const int k = 4 * ks + lk;
-    int r = row, col = k;
-    bool ok = row < m && k < m;
-    if (SPLIT == 1) {
-      ok = row < m && k < (anti ? ph : ps);
-    } else if (SPLIT == 2) {
-      r = anti ? row - ps : row;
-      col = anti ? ps + k : k;
-      ok = r < (anti ? ph : ps) && k < (anti ? ph : ps);
-    }
-    const size_t at = g.trans ? (size_t)col * m + r : (size_t)r * m + col;
-    a[ks] = ok ? M[at] : T(0);
+  // the first task's operand, in flight across the barrier
+  int task = blockIdx.x * kFdmWaves + wave;
+  if (task < ntasks) {
+    locate(task);
+    load();
   }
-  for (int e = tid; e < (MP - m) * SC; e += NT) Xs[m * SC + e] = T(0);
-  for (; tile < ntiles; tile += gridDim.x, slot ^= 1) {
-    __syncthreads();  // the previous tile's readers of Xs are done
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      if (e < tot) {
-        const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
-        Xs[k * SC + c] = v[q];
-      }
+  if (YF) {
+    // the boundary nodes of the output fields (the contraction writes the interior)
+    const long long faces = 2LL * ((long long)n1 * n2 + (long long)n0 * n2 + (long long)n0 * n1);
+    for (long long t = (long long)blockIdx.x * 64 * kFdmWaves + tid; t < faces * g.nb;
+         t += (long long)gridDim.x * 64 * kFdmWaves) {
+      const int b = (int)(t / faces);
+      const long long fo = g.offs ? g.offs[b] : (long long)b * fsz;
+      Y[fo + face_node(t - b * faces, n0, n1, n2)] = T(0);
     }
-    cols(tile + gridDim.x, slot ^ 1);
-    __syncthreads();
-    load(slot ^ 1, v);  // the next tile, in flight during this one
-    if (SPLIT == 1) {
-      // node pairs (j, m-1-j), j < ph, into sums (row j) and differences (row ps + j)
-      constexpr int PPT = (MP / 2 * C + NT - 1) / NT;
-      T xa[PPT], xb[PPT];
+  }
+  __syncthreads();
+  for (; task < ntasks; task += gridDim.x * kFdmWaves) {
+    // every row block at once, k-step by k-step: eight independent
+    // accumulation chains, started as soon as the first rows arrive
+    V4 acc[NB];
+    contract<T, SA, NB, KF, KH>(tabA, lane, B, acc);
+    if constexpr (MID) {
+      // the first contraction, scaled, is the second one's B operand
+      const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;
+      const double sc = valid ? double(lam_s[a0 * 128 + ia]) + double(lam_s[a1 * 128 + ib]) : 0.0;
+      const double ik = valid ? (g.sys ? 1.0 / g.kc[g.sys[bi]] : g.inv_k) : 0.0;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int e = tid + q * NT;
-        if (e < ph * C) {
-          const int j = e / C, c = e - j * C;
-          xa[q] = Xs[j * SC + c];
-          xb[q] = Xs[(m - 1 - j) * SC + c];
+      for (int rb = 0; rb < NB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * rb + Mfma<T>::row(lk, r);
+          B[4 * rb + r] = i < m ? T(double(acc[rb][r]) * ik / (sc + double(lam_s[axis * 128 + i]))) : T(0);
         }
-      }
-      __syncthreads();
+      contract<T, SB, NB, KF, KH>(tabB, lane, B, acc);
+    } else if constexpr (SCL) {
+      const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;
+      const double sc = valid ? double(lam_s[a0 * 128 + ia]) + double(lam_s[a1 * 128 + ib]) : 0.0;
+      const double ik = valid ? (g.sys ? 1.0 / g.kc[g.sys[bi]] : g.inv_k) : 0.0;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int e = tid + q * NT;
-        if (e < ph * C) {
-          const int j = e / C, c = e - j * C;
-          Xs[j * SC + c] = xa[q] + xb[q];
-          Xs[(ps + j) * SC + c] = xa[q] - xb[q];
+      for (int rb = 0; rb < NB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * rb + Mfma<T>::row(lk, r);
+          if (i < m) acc[rb][r] = T(double(acc[rb][r]) * ik / (sc + double(lam_s[axis * 128 + i])));
         }
-      }
-      __syncthreads();
     }
-    V4 acc = V4{0, 0, 0, 0};
+    constexpr int SOUT = MID ? SB : SA;  // the kind whose outputs are stored
+    if (valid) {
+      if constexpr (SOUT == 2) {
+        // rows i of the symmetric blocks hold a_i, of the antisymmetric ones b_i
 #pragma unroll
-    for (int ks = 0; ks < KSE; ++ks) acc = Mfma<T>::mac(a[ks], Xs[(xoff + 4 * ks + lk) * SC + li], acc);
-    __syncthreads();  // every wave has read the tile
+        for (int rb = 0; rb < NB / 2; ++rb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * wave + Mfma<T>::row(lk, r);
-      if (i < m) Xs[i * SC + li] = acc[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      if (e < tot) {
-        const int c = contig ? e / m : e % C, k = contig ? e - c * m : e / C;
-        const int b = pby[slot][c];
-        if (b >= 0) {
-          T val;
-          if (SPLIT == 2) {
-            if (k < ph) val = Xs[k * SC + c] + Xs[(ps + k) * SC + c];
-            else if (k >= m - ph) val = Xs[(m - 1 - k) * SC + c] - Xs[(ps + m - 1 - k) * SC + c];
-            else val = Xs[k * SC + c];  // the middle node of odd m
-          } else {
-            val = Xs[k * SC + c];
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * rb + Mfma<T>::row(lk, r);
+            const T a = acc[rb][r], b = acc[rb + NB / 2][r];
+            if (i < ph) {
+              Y[by + (long long)i * sya] = a + b;
+              Y[by + (long long)(m - 1 - i) * sya] = a - b;
+            } else if (i < ps) {
+              Y[by + (long long)i * sya] = a;  // the middle node of odd m
+            }
           }
-          if (SCL)
-            val = T(double(val) * pik[SCL ? slot : 0][c] / (psc[SCL ? slot : 0][c] + double(lam_s[SCL ? axis : 0][k])));
-          Y[b + k * sya] = val;
-        }
+      } else {
+#pragma unroll
+        for (int rb = 0; rb < NB; ++rb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * rb + Mfma<T>::row(lk, r);
+            if (i < m) Y[by + (long long)i * sya] = acc[rb][r];
+          }
       }
     }
-  }
-}
-
-// zero the boundary nodes of field blockIdx.y (at offs[y], or y * n0*n1*n2)
-template <typename T>
-__global__ void k_zero_faces(T* __restrict__ out, const long long* __restrict__ offs, int n0, int n1, int n2,
-                             const int* gate) {
-  if (gate && !*gate) return;
-  T* o = out + (offs ? offs[blockIdx.y] : (long long)blockIdx.y * n0 * n1 * n2);
-  const long long fxy = (long long)n1 * n2, fxz = (long long)n0 * n2, fyz = (long long)n0 * n1;
-  const long long tot = 2 * (fxy + fxz + fyz);
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
-    long long u = t;
-    int i, j, k;
-    if (u < 2 * fxy) {  // x faces
-      i = u < fxy ? 0 : n0 - 1;
-      u %= fxy;
-      j = (int)(u / n2);
-      k = (int)(u % n2);
-    } else if ((u -= 2 * fxy) < 2 * fxz) {  // y faces
-      j = u < fxz ? 0 : n1 - 1;
-      u %= fxz;
-      i = (int)(u / n2);
-      k = (int)(u % n2);
-    } else {  // z faces
-      u -= 2 * fxz;
-      k = u < fyz ? 0 : n2 - 1;
-      u %= fyz;
-      i = (int)(u / n1);
-      j = (int)(u % n1);
+    if (task + gridDim.x * kFdmWaves < ntasks) {
+      locate(task + gridDim.x * kFdmWaves);
+      load();
     }
-    o[((long long)i * n1 + j) * n2 + k] = T(0);
   }
 }
 
@@ -755,11 +816,38 @@ inline int grid1(size_t n) {
 // ---------------------------------------------------------------------------
 // plan-level setup and application
 // ---------------------------------------------------------------------------
+
+// Fragment table of one contraction (see k_fdm_wave): entry (rb * KS + ks) * 64
+// + lane is the A operand of row block rb at step ks for that lane: M (M^T with
+// tr) at row 16 rb + lane % 16 and column fdm_kmap(ks, lane / 16), with the
+// half-matrix indexing of the even-odd kinds, zero outside.  M is m x m,
+// row-major.
+static void fdm_table(const double* M, int m, int mp, int kind, bool tr, bool f32, double* out) {
+  const int nbk = mp / 16, nks = kind ? mp / 8 : mp / 4;
+  const int ps = (m + 1) / 2, ph = m / 2;
+  for (int rb = 0; rb < nbk; ++rb)
+    for (int ks = 0; ks < nks; ++ks)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int row = 16 * rb + (lane & 15), k = fdm_kmap(ks, lane >> 4, f32);
+        const bool anti = kind != 0 && 16 * rb >= ps;
+        int r = row, col = k;
+        bool ok = row < m && k < m;
+        if (kind == 1) {
+          ok = row < m && k < (anti ? ph : ps);
+        } else if (kind == 2) {
+          r = anti ? row - ps : row;
+          col = anti ? ps + k : k;
+          ok = r < (anti ? ph : ps) && k < (anti ? ph : ps);
+        }
+        out[((size_t)rb * nks + ks) * 64 + lane] = ok ? (tr ? M[(size_t)col * m + r] : M[(size_t)r * m + col]) : 0.0;
+      }
+}
+
 int precond_setup(cheb_plan* p) {
   if (p->pc_ready) return CHEB_OK;
   size_t off64 = 0;
   std::vector<double> host;
-  PrecondAxis ax[3];
+  PrecondAxis ax[3] = {};
   // axes with the same 1-D problem (N, L, face pair) share one decomposition;
   // the distinct ones are decomposed on host threads of their own
   int src[3];
@@ -817,8 +905,40 @@ int precond_setup(cheb_plan* p) {
     host.insert(host.end(), lam.begin(), lam.end());
     off64 += (size_t)m;
   }
+  // fragment tables of the matrix-core contractions: each side (V^{-1}, V)
+  // plain and transposed, in the k order of each precision's accumulator
+  // layout (so the FP32 tables are written separately)
+  struct TabJob {
+    int a, dir, tr, kind;
+    size_t off;
+  };
+  std::vector<TabJob> jobs;
+  for (int a = 0; a < 3; ++a) {
+    const int m = ax[a].m;
+    if (m > 128) continue;
+    const int mp = 16 * ((m + 15) / 16);
+    for (int dir = 0; dir < 2; ++dir)
+      for (int tr = 0; tr < 2; ++tr) {
+        off64 = (off64 + 3) / 4 * 4;  // 16-byte aligned in both precisions
+        const int kind = ax[a].split ? dir + 1 : 0;
+        ax[a].off_tab[dir][tr] = off64;
+        jobs.push_back({a, dir, tr, kind, off64});
+        off64 += fdm_tab_elems(mp, kind);
+      }
+  }
+  host.resize(off64, 0.0);
   std::vector<float> host32(host.size());
   for (size_t i = 0; i < host.size(); ++i) host32[i] = float(host[i]);
+  for (const TabJob& j : jobs) {
+    const int m = ax[j.a].m, mp = 16 * ((m + 15) / 16);
+    // the V^{-1} side applies V^{-1} (V^T when transposed), the V side V (V^{-1} T)
+    const double* M = host.data() + ((j.dir == 0) != (j.tr != 0) ? ax[j.a].off_Vi : ax[j.a].off_V);
+    std::vector<double> t(fdm_tab_elems(mp, j.kind));
+    fdm_table(M, m, mp, j.kind, j.tr != 0, false, t.data());
+    std::copy(t.begin(), t.end(), host.begin() + j.off);
+    fdm_table(M, m, mp, j.kind, j.tr != 0, true, t.data());
+    for (size_t i = 0; i < t.size(); ++i) host32[j.off + i] = float(t[i]);
+  }
   int rc = hip_check(hipMalloc((void**)&p->pc64, host.size() * sizeof(double)), "hipMalloc(preconditioner)");
   if (!rc) rc = hip_check(hipMalloc((void**)&p->pc32, host.size() * sizeof(float)), "hipMalloc(preconditioner)");
   if (!rc)
@@ -840,27 +960,32 @@ const double* pc_base<double>(const cheb_plan* p) { return p->pc64; }
 template <>
 const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
 
-// persistent launch: as many workgroups as the device holds at once (queried
-// once per instantiation), at most one per tile
+// persistent launch: at most as many workgroups as the device holds at once
+// (queried once per instantiation), no more than the tasks need
 template <typename T, int MP, int MODE, int SPLIT>
 static int launch_fdm(const FdmArgs& f, hipStream_t s) {
+  constexpr int lds = fdm_lds_bytes<T>(MP, MODE, SPLIT);
+  static_assert(lds <= 160 * 1024, "contraction tables exceed LDS");
   static int resident = 0;
   if (resident == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (!rc && lds > 64 * 1024)
+      rc = hip_check(hipFuncSetAttribute((const void*)k_fdm_wave<T, MP, MODE, SPLIT>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds),
+                     "contraction LDS attribute");
     if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     if (!rc)
-      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                                  (const void*)k_fdm_contract<T, MP, MODE, SPLIT>,
-                                                                  4 * MP, 0),
+      rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fdm_wave<T, MP, MODE, SPLIT>,
+                                                                  64 * kFdmWaves, lds),
                      "occupancy query");
     if (rc) return rc;
     resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
   }
   const long long npen = (long long)f.m0 * f.m1 * f.m2 / f.m * f.nb;
-  const long long tiles = (npen + 15) / 16;
-  const int grid = (int)(tiles < resident ? (tiles > 0 ? tiles : 1) : resident);
-  hipLaunchKernelGGL((k_fdm_contract<T, MP, MODE, SPLIT>), dim3(grid), dim3(4 * MP), 0, s, f);
+  const long long wgs = ((npen + 15) / 16 + kFdmWaves - 1) / kFdmWaves;
+  const int grid = (int)(wgs < resident ? (wgs > 0 ? wgs : 1) : resident);
+  hipLaunchKernelGGL((k_fdm_wave<T, MP, MODE, SPLIT>), dim3(grid), dim3(64 * kFdmWaves), lds, s, f);
   return hip_check(hipGetLastError(), "axis contraction");
 }
 
@@ -889,10 +1014,16 @@ static int launch_fdm_mode(const FdmArgs& f, hipStream_t s) {
   }
 }
 
-// split: 0 plain, 1 input through Q^T (the V^{-1} half), 2 output through Q
-// (the V half); see k_fdm_contract
+// split: 0 plain, 1 input through Q^T (the V^{-1} side), 2 output through Q
+// (the V side), 3 the middle pair on a split axis; see k_fdm_wave
 template <typename T>
 static int launch_fdm_m(const FdmArgs& f, int mode, int split, hipStream_t s) {
+  if (mode == (FDM_MID | FDM_SCALE)) {
+    if (split == 3) return launch_fdm_mode<T, FDM_MID | FDM_SCALE, 3>(f, s);
+    if constexpr (sizeof(T) == sizeof(float)) return launch_fdm_mode<T, FDM_MID | FDM_SCALE, 0>(f, s);
+    set_error("middle pair: FP64 needs a split axis");
+    return CHEB_ERR_INVALID_ARG;
+  }
   if (split == 1) {
     switch (mode) {
       case FDM_XFULL: return launch_fdm_mode<T, FDM_XFULL, 1>(f, s);
@@ -912,29 +1043,38 @@ static int launch_fdm_m(const FdmArgs& f, int mode, int split, hipStream_t s) {
   }
 }
 
-// Y = M applied along `axis` of the packed block X (m0, m1, m2); trans uses M^T.
-// nb consecutive blocks of the same shape are contracted by one launch.
+// fragment table of axis a for side dir (0: the V^{-1} side, 1: the V side)
+// and the transposed preconditioner (tr)
 template <typename T>
-static int axis_contract(const T* M, bool trans, int axis, const int* m, const T* X, T* Y, hipStream_t s,
-                         int nb = 1) {
-  if (m[axis] <= 128) {
+static const T* fdm_tab(const cheb_plan* p, int a, int dir, bool tr) {
+  return pc_base<T>(p) + p->pc_ax[a].off_tab[dir][tr ? 1 : 0];
+}
+
+// Y = (side dir of axis a) applied along `axis` of the packed block X (m0, m1,
+// m2): V^{-1} (dir 0) or V (dir 1), transposed with tr.  nb consecutive blocks
+// of the same shape are contracted by one launch.
+template <typename T>
+static int axis_contract(const cheb_plan* p, int a, int dir, bool tr, const int* m, const T* X, T* Y,
+                         hipStream_t s, int nb = 1) {
+  if (m[a] <= 128) {
     FdmArgs f{};
-    f.M = M;
+    f.tab = fdm_tab<T>(p, a, dir, tr);
     f.X = X;
     f.Y = Y;
-    f.m = m[axis];
-    f.axis = axis;
-    f.trans = trans ? 1 : 0;
+    f.m = m[a];
+    f.axis = a;
     f.nb = nb;
     f.m0 = m[0];
     f.m1 = m[1];
     f.m2 = m[2];
-    return launch_fdm_m<T>(f, 0, 0, s);
+    return launch_fdm_m<T>(f, 0, p->pc_ax[a].split ? dir + 1 : 0, s);
   }
+  const T* base = pc_base<T>(p);
+  const T* M = base + ((dir == 0) != tr ? p->pc_ax[a].off_Vi : p->pc_ax[a].off_V);
   GemmArgs g;
-  const long long msz = m[axis];
-  const long long ms_i = trans ? 1 : msz, ms_k = trans ? msz : 1;  // M(i,k) strides
-  if (axis == 2) {
+  const long long msz = m[a];
+  const long long ms_i = tr ? 1 : msz, ms_k = tr ? msz : 1;  // M(i,k) strides
+  if (a == 2) {
     // Y[r, i] = sum_k X[r, k] M[i, k]: rows r, columns i
     g.A = X; g.B = M; g.D = Y;
     g.I = m[0] * m[1] * nb; g.Kd = m[2]; g.C = m[2];
@@ -946,46 +1086,43 @@ static int axis_contract(const T* M, bool trans, int axis, const int* m, const T
     hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
   } else {
     // Y_b = M X_b with X_b (m_axis x C), C = product of the later dims
-    const int C = axis == 0 ? m[1] * m[2] : m[2];
-    const int batch = (axis == 0 ? 1 : m[0]) * nb;
+    const int C = a == 0 ? m[1] * m[2] : m[2];
+    const int batch = (a == 0 ? 1 : m[0]) * nb;
     g.A = M; g.B = X; g.D = Y;
-    g.I = m[axis]; g.Kd = m[axis]; g.C = C;
+    g.I = m[a]; g.Kd = m[a]; g.C = C;
     g.a_si = ms_i; g.a_sk = ms_k;
     g.b_sk = C; g.b_sc = 1;
     g.d_si = C; g.d_sc = 1;
     g.a_sb = 0;
-    g.b_sb = g.d_sb = (long long)m[axis] * C;
+    g.b_sb = g.d_sb = (long long)m[a] * C;
     dim3 grid((g.I + 15) / 16, (C + 255) / 256, batch);
     hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
   }
   return hip_check(hipGetLastError(), "axis contraction");
 }
 
-// the fused path: every axis on the pencil-tile kernel, 32-bit element offsets
-// in the packed blocks and the fields, the block tables in LDS
-static bool fused_ok(const int* m, int nb, size_t span) {
+// the fused path: every axis on the per-wave kernel, element offsets in the
+// packed blocks below 2^31
+static bool fused_ok(const int* m, int nb) {
   const size_t lim = (size_t)1 << 31;
-  return m[0] <= 128 && m[1] <= 128 && m[2] <= 128 && nb <= kFdmMaxNb && span < lim &&
-         (size_t)m[0] * m[1] * m[2] * (size_t)nb < lim;
+  return m[0] <= 128 && m[1] <= 128 && m[2] <= 128 && (size_t)m[0] * m[1] * m[2] * (size_t)nb < lim;
 }
 
 // The six contractions on the matrix cores with the packing, the eigenvalue
-// scaling and the unpacking folded into the first, third and last (every axis
-// with m <= 128); nb fields at offs (null: one field), the boundary nodes of
-// the output set to zero by a small kernel.
+// scaling and the unpacking folded into the first, the middle and the last
+// (every axis with m <= 128); nb fields at offs (null: one field).  The last
+// contraction also zeroes the boundary nodes of the output.
 template <typename T>
 static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, bool transpose, int nb,
                          const long long* offs, double inv_k, const int* sys, const double* kc, hipStream_t s) {
   const int n0 = p->g.n[0], n1 = p->g.n[1], n2 = p->g.n[2];
   const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
   const T* base = pc_base<T>(p);
-  auto V = [&](int a) { return base + p->pc_ax[a].off_V; };
-  auto Vi = [&](int a) { return base + p->pc_ax[a].off_Vi; };
-  auto run = [&](int a, bool fwd, const T* X, T* Y, int mode) {
+  auto run = [&](int a, int dir, const T* X, T* Y, int mode) {
     FdmArgs f{};
     f.gate = offs ? nullptr : p->gate;
-    f.M = fwd ? (transpose ? V(a) : Vi(a)) : (transpose ? Vi(a) : V(a));
-    f.trans = transpose ? 1 : 0;
+    f.tab = fdm_tab<T>(p, a, dir, transpose);
+    f.tab2 = fdm_tab<T>(p, a, 1, transpose);  // the middle pair's second contraction
     f.X = X;
     f.Y = Y;
     f.m = m[a];
@@ -995,7 +1132,7 @@ static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bu
     f.m1 = m[1];
     f.m2 = m[2];
     f.offs = offs;
-    if (mode == FDM_SCALE) {
+    if (mode & FDM_SCALE) {
       f.lam0 = base + p->pc_ax[0].off_lam;
       f.lam1 = base + p->pc_ax[1].off_lam;
       f.lam2 = base + p->pc_ax[2].off_lam;
@@ -1003,20 +1140,24 @@ static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bu
       f.sys = sys;
       f.kc = kc;
     }
-    return launch_fdm_m<T>(f, mode, p->pc_ax[a].split ? (fwd ? 1 : 2) : 0, s);
+    const int split = p->pc_ax[a].split ? (mode & FDM_MID ? 3 : dir + 1) : 0;
+    return launch_fdm_m<T>(f, mode, split, s);
   };
-  int rc = run(0, true, in, bufA, FDM_XFULL);
-  if (!rc) rc = run(1, true, bufA, bufB, 0);
-  if (!rc) rc = run(2, true, bufB, bufA, FDM_SCALE);
-  if (!rc) rc = run(2, false, bufA, bufB, 0);
-  if (!rc) rc = run(1, false, bufB, bufA, 0);
-  if (!rc) rc = run(0, false, bufA, out, FDM_YFULL);
-  if (rc) return rc;
-  const long long faces = 2LL * ((long long)n1 * n2 + (long long)n0 * n2 + (long long)n0 * n1);
-  const int fb = (int)std::min<long long>((faces + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_zero_faces<T>, dim3(fb, nb), dim3(256), 0, s, out, offs, n0, n1, n2,
-                     offs ? nullptr : p->gate);
-  return hip_check(hipGetLastError(), "boundary zero");
+  // the two z contractions and the scaling between them as one kernel where
+  // both tables fit in LDS (FP64: split axes only)
+  const bool mid = p->pc_ax[2].split || sizeof(T) == sizeof(float);
+  int rc = run(0, 0, in, bufA, FDM_XFULL);
+  if (!rc) rc = run(1, 0, bufA, bufB, 0);
+  if (mid) {
+    if (!rc) rc = run(2, 0, bufB, bufA, FDM_MID | FDM_SCALE);
+  } else {
+    if (!rc) rc = run(2, 0, bufB, bufA, FDM_SCALE);
+    if (!rc) rc = run(2, 1, bufA, bufB, 0);
+    std::swap(bufA, bufB);
+  }
+  if (!rc) rc = run(1, 1, bufA, bufB, 0);
+  if (!rc) rc = run(0, 1, bufB, out, FDM_YFULL);  // also zeroes the boundary nodes of out
+  return rc;
 }
 
 template <typename T>
@@ -1024,12 +1165,10 @@ int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, dou
                   hipStream_t s) {
   const int n0 = p->g.n[0], n1 = p->g.n[1], n2 = p->g.n[2];
   const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
-  if (fused_ok(m, 1, (size_t)n0 * n1 * n2))
+  if (fused_ok(m, 1))
     return precond_fused<T>(p, in, out, bufA, bufB, transpose, 1, nullptr, 1.0 / kc, nullptr, nullptr, s);
   const size_t tot = (size_t)m[0] * m[1] * m[2];
   const T* base = pc_base<T>(p);
-  auto V = [&](int a) { return base + p->pc_ax[a].off_V; };
-  auto Vi = [&](int a) { return base + p->pc_ax[a].off_Vi; };
   hipLaunchKernelGGL(k_pack_interior<T>, dim3(grid1(tot)), dim3(256), 0, s, in, bufA, n0, n1, n2);
   int rc = hip_check(hipGetLastError(), "pack");
   if (rc) return rc;
@@ -1037,7 +1176,7 @@ int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, dou
   T* x = bufA;
   T* y = bufB;
   for (int a = 0; a < 3 && !rc; ++a) {
-    rc = transpose ? axis_contract<T>(V(a), true, a, m, x, y, s) : axis_contract<T>(Vi(a), false, a, m, x, y, s);
+    rc = axis_contract<T>(p, a, 0, transpose, m, x, y, s);
     std::swap(x, y);
   }
   if (rc) return rc;
@@ -1045,7 +1184,7 @@ int precond_apply(const cheb_plan* p, const T* in, T* out, T* bufA, T* bufB, dou
                      base + p->pc_ax[1].off_lam, base + p->pc_ax[2].off_lam, 1.0 / kc, m[0], m[1], m[2]);
   rc = hip_check(hipGetLastError(), "eigen scale");
   for (int a = 2; a >= 0 && !rc; --a) {
-    rc = transpose ? axis_contract<T>(Vi(a), true, a, m, x, y, s) : axis_contract<T>(V(a), false, a, m, x, y, s);
+    rc = axis_contract<T>(p, a, 1, transpose, m, x, y, s);
     std::swap(x, y);
   }
   if (rc) return rc;
@@ -1073,7 +1212,8 @@ int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long lo
   if (nmem <= 0) return CHEB_OK;
   const int n0 = rep->g.n[0], n1 = rep->g.n[1], n2 = rep->g.n[2];
   const int m[3] = {n0 - 2, n1 - 2, n2 - 2};
-  if (fused_ok(m, nmem, span))
+  (void)span;
+  if (fused_ok(m, nmem))
     return precond_fused<T>(rep, in, out, bufA, bufB, false, nmem, offs, 0.0, sys, kc, s);
   const size_t tot = (size_t)m[0] * m[1] * m[2];
   const T* base = pc_base<T>(rep);
@@ -1082,7 +1222,7 @@ int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long lo
   T* x = bufA;
   T* y = bufB;
   for (int a = 0; a < 3 && !rc; ++a) {
-    rc = axis_contract<T>(base + rep->pc_ax[a].off_Vi, false, a, m, x, y, s, nmem);
+    rc = axis_contract<T>(rep, a, 0, false, m, x, y, s, nmem);
     std::swap(x, y);
   }
   if (rc) return rc;
@@ -1090,7 +1230,7 @@ int precond_apply_batch(const cheb_plan* rep, const T* in, T* out, const long lo
                      base + rep->pc_ax[1].off_lam, base + rep->pc_ax[2].off_lam, sys, kc, m[0], m[1], m[2]);
   rc = hip_check(hipGetLastError(), "batched eigen scale");
   for (int a = 2; a >= 0 && !rc; --a) {
-    rc = axis_contract<T>(base + rep->pc_ax[a].off_V, false, a, m, x, y, s, nmem);
+    rc = axis_contract<T>(rep, a, 1, false, m, x, y, s, nmem);
     std::swap(x, y);
   }
   if (rc) return rc;
@@ -1123,4 +1263,45 @@ extern "C" int cheb_debug_gemm(int32_t precision, const void* A, const void* B, 
   if (precision == CHEB_F32)
     return mfma_gemm<float>((const float*)A, (const float*)B, (float*)D, I, K, C, (hipStream_t)stream);
   return mfma_gemm<double>((const double*)A, (const double*)B, (double*)D, I, K, C, (hipStream_t)stream);
+}
+
+extern "C" int cheb_precond_apply(cheb_plan* plan, int32_t field_precision, double kc, const void* in, void* out,
+                                  uint32_t flags) {
+  if (!plan || !in || !out) {
+    set_error("null argument");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (field_precision != CHEB_F64 && field_precision != CHEB_F32) {
+    set_error("preconditioner: field_precision must be CHEB_F64 or CHEB_F32");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if ((flags & ~(uint32_t)CHEB_APPLY_TRANSPOSE) != 0) {
+    set_error("preconditioner: flags must be 0 or CHEB_APPLY_TRANSPOSE");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  if (!(kc > 0.0) || !std::isfinite(kc)) {
+    set_error("preconditioner: kc must be positive and finite");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  const size_t es = field_precision == CHEB_F64 ? sizeof(double) : sizeof(float);
+  const size_t pb = round_up((size_t)(plan->g.n[0] - 2) * (plan->g.n[1] - 2) * (plan->g.n[2] - 2) * es, 256);
+  if (!plan->ws || plan->ws_bytes < 2 * pb) {
+    set_error("preconditioner: the workspace must hold two interior blocks");
+    return CHEB_ERR_WORKSPACE;
+  }
+  int rc = precond_setup(plan);
+  if (rc) return rc;
+  // outside a solve nothing gates the contractions
+  const int* gate = plan->gate;
+  plan->gate = nullptr;
+  char* w = (char*)plan->ws;
+  const bool tr = (flags & CHEB_APPLY_TRANSPOSE) != 0;
+  if (field_precision == CHEB_F64)
+    rc = precond_apply<double>(plan, (const double*)in, (double*)out, (double*)w, (double*)(w + pb), kc, tr,
+                               plan->stream);
+  else
+    rc = precond_apply<float>(plan, (const float*)in, (float*)out, (float*)w, (float*)(w + pb), kc, tr,
+                              plan->stream);
+  plan->gate = gate;
+  return rc;
 }
