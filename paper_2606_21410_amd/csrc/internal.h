@@ -32,7 +32,7 @@ struct PrecondAxis {
   int split;  // centro-symmetric factors whose even and odd halves fill whole 16-row blocks
   size_t off_V, off_Vi, off_lam;
   // matrix-core fragment tables (m <= 128): [0: the V^{-1} side, 1: the V side][transposed]
-  size_t off_tab[2][2];
+  size_t off_tab[2][2];  // an axis with the same 1-D problem as an earlier one shares its tables
 };
 
 }  // namespace cheb

@@ -916,6 +916,12 @@ int precond_setup(cheb_plan* p) {
   for (int a = 0; a < 3; ++a) {
     const int m = ax[a].m;
     if (m > 128) continue;
+    if (src[a] != a) {
+      // the same 1-D problem as an earlier axis: the same tables
+      for (int dir = 0; dir < 2; ++dir)
+        for (int tr = 0; tr < 2; ++tr) ax[a].off_tab[dir][tr] = ax[src[a]].off_tab[dir][tr];
+      continue;
+    }
     const int mp = 16 * ((m + 15) / 16);
     for (int dir = 0; dir < 2; ++dir)
       for (int tr = 0; tr < 2; ++tr) {
@@ -1143,10 +1149,10 @@ static int precond_fused(const cheb_plan* p, const T* in, T* out, T* bufA, T* bu
     const int split = p->pc_ax[a].split ? (mode & FDM_MID ? 3 : dir + 1) : 0;
     return launch_fdm_m<T>(f, mode, split, s);
   };
+  int rc = run(0, 0, in, bufA, FDM_XFULL);
   // the two z contractions and the scaling between them as one kernel where
   // both tables fit in LDS (FP64: split axes only)
   const bool mid = p->pc_ax[2].split || sizeof(T) == sizeof(float);
-  int rc = run(0, 0, in, bufA, FDM_XFULL);
   if (!rc) rc = run(1, 0, bufA, bufB, 0);
   if (mid) {
     if (!rc) rc = run(2, 0, bufB, bufA, FDM_MID | FDM_SCALE);

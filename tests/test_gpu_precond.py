@@ -165,9 +165,25 @@ def test_precond_exact_even_split_widths(shape, robin):
     ((129, 129, 129), (0,) * 6, None),                    # the 129^3 workload's grid: split width 128
     ((17, 20, 257), (0,) * 6, None),                      # z interior 255: the generic contraction path
     ((66, 130, 34), (0, 0, 1, 1, 0, 0), (0.0, 0.0, 0.7, 0.7, 0.0, 0.0)),  # Robin pair, even widths
+    # y and z axes with one 1-D problem (cubic y-z box), which share their
+    # fragment tables
+    ((98, 34, 34), (0, 1, 0, 0, 0, 0), "cube"),           # split, width 32
+    ((100, 49, 49), (0, 0, 1, 1, 1, 1), "cube"),          # 47: plain, width 48
+    ((97, 97, 97), (1, 1, 0, 1, 0, 1), "cube"),           # faces differ: plain, width 96
+    ((99, 66, 66), (0, 0, 1, 1, 1, 1), "cube-robin"),     # split, width 64, Robin pairs
+    ((129, 129, 129), (0, 0, 1, 1, 1, 1), "cube"),        # the 129^3 workload's faces: split 128
 ])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_precond_apply_vs_oracle(shape, bc, robin, prec):
+    if robin == "cube" or robin == "cube-robin":
+        box = ((0.0, 0.0, 0.0), (1.5, 1.0, 1.0))
+        robin = (0.0, 0.0, 0.4, 0.4, 0.4, 0.4) if robin == "cube-robin" else None
+    else:
+        box = ((0.0, -1.0, 0.5), (1.0, 1.0, 2.0))
+    _precond_case(shape, bc, robin, prec, box)
+
+
+def _precond_case(shape, bc, robin, prec, box):
     """cheb_precond_apply against the oracle's fast diagonalisation (itself
     pinned to a direct solve of the constant-coefficient reduced operator),
     element by element on the interior, zero on the boundary.  The 1-D
@@ -181,7 +197,7 @@ def test_precond_apply_vs_oracle(shape, bc, robin, prec):
     require_gpu()
     import torch
     from paper_2606_21410_amd.api import Plan
-    LO, HI = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+    LO, HI = box
     kc = 1.7
     G = O.Grid3(shape, LO, HI, bc, robin)
     F = O.FDM(G, kc)
