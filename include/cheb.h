@@ -325,6 +325,16 @@ int cheb_derivative(cheb_plan* plan, const void* u, void* du, int32_t axis);
  * Uses 4 fields of workspace.  Synchronises. */
 int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[3]);
 
+/* Apparent conductivity of one load case (Section 3.3): with u the solution
+ * of a load case along `axis` whose faces impose a jump `jump` of u across the
+ * box (mean gradient G = jump / (hi[axis] - lo[axis])), out[b] = <K du/dx_b>_CC
+ * / G for b = 0, 1, 2 (host out[3]): column `axis` of the apparent
+ * conductivity tensor.  Same workspace and synchronisation as
+ * cheb_flux_average; CHEB_ERR_INVALID_ARG for an axis outside 0..2 or a zero
+ * or non-finite jump. */
+int cheb_apparent_conductivity(cheb_plan* plan, const void* K, const void* u, int32_t axis, double jump,
+                               double out[3]);
+
 /* Fast-diagonalisation preconditioner, the one the preconditioned solves use
  * (an addition to the paper's plain LGMRES).  With constant K = kc the reduced
  * operator of Section 2.3.1 is kc (A_x (+) A_y (+) A_z), a Kronecker sum of the
@@ -348,20 +358,6 @@ int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[
  * failed). */
 int cheb_precond_apply(cheb_plan* plan, int32_t field_precision, double kc, const void* in, void* out,
                        uint32_t flags);
-
-/* Copy of n doubles, src -> dst (device arrays, 16-byte aligned, not
- * overlapping), by the library's stream-copy kernel: 16-byte loads and stores
- * in a grid-stride loop.  The attainable HBM bandwidth the operator's roofline
- * fraction is also quoted against (2 n * 8 bytes moved).  Asynchronous on
- * `stream`. */
-int cheb_debug_copy(const void* src, void* dst, size_t n, void* stream);
-
-/* Dense GEMM on the matrix cores, D (I x C) = A (I x K) B (K x C), row-major
- * device arrays (double for CHEB_F64, float for CHEB_F32).  This is the
- * contraction kernel of the preconditioner, exposed so its MFMA lane layout can
- * be checked directly.  Asynchronous on `stream`. */
-int cheb_debug_gemm(int32_t precision, const void* A, const void* B, void* D, int32_t I, int32_t K, int32_t C,
-                    void* stream);
 
 const char* cheb_status_string(int status);
 const char* cheb_last_error(void);

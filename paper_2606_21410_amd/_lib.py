@@ -89,6 +89,8 @@ _SIGS = {
     "cheb_derivative": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
     "cheb_flux_average": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "cheb_precond_apply": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp, ctypes.c_uint32]),
+    "cheb_apparent_conductivity": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                                  ctypes.POINTER(ctypes.c_double)]),
     "cheb_debug_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "cheb_debug_gemm": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, _vp]),
@@ -141,7 +143,7 @@ def check(rc: int) -> int:
 
 
 def declared_functions(header_path: str | None = None) -> list[str]:
-    """Names of the functions include/cheb.h declares."""
+    """Names of the functions a header under include/ declares (default cheb.h)."""
     import re
     if header_path is None:
         header_path = os.path.join(os.path.dirname(_HERE), "include", "cheb.h")

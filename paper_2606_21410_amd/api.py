@@ -335,6 +335,16 @@ class Plan:
                                             L.CHEB_APPLY_TRANSPOSE if transpose else 0))
         return out
 
+    def apparent_conductivity(self, K, u, axis: int, jump: float = 1.0):
+        """Column `axis` of the apparent conductivity tensor from one load case
+        (cheb_apparent_conductivity): <K du/dx_b>_CC / G, G = jump / L_axis."""
+        self._sync_stream()
+        self.ensure_workspace()
+        out = (ctypes.c_double * 3)()
+        L.check(self.lib.cheb_apparent_conductivity(self._h, self._field(K, "K"), self._field(u, "u"),
+                                                    int(axis), float(jump), out))
+        return [out[0], out[1], out[2]]
+
     def flux_average(self, K, u):
         self._sync_stream()
         self.ensure_workspace()
@@ -504,7 +514,7 @@ def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", op
     three load cases per microstructure (unit mean gradient along x, y, z
     through Dirichlet faces, zero flux elsewhere) solved together in one batch,
     then K_app[b][a] = <K du^(a)/dx_b>_CC / G_a with Clenshaw-Curtis volume
-    averages.  Returns (list of 3x3 nested lists, per-system infos, solutions);
+    averages (cheb_apparent_conductivity).  Returns (list of 3x3 nested lists, per-system infos, solutions);
     a dict passed as `details` receives the batch's tuned tile shapes."""
     grids, KK, ff, gg = [], [], [], []
     for K in Ks:
@@ -527,10 +537,9 @@ def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", op
         plan = Plan(n, lo, hi, grids[3 * s][3], "f64", device)
         Kapp = [[0.0] * 3 for _ in range(3)]
         for a in range(3):
-            G = 1.0 / (hi[a] - lo[a])
-            fa = plan.flux_average(K, us[3 * s + a])
+            col = plan.apparent_conductivity(K, us[3 * s + a], a, 1.0)
             for b in range(3):
-                Kapp[b][a] = fa[b] / G
+                Kapp[b][a] = col[b]
         out.append(Kapp)
     return out, infos, us
 

@@ -421,4 +421,19 @@ int cheb_flux_average(cheb_plan* plan, const void* K, const void* u, double out[
   return CHEB_OK;
 }
 
+int cheb_apparent_conductivity(cheb_plan* plan, const void* K, const void* u, int32_t axis, double jump,
+                               double out[3]) {
+  if (!plan || !out || axis < 0 || axis > 2 || !(jump != 0.0) || !std::isfinite(jump)) {
+    set_error("apparent conductivity: null argument, axis outside 0..2 or zero / non-finite jump");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  double fl[3];
+  const int rc = cheb_flux_average(plan, K, u, fl);
+  if (rc) return rc;
+  // Section 3.3: K_app[b][axis] = <K du/dx_b> / G with the imposed mean gradient G
+  const double G = jump / (plan->g.hi[axis] - plan->g.lo[axis]);
+  for (int b = 0; b < 3; ++b) out[b] = fl[b] / G;
+  return CHEB_OK;
+}
+
 }  // extern "C"

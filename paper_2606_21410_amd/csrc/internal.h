@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/cheb.h"
+#include "../../include/cheb_debug.h"
 
 namespace cheb {
 

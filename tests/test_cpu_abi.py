@@ -21,7 +21,9 @@ def test_exports_every_declared_symbol():
     lib = _lib()
     names = L.declared_functions(os.path.join(ROOT, "include", "cheb.h"))
     assert len(names) >= 14
-    for nm in names:
+    debug = L.declared_functions(os.path.join(ROOT, "include", "cheb_debug.h"))
+    assert debug == ["cheb_debug_copy", "cheb_debug_gemm"]
+    for nm in names + debug:
         assert hasattr(lib, nm), nm
 
 
@@ -89,3 +91,10 @@ def test_load_case_packing_matches_generator():
         bc, g = load_case(n, a, device="cpu")
         assert bc == W.load_case_bc(a)
         np.testing.assert_array_equal(g.numpy(), W.load_case_faces(grid, a))
+
+
+def test_apparent_conductivity_rejects_null_plan():
+    import ctypes
+    lib = _lib()
+    out = (ctypes.c_double * 3)()
+    assert lib.cheb_apparent_conductivity(None, None, None, 0, 1.0, out) == L.CHEB_ERR_INVALID_ARG
