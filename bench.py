@@ -519,6 +519,43 @@ def refinement_stop_section(dev, levels=(33, 65, 129, 257), tol=2e-3):
     return out
 
 
+def precond_section(dev, P, reps=50, warmup=5):
+    """One application of the fast-diagonalisation preconditioner
+    (cheb_precond_apply) on the 129^3 workload's grid with Kc = mean K, FP64 and
+    FP32 fields, event-timed on the plan's stream.  Bytes: each of the five
+    launches (x, y, the fused z pair, y, x) reads and writes one field of the
+    interior nodes, 10 x m^3 x sizeof(T)."""
+    import numpy as np
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    from paper_2606_21410_amd import workloads as W
+    out = {}
+    m = [v - 2 for v in P.grid.n]
+    kc = float(np.mean(P.K))
+    r = W.random_field(P.grid.n, 5)
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        pl = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, prec, dev)
+        rd = torch.from_numpy(r).to(dev, dt)
+        yd = torch.empty_like(rd)
+        for _ in range(warmup):
+            pl.precond(rd, kc, out=yd)
+        stream = torch.cuda.current_stream(dev)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            pl.precond(rd, kc, out=yd)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        nbytes = 10 * m[0] * m[1] * m[2] * (8 if prec == "f64" else 4)
+        out[prec] = {"us_per_application": round(us, 2), "launches": 5,
+                     "mb_moved": round(nbytes / 1e6, 1), "gbs": round(nbytes / us / 1e3, 1)}
+        del pl, rd, yd
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_reference(dev, n=64 * 1024 * 1024, reps=20):
     """Attainable HBM bandwidth: the library's stream-copy kernel (cheb_debug_copy)
     moving n doubles (512 MiB read + 512 MiB written, far beyond the 256 MB
@@ -646,6 +683,9 @@ def main():
     ap.add_argument("--profile-newton", action="store_true",
                     help="for profiler runs: the Section 3.4 Newton solve from a cold start at N = 128, then "
                          "the refinement chain N = 8 .. 128")
+    ap.add_argument("--profile-precond", action="store_true",
+                    help="for profiler runs: the preconditioner applications of the bench's precond section "
+                         "only")
     ap.add_argument("--profile-solve", action="store_true",
                     help="for profiler runs: the preconditioned FP64 and mixed solves only, each twice on "
                          "one plan (the first with plan and preconditioner set-up)")
@@ -690,6 +730,10 @@ def main():
         _log(f"cold Newton N=128: {cold}")
         chain = thermal_newton_section(dev, levels=(8, 16, 32, 64, 128))
         print(json.dumps({"profile_newton": {"cold_128": cold, "chain": chain}}), flush=True)
+        return
+
+    if args.profile_precond:
+        print(json.dumps({"profile_precond": precond_section(dev, P)}), flush=True)
         return
 
     if args.profile_solve:
@@ -822,6 +866,9 @@ def main():
     roofline["frac_of_copy"] = round(achieved / copy["gbs"], 4)
     a257 = apply_257(dev)
     _log(f"copy {copy}; apply 257^3 {a257}")
+    _log("preconditioner applications")
+    precond = precond_section(dev, P)
+    _log(f"preconditioner {precond}")
     # CPU-baseline leg: the oracle on the host -- its apply rate, and its
     # solution of the 129^3 system, which the time-to-1e-8 errors are measured
     # against
@@ -896,6 +943,7 @@ def main():
         "apply_detail": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
                              if kk != "wall_s"} for k, v in res.items()},
         "roofline": roofline,
+        "precond_apply": precond,
         "cpu_baseline": cpu,
         "cpu_baseline_detail": cpu_more,
         "time_to_1e-8_129": solve,

@@ -71,7 +71,10 @@ def test_paper_poisson_17_f64():
 # contracting once the residual reaches ~1e-6 (kappa(A) * u_f32 >= 1 for the
 # spectral operator), so plain mixed ends STAGNATED near FP32 accuracy; the
 # preconditioned mixed solve (test_gpu_precond) is the one that reaches FP64.
-@pytest.mark.parametrize("prec,rtol,bar", [("f64", 1e-13, 1e-8), ("mixed", 1e-10, 2e-2), ("f32", 1e-6, 5e-2)])
+# Measured on MI355X: plain mixed stagnates at relres 4.2e-7 with error 2.6e-3,
+# FP32 reaches relres 1e-6 with error 5.9e-3; the bars are kappa x 2 x those
+# residual floors (1e-2, 2e-2).
+@pytest.mark.parametrize("prec,rtol,bar", [("f64", 1e-13, 1e-8), ("mixed", 1e-10, 1e-2), ("f32", 1e-6, 2e-2)])
 def test_two_phase_33(prec, rtol, bar):
     """Spherical inclusions (vf 0.2, contrast 10), u = -1/+1 on the x faces,
     zero flux elsewhere: relative error to the oracle's solution.  The plain
