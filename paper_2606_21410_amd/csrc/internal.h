@@ -151,10 +151,11 @@ int arnoldi_begin(ArnoldiState* st, const double* dots, hipStream_t s);
 // re-orthogonalisation, only while pass 0 has paused the cycle for it: it
 // first sets w <- w - V h0 with h0 the pass-0 coefficients); dots[0..j+1]
 // receive the pass's coefficients and ||w||^2; partials:
-// multidot_partials_len(npts, j + 1)
+// multidot_partials_len(npts, j + 1); host_head (pinned host memory, or null)
+// receives the state's head once the column is done
 template <typename T>
 int gram_schmidt(const T* V, size_t ld, int j, T* w, size_t npts, const double* h0, double* partials,
-                 double* dots, ArnoldiState* st, int pass, hipStream_t s);
+                 double* dots, ArnoldiState* st, int pass, hipStream_t s, ArnoldiHead* host_head = nullptr);
 // st->y = R^{-1} g over the cycle's columns
 int arnoldi_solve(ArnoldiState* st, hipStream_t s);
 template <typename T>

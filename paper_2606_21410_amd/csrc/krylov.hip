@@ -234,13 +234,28 @@ __global__ __launch_bounds__(kGsThreads) void k_gram_schmidt(const T* __restrict
 
 // column sums of the nb blocks' partial results (wave q takes columns q,
 // q + 4, ...; lanes stride the blocks), then the Hessenberg column
+// The step's status record (the state's head) then goes to host_head (pinned
+// host memory, or null), written by lane 0 of wave 0 after the column, so the
+// host reads it once the step's event has completed, with no copy launch.
+__device__ __forceinline__ void head_to_host(const ArnoldiState* st, ArnoldiHead* host_head) {
+  static_assert(sizeof(ArnoldiHead) % sizeof(double) == 0, "head copied as doubles");
+  const double* src = reinterpret_cast<const double*>(static_cast<const ArnoldiHead*>(st));
+  double* dst = reinterpret_cast<double*>(host_head);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ArnoldiHead) / sizeof(double)); ++i) dst[i] = src[i];
+}
+
 template <int PASS>
 __global__ __launch_bounds__(kGsThreads) void k_gs_column(const double* __restrict__ partials, int nb, int nv,
-                                                          double* dots, ArnoldiState* st, int j) {
+                                                          double* dots, ArnoldiState* st, int j,
+                                                          ArnoldiHead* host_head) {
   __shared__ double hs[kMaxKrylovCols + 2];
   __shared__ double col[3 * (kMaxKrylovCols + 2)];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (PASS == 0 ? !st->active : !st->reorth) return;
+  if (PASS == 0 ? !st->active : !st->reorth) {
+    if (host_head && tid == 0) head_to_host(st, host_head);
+    return;
+  }
   for (int c = wave; c <= nv; c += kGsThreads / 64) {
     const double* pc = partials + (size_t)c * nb;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -256,7 +271,11 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_column(const double* __restri
   }
   __syncthreads();
   for (int v = tid; v <= nv; v += kGsThreads) dots[v] = hs[v];
-  if (wave == 0) arnoldi_column_wave(st, hs, j, PASS, lane, col);
+  if (wave == 0) {
+    arnoldi_column_wave(st, hs, j, PASS, lane, col);
+    // lane 0 wrote the head's scalars; the other lanes' H writes are not in it
+    if (host_head && lane == 0) head_to_host(st, host_head);
+  }
 }
 
 // y = R^{-1} g over the columns the cycle built (back-substitution)
@@ -304,7 +323,7 @@ int arnoldi_begin(ArnoldiState* st, const double* dots, hipStream_t s) {
 
 template <typename T>
 int gram_schmidt(const T* V, size_t ld, int j, T* w, size_t npts, const double* h0, double* partials,
-                 double* dots, ArnoldiState* st, int pass, hipStream_t s) {
+                 double* dots, ArnoldiState* st, int pass, hipStream_t s, ArnoldiHead* host_head) {
   if (j < 0 || j >= kMaxKrylovCols || npts == 0) {
     set_error("Arnoldi column out of range");
     return CHEB_ERR_INVALID_ARG;
@@ -313,11 +332,13 @@ int gram_schmidt(const T* V, size_t ld, int j, T* w, size_t npts, const double* 
   if (pass == 0) {
     hipLaunchKernelGGL((k_gram_schmidt<T, 0>), dim3(nb), dim3(kGsThreads), 0, s, V, ld, j + 1, w, npts, h0,
                        partials, st);
-    hipLaunchKernelGGL(k_gs_column<0>, dim3(1), dim3(kGsThreads), 0, s, partials, nb, j + 1, dots, st, j);
+    hipLaunchKernelGGL(k_gs_column<0>, dim3(1), dim3(kGsThreads), 0, s, partials, nb, j + 1, dots, st, j,
+                       host_head);
   } else {
     hipLaunchKernelGGL((k_gram_schmidt<T, 1>), dim3(nb), dim3(kGsThreads), 0, s, V, ld, j + 1, w, npts, h0,
                        partials, st);
-    hipLaunchKernelGGL(k_gs_column<1>, dim3(1), dim3(kGsThreads), 0, s, partials, nb, j + 1, dots, st, j);
+    hipLaunchKernelGGL(k_gs_column<1>, dim3(1), dim3(kGsThreads), 0, s, partials, nb, j + 1, dots, st, j,
+                       host_head);
   }
   return hip_check(hipGetLastError(), "gram_schmidt");
 }
@@ -334,9 +355,9 @@ int scale_by(T* v, const double* dscale, size_t npts, hipStream_t s) {
 }
 
 template int gram_schmidt<double>(const double*, size_t, int, double*, size_t, const double*, double*, double*,
-                                  ArnoldiState*, int, hipStream_t);
+                                  ArnoldiState*, int, hipStream_t, ArnoldiHead*);
 template int gram_schmidt<float>(const float*, size_t, int, float*, size_t, const double*, double*, double*,
-                                 ArnoldiState*, int, hipStream_t);
+                                 ArnoldiState*, int, hipStream_t, ArnoldiHead*);
 template int scale_by<double>(double*, const double*, size_t, hipStream_t);
 template int scale_by<float>(float*, const double*, size_t, hipStream_t);
 

@@ -240,7 +240,8 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
       T* wj = (j & 1) ? kw.w2 : w;
       int r = A(dir, wj);
       p->gate = nullptr;
-      if (!r) r = gram_schmidt<T>(kw.V, ld, j, wj, npts, nullptr, sc.partials, sc.dots, ast, 0, s);
+      // the column kernel also writes the step's head to its pinned ring slot
+      if (!r) r = gram_schmidt<T>(kw.V, ld, j, wj, npts, nullptr, sc.partials, sc.dots, ast, 0, s, &ring[j & 1]);
       if (!r)
         r = update_scale<T>(kw.V, ld, j + 1, sc.dots, wj, kw.V + (size_t)(j + 1) * ld, 1.0, npts, s, &ast->inv_hn,
                             &ast->direct);
@@ -261,9 +262,6 @@ int lgmres(cheb_plan* p, ApplyFn&& A, const T* b, T* x, bool x_zero, double tol_
       int last = -1;
       for (int j = jnext; j < jmax; ++j) {
         rc = step(j);
-        if (!rc)
-          rc = hip_check(hipMemcpyAsync(&ring[j & 1], ast, sizeof(ArnoldiHead), hipMemcpyDeviceToHost, s),
-                         "hipMemcpyAsync(D2H)");
         if (!rc) rc = hip_check(hipEventRecord(p->kev[j & 1], s), "hipEventRecord");
         if (rc) return rc;
         last = j;
