@@ -511,6 +511,18 @@ __device__ __forceinline__ void copy_to_lds(const int4* __restrict__ src, int4* 
   }
 }
 
+// the eigenvalue scaling v / (Kc (lam_transverse + lam_i)), ik = 1 / Kc: FP64
+// divides exactly; FP32 multiplies by the hardware reciprocal (1 ulp), which the
+// FP32 preconditioner's accuracy does not notice
+template <typename T>
+__device__ __forceinline__ T fdm_scale(T v, double ik, double sc, T lam) {
+  if constexpr (sizeof(T) == sizeof(float)) {
+    return v * float(ik) * __builtin_amdgcn_rcpf(float(sc) + lam);
+  } else {
+    return T(double(v) * ik / (sc + double(lam)));
+  }
+}
+
 // acc[rb] (16 rows of row block rb, every rb) = table x B, k-step by k-step
 // (KIND 0: KF steps over B[ks]; kinds 1, 2: KH steps, the symmetric blocks
 // over B[ks], the antisymmetric ones over B[KH + ks])
@@ -654,7 +666,12 @@ __global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
       Y[fo + face_node(t - b * faces, n0, n1, n2)] = T(0);
     }
   }
-  __syncthreads();
+  // a barrier over the LDS stores only: a full __syncthreads() would also wait
+  // for the operand loads just issued, which are meant to land during the
+  // first matrix-core steps
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   for (; task < ntasks; task += gridDim.x * kFdmWaves) {
     // every row block at once, k-step by k-step: eight independent
     // accumulation chains, started as soon as the first rows arrive
@@ -670,7 +687,7 @@ __global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * rb + Mfma<T>::row(lk, r);
-          B[4 * rb + r] = i < m ? T(double(acc[rb][r]) * ik / (sc + double(lam_s[axis * 128 + i]))) : T(0);
+          B[4 * rb + r] = i < m ? fdm_scale<T>(acc[rb][r], ik, sc, lam_s[axis * 128 + i]) : T(0);
         }
       contract<T, SB, NB, KF, KH>(tabB, lane, B, acc);
     } else if constexpr (SCL) {
@@ -682,7 +699,7 @@ __global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * rb + Mfma<T>::row(lk, r);
-          if (i < m) acc[rb][r] = T(double(acc[rb][r]) * ik / (sc + double(lam_s[axis * 128 + i])));
+          if (i < m) acc[rb][r] = fdm_scale<T>(acc[rb][r], ik, sc, lam_s[axis * 128 + i]);
         }
     }
     constexpr int SOUT = MID ? SB : SA;  // the kind whose outputs are stored
