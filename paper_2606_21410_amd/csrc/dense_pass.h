@@ -466,7 +466,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   DENSE_SYS(tile < ntiles ? tile : 0, cu, cK, cy, cbm);
   nu = cu;
   nK = cK;
-  __syncthreads();
+  lds_barrier();
   // V = 0 loads the next tile's u and K into registers between the first
   // product's matrix instructions and writes them to LDS at the top of the next
   // tile.  V = 1, whose registers hold the fragments, loads each tile at its
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 
   for (; tile < t_end; tile += t_step, slot ^= 1) {
     const int nxt = tile + t_step < t_end ? tile + t_step : ntiles;
-    __syncthreads();  // previous tile's readers of U and of slot^1 are done
+    lds_barrier();  // previous tile's readers of U and of slot^1 are done
     DENSE_SYS(tile, cu, cK, cy, cbm);
     nlo = (cbm >> (2 * axis)) & 1;
     nhi = (cbm >> (2 * axis + 1)) & 1;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_PUT(U, ureg, kreg);
     if (nxt < ntiles) DENSE_COLS(slot ^ 1, nxt);
     else if (tid < C) cbase[slot ^ 1][tid] = -1;  // loads of the next tile all read node 0
-    __syncthreads();
+    lds_barrier();
 
     // in flight during this tile: next tile's u and K (V = 0), this tile's y.  Their
     // addresses are formed here and the loads are issued a few at a time
@@ -578,9 +578,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     for (int ks = S.KE4; ks < (PREF ? NL : 0); ++ks) DENSE_PREF1(ks);
     DENSE_VDOT(midv);
     if (MODE == DENSE_REDUCED) DENSE_LIFTVALS(acco, acce);
-    __syncthreads();
+    lds_barrier();
     DENSE_EPI(acco, acce, midv, true, MODE == DENSE_REDUCED);
-    __syncthreads();
+    lds_barrier();
 
     // divergence part
     DENSE_GEMM(acco, acce, DENSE_ISSUE2);
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
       if (!FIRST) yreg[q] = dense_at(cy, DENSE_AD(slot, q));
     DENSE_VDOT(midv);
     DENSE_EPI(acco, acce, midv, false, false);  // into the K tile: no barrier needed before it
-    __syncthreads();
+    lds_barrier();
 
     if (MODE == DENSE_TRANSPOSE) {
       // transposed lift: mu = M^{-T} [z_0, z_N]; interior -= mu0 D[0][:] + muN D[N][:]
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         cend[2 * tid] = mu0;
         cend[2 * tid + 1] = muN;
       }
-      __syncthreads();
+      lds_barrier();
     }
 
     // store: interior nodes (accumulated), the two end nodes (0); values

@@ -177,6 +177,16 @@ struct DFT {
   }
 };
 
+// Workgroup barrier over LDS only: waits for this thread's LDS accesses, not
+// for its global loads in flight (a __syncthreads() fence waits for those too,
+// which serialises a prefetch into the next barrier).  For barriers whose only
+// purpose is the exchange through LDS.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Four-step split of the even-extension length L = 2N = R1 * R2 used by the
 // pencil DCT-I.  Both factors are register DFT sizes; R2 is even.
