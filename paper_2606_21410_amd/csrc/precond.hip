@@ -524,21 +524,43 @@ __device__ __forceinline__ T fdm_scale(T v, double ik, double sc, T lam) {
 }
 
 // acc[rb] (16 rows of row block rb, every rb) = table x B, k-step by k-step
-// (KIND 0: KF steps over B[ks]; kinds 1, 2: KH steps, the symmetric blocks
-// over B[ks], the antisymmetric ones over B[KH + ks])
-template <typename T, int KIND, int NB, int KF, int KH>
+// (KIND 0: KF steps; kinds 1, 2: KH steps, the symmetric blocks taking one
+// operand, the antisymmetric ones the other).  MASKED: B holds the pencil's
+// raw loads (see k_fdm_wave's load()), turned into operands here, one step at
+// a time, so that each step waits only for its own loads; otherwise B holds
+// the operands themselves (B[ks] and, kinds 1 and 2, B[KH + ks]).
+template <typename T, int KIND, int NB, int KF, int KH, bool MASKED>
 __device__ __forceinline__ void contract(const T* __restrict__ tab, int lane, const T (&B)[KF],
-                                         typename Mfma<T>::v4 (&acc)[NB]) {
+                                         typename Mfma<T>::v4 (&acc)[NB], int lk, int m, bool valid) {
   constexpr int NKS = KIND ? KH : KF;
+  constexpr bool F32 = sizeof(T) == sizeof(float);
+  const int ps = (m + 1) / 2, ph = m / 2;
 #pragma unroll
   for (int rb = 0; rb < NB; ++rb) acc[rb] = typename Mfma<T>::v4{0, 0, 0, 0};
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
     // one step's table reads at a time: hoisting more only costs registers
     __builtin_amdgcn_sched_barrier(0);
+    const int j = fdm_kmap(ks, lk, F32);
+    T bs, ba;  // operand of the symmetric (or every) row block, of the antisymmetric ones
+    if constexpr (!MASKED) {
+      bs = B[ks];
+      ba = KIND ? B[KH + ks] : bs;
+    } else if constexpr (KIND == 1) {
+      // pair sums and differences; the middle node of odd m (j = ph) stands alone
+      const T xj = B[ks], xr = B[KH + ks];
+      bs = valid ? (j < ph ? xj + xr : xj) : T(0);
+      ba = valid && j < ph ? xj - xr : T(0);
+    } else if constexpr (KIND == 2) {
+      bs = valid ? B[ks] : T(0);
+      ba = valid && ps + j < m ? B[KH + ks] : T(0);
+    } else {
+      bs = valid && j < m ? B[ks] : T(0);
+      ba = bs;
+    }
 #pragma unroll
     for (int rb = 0; rb < NB; ++rb)
-      acc[rb] = Mfma<T>::mac(tab[(rb * NKS + ks) * 64 + lane], B[(KIND && rb >= NB / 2) ? KH + ks : ks], acc[rb]);
+      acc[rb] = Mfma<T>::mac(tab[(rb * NKS + ks) * 64 + lane], (KIND && rb >= NB / 2) ? ba : bs, acc[rb]);
   }
 }
 
@@ -607,36 +629,38 @@ __global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
     ia = axis == 0 ? i1 : i0;  // the first transverse axis' index
     ib = axis == 2 ? i1 : i2;  // the second one's
   };
-  // the B operand: row fdm_kmap(ks, lk) of the pencil at step ks (kind 1: the
-  // pair sums for the symmetric blocks, then the differences; kind 2: the
-  // first ps rows, then the rest)
+  // the B operand's raw loads: row fdm_kmap(ks, lk) of the pencil at step ks
+  // (kind 1: and its mirror node m-1-j for the pair sums and differences;
+  // kind 2: the first ps rows, then the rest).  Every load is issued, rows past
+  // the pencil clamped to its last node and invalid lanes reading element 0, so
+  // the number in flight is static and the matrix-core steps wait only for
+  // their own loads; contract() masks the values it does not use.
   T B[KF];
   auto load = [&]() {
     if (SA == 1) {
 #pragma unroll
       for (int ks = 0; ks < KH; ++ks) {
         const int j = fdm_kmap(ks, lk, F32);  // < ps
-        const T xj = valid ? X[bx + (long long)j * sxa] : T(0);
-        const T xr = valid && j < ph ? X[bx + (long long)(m - 1 - j) * sxa] : T(0);
-        B[ks] = j < ph ? xj + xr : xj;  // j = ph: the middle node of odd m
-        B[KH + ks] = j < ph ? xj - xr : T(0);
+        const int jr = j < ph ? m - 1 - j : j;
+        B[ks] = X[bx + (long long)j * sxa];
+        B[KH + ks] = X[bx + (long long)jr * sxa];
       }
     } else if (SA == 2) {
 #pragma unroll
       for (int ks = 0; ks < KH; ++ks) {
         const int j = fdm_kmap(ks, lk, F32);
-        B[ks] = valid ? X[bx + (long long)j * sxa] : T(0);
-        B[KH + ks] = valid && ps + j < m ? X[bx + (long long)(ps + j) * sxa] : T(0);
+        const int j2 = ps + j < m ? ps + j : m - 1;
+        B[ks] = X[bx + (long long)j * sxa];
+        B[KH + ks] = X[bx + (long long)j2 * sxa];
       }
     } else {
 #pragma unroll
       for (int ks = 0; ks < KF; ++ks) {
         const int j = fdm_kmap(ks, lk, F32);
-        B[ks] = valid && j < m ? X[bx + (long long)j * sxa] : T(0);
+        B[ks] = X[bx + (long long)(j < m ? j : m - 1) * sxa];
       }
     }
-  };
-  // the fragment tables (and eigenvalues) into LDS, 16 bytes per lane, the
+  };  // the fragment tables (and eigenvalues) into LDS, 16 bytes per lane, the
   // loads of a table in flight together (a load-store loop would pay the L2
   // latency once per iteration); before the first task's operand loads, which
   // would hold the table's loads back behind memory latency
@@ -676,7 +700,7 @@ __global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
     // every row block at once, k-step by k-step: eight independent
     // accumulation chains, started as soon as the first rows arrive
     V4 acc[NB];
-    contract<T, SA, NB, KF, KH>(tabA, lane, B, acc);
+    contract<T, SA, NB, KF, KH, true>(tabA, lane, B, acc, lk, m, valid);
     if constexpr (MID) {
       // the first contraction, scaled, is the second one's B operand
       const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;
@@ -689,7 +713,7 @@ __global__ __launch_bounds__(64 * kFdmWaves) void k_fdm_wave(FdmArgs g) {
           const int i = 16 * rb + Mfma<T>::row(lk, r);
           B[4 * rb + r] = i < m ? fdm_scale<T>(acc[rb][r], ik, sc, lam_s[axis * 128 + i]) : T(0);
         }
-      contract<T, SB, NB, KF, KH>(tabB, lane, B, acc);
+      contract<T, SB, NB, KF, KH, false>(tabB, lane, B, acc, lk, m, valid);
     } else if constexpr (SCL) {
       const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;
       const double sc = valid ? double(lam_s[a0 * 128 + ia]) + double(lam_s[a1 * 128 + ib]) : 0.0;
