@@ -23,7 +23,10 @@ recurrence here.  Everything is the plain definition, written out:
 * the adjoint of the reduced system and dL/dlog K;
 * Picard (lagged-coefficient) iteration for K = K0 (1 + u^2/2);
 * Newton's method for k = K0 / (1 + alpha T) (Section 3.4): residual, the
-  reduced Jacobian action and the outer loop.
+  reduced Jacobian action and the outer loop;
+* Robin rows du/dn + sigma u = g with sigma per face plus a per-node part
+  (Section 2.3.1's general linear row; the flux condition of Section 3.4 is
+  such a row with a node-dependent sigma).
 
 Readings of the paper that this oracle fixes (edge/corner ownership, Neumann
 datum = outward du/dn, operator sign div(K grad u) = f, ascending node order)
@@ -93,7 +96,8 @@ def deriv_t(D: np.ndarray, U: np.ndarray, axis: int) -> np.ndarray:
 class Grid3:
     """Tensor CGL grid with per-face boundary types (x_lo, x_hi, y_lo, y_hi, z_lo, z_hi)."""
 
-    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(DIRICHLET,) * 6, robin=None):
+    def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(DIRICHLET,) * 6, robin=None,
+                 robin_nodes=None):
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)
@@ -104,6 +108,16 @@ class Grid3:
             raise ValueError("a Robin coefficient needs a Neumann face")
         if any(v < 3 for v in self.n):
             raise ValueError("at least 3 nodes per axis")
+        # a per-node part of sigma (packed faces, the layout of g), added to
+        # robin[f] at each node of face f; a coefficient that varies along the
+        # face is the general linear row of Section 2.3.1 with node-dependent
+        # coefficients (the flux row of Section 3.4 is one)
+        self.robin_nodes = None
+        if robin_nodes is not None:
+            faces = [np.array(F, dtype=np.float64) for F in self.unpack_faces(np.asarray(robin_nodes))]
+            if any(self.bc[f] == DIRICHLET and np.any(faces[f] != 0.0) for f in range(6)):
+                raise ValueError("a Robin coefficient needs a Neumann face")
+            self.robin_nodes = faces
         self.D = [diff_matrix(self.n[a] - 1, self.lo[a], self.hi[a]) for a in range(3)]
         self.x = [nodes(self.n[a] - 1, self.lo[a], self.hi[a]) for a in range(3)]
         self.owner = owner_map(self.n, self.bc)
@@ -115,6 +129,21 @@ class Grid3:
     def face_shape(self, f):
         a = f // 2
         return tuple(self.n[b] for b in range(3) if b != a)
+
+    def sigma(self, f):
+        """Robin coefficient at every node of face f (array of the face's shape)."""
+        s = np.full(self.face_shape(f), self.robin[f])
+        if self.robin_nodes is not None:
+            s = s + self.robin_nodes[f]
+        return s
+
+    def sigma_mean(self):
+        """Mean Robin coefficient of each face (the constant-coefficient
+        operator that preconditions a node-dependent one uses these)."""
+        return tuple(float(np.mean(self.sigma(f))) for f in range(6))
+
+    def sigma_uniform(self):
+        return all(np.all(self.sigma(f) == self.robin[f]) for f in range(6))
 
     def unpack_faces(self, g):
         out, off = [], 0
@@ -163,15 +192,27 @@ def interior_operator(G: Grid3, K: np.ndarray, U: np.ndarray) -> np.ndarray:
 
 
 def end_block(G: Grid3, a: int):
-    """Coefficients of the two end values in the boundary rows of a pencil along
-    axis a, written as  m00 U_0 + m0N U_N = -g_lo - s_0,  mN0 U_0 + mNN U_N = g_hi - s_N
-    with s the rows' sums over the inner nodes.  The lo row is
-    -(D U)_0 + sigma_lo U_0 = g_lo, the hi row (D U)_N + sigma_hi U_N = g_hi
-    (the general linear row a u + b du/dn = g of Section 2.3.1 with b != 0,
-    divided by b; sigma = 0 is the Neumann row)."""
+    """Coefficients of the two end values in the boundary rows of each pencil
+    along axis a, written as  m00 U_0 + m0N U_N = -g_lo - s_0,
+    mN0 U_0 + mNN U_N = g_hi - s_N  with s the rows' sums over the inner nodes.
+    The lo row is -(D U)_0 + sigma_lo U_0 = g_lo, the hi row
+    (D U)_N + sigma_hi U_N = g_hi (the general linear row a u + b du/dn = g of
+    Section 2.3.1 with b != 0, divided by b; sigma = 0 is the Neumann row).
+    m00 and mNN are arrays over the pencils (the face's shape: sigma may vary
+    from node to node), m0N and mN0 scalars."""
     D = G.D[a]
     N = G.n[a] - 1
-    return (D[0, 0] - G.robin[2 * a], D[0, N], D[N, 0], D[N, N] + G.robin[2 * a + 1])
+    return (D[0, 0] - G.sigma(2 * a), D[0, N], D[N, 0], D[N, N] + G.sigma(2 * a + 1))
+
+
+def _blocks(m00, m0N, mN0, mNN):
+    """Stack of 2 x 2 end blocks [[m00, m0N], [mN0, mNN]], one per pencil."""
+    M = np.empty(m00.shape + (2, 2))
+    M[..., 0, 0] = m00
+    M[..., 0, 1] = m0N
+    M[..., 1, 0] = mN0
+    M[..., 1, 1] = mNN
+    return M
 
 
 def bc_rows(G: Grid3, U: np.ndarray) -> np.ndarray:
@@ -187,7 +228,8 @@ def bc_rows(G: Grid3, U: np.ndarray) -> np.ndarray:
             y[m] = U[m]
         else:
             d = deriv(G.D[a], U, a)
-            y[m] = (d if side == 1 else -d)[m] + G.robin[f] * U[m]
+            sig = np.broadcast_to(np.expand_dims(G.sigma(f), a), G.n)
+            y[m] = (d if side == 1 else -d)[m] + sig[m] * U[m]
     return y
 
 
@@ -250,17 +292,17 @@ def lift(G: Grid3, x: np.ndarray, g=None) -> np.ndarray:
         if both.any():
             s0 = inner[both] @ D[0, 1:N]
             sN = inner[both] @ D[N, 1:N]
-            M = np.array([[m00, m0N], [mN0, mNN]])
-            rhs = np.stack([-glo[both] - s0, ghi[both] - sN])
-            sol = np.linalg.solve(M, rhs)
-            Um[..., 0][both] = sol[0]
-            Um[..., N][both] = sol[1]
+            M = _blocks(m00[both], m0N, mN0, mNN[both])
+            rhs = np.stack([-glo[both] - s0, ghi[both] - sN], axis=-1)
+            sol = np.linalg.solve(M, rhs[..., None])[..., 0]
+            Um[..., 0][both] = sol[:, 0]
+            Um[..., N][both] = sol[:, 1]
         if lo_only.any():
             s0 = Um[lo_only][:, 1:] @ D[0, 1:]
-            Um[..., 0][lo_only] = (-glo[lo_only] - s0) / m00
+            Um[..., 0][lo_only] = (-glo[lo_only] - s0) / m00[lo_only]
         if hi_only.any():
             sN = Um[hi_only][:, :N] @ D[N, :N]
-            Um[..., N][hi_only] = (ghi[hi_only] - sN) / mNN
+            Um[..., N][hi_only] = (ghi[hi_only] - sN) / mNN[hi_only]
     if np.isnan(U).any():
         raise AssertionError("lift left boundary values undetermined")
     return U
@@ -293,25 +335,25 @@ def lift_transpose(G: Grid3, z: np.ndarray) -> np.ndarray:
         hi_only = nhi & ~nlo
         m00, m0N, mN0, mNN = end_block(G, a)
         if both.any():
-            M = np.array([[m00, m0N], [mN0, mNN]])
+            MT = np.swapaxes(_blocks(m00[both], m0N, mN0, mNN[both]), -1, -2)
             # forward: [U0, UN] = M^{-1} [-s0, -sN] (+ data), s = D_{end, 1:N} . inner
             zl = Wm[..., 0][both]
             zh = Wm[..., N][both]
-            mu = np.linalg.solve(M.T, np.stack([zl, zh]))
+            mu = np.linalg.solve(MT, np.stack([zl, zh], axis=-1)[..., None])[..., 0]
             blk = Wm[both]
-            blk[:, 1:N] -= np.outer(mu[0], D[0, 1:N]) + np.outer(mu[1], D[N, 1:N])
+            blk[:, 1:N] -= np.outer(mu[:, 0], D[0, 1:N]) + np.outer(mu[:, 1], D[N, 1:N])
             blk[:, 0] = 0.0
             blk[:, N] = 0.0
             Wm[both] = blk
         if lo_only.any():
             blk = Wm[lo_only]
-            mu = blk[:, 0] / m00
+            mu = blk[:, 0] / m00[lo_only]
             blk[:, 1:] -= np.outer(mu, D[0, 1:])
             blk[:, 0] = 0.0
             Wm[lo_only] = blk
         if hi_only.any():
             blk = Wm[hi_only]
-            mu = blk[:, N] / mNN
+            mu = blk[:, N] / mNN[hi_only]
             blk[:, :N] -= np.outer(mu, D[N, :N])
             blk[:, N] = 0.0
             Wm[hi_only] = blk
@@ -369,7 +411,7 @@ def assemble_full(G: Grid3, K: np.ndarray) -> np.ndarray:
             A[rows, rows] = 1.0
         else:
             A[rows, :] = (Da[a][rows, :].toarray()) * (1.0 if side == 1 else -1.0)
-            A[rows, rows] += G.robin[f]
+            A[rows, rows] += np.broadcast_to(np.expand_dims(G.sigma(f), a), G.n).ravel()[rows]
     return A
 
 
@@ -422,16 +464,20 @@ def reduced_1d(D: np.ndarray, bclo: int, bchi: int, slo: float = 0.0, shi: float
 
 class FDM:
     """Exact inverse of the constant-coefficient reduced operator Kc * (A_x + A_y + A_z)
-    (Kronecker sum of 1-D reduced operators) by eigendecomposition of each."""
+    (Kronecker sum of 1-D reduced operators) by eigendecomposition of each.
+    Robin coefficients that vary along a face enter through their face means:
+    the inverse is then exact only for its own constant-coefficient operator
+    (a preconditioner for the node-dependent one)."""
 
     def __init__(self, G: Grid3, Kc: float = 1.0):
-        if all(b == NEUMANN for b in G.bc) and not any(G.robin):
+        sm = G.sigma_mean()
+        if all(b == NEUMANN for b in G.bc) and not any(sm):
             raise ValueError("all-Neumann problem is singular")
         self.G = G
         self.Kc = float(Kc)
         self.V, self.Vi, self.lam = [], [], []
         for a in range(3):
-            A1 = reduced_1d(G.D[a], G.bc[2 * a], G.bc[2 * a + 1], G.robin[2 * a], G.robin[2 * a + 1])
+            A1 = reduced_1d(G.D[a], G.bc[2 * a], G.bc[2 * a + 1], sm[2 * a], sm[2 * a + 1])
             w, V = np.linalg.eig(A1)
             if np.max(np.abs(w.imag)) > 1e-8 * np.max(np.abs(w)):
                 raise AssertionError("complex eigenvalues in 1-D reduced operator")
@@ -506,7 +552,7 @@ def solve_interior_system(G: Grid3, K, rhs_int_full, tol=1e-13, x0=None, Kc=None
     directly.  Variable K: GMRES right-preconditioned by FDM at mean(K)."""
     K = np.asarray(K)
     kmin, kmax = float(K.min()), float(K.max())
-    if kmax - kmin <= 1e-15 * max(abs(kmax), 1.0):
+    if kmax - kmin <= 1e-15 * max(abs(kmax), 1.0) and G.sigma_uniform():
         return FDM(G, kmax).solve(rhs_int_full), 0, 0.0
     fdm = FDM(G, float(np.mean(K)) if Kc is None else Kc)
     mask = G.interior

@@ -55,6 +55,8 @@ class Grid:
     bc: tuple[int, int, int, int, int, int] = (DIRICHLET,) * 6
     # sigma of the Neumann row du/dn + sigma u = g per face (0: plain Neumann)
     robin: tuple[float, float, float, float, float, float] = (0.0,) * 6
+    # per-node part of sigma (packed faces like g, added to robin[f]); None: none
+    robin_nodes: np.ndarray | None = None
 
     def coords(self):
         return [cgl_coords(self.n[a], self.lo[a], self.hi[a]) for a in range(3)]
@@ -125,9 +127,23 @@ def _faces_from(grid: Grid, value_fn, grad_fn):
         else:
             sgn = -1.0 if side == 0 else 1.0
             data = sgn * grad_fn(X, Y, Z)[a]
-            if grid.robin[f] != 0.0:
-                data = data + grid.robin[f] * value_fn(X, Y, Z)
+            sig = grid.robin[f]
+            if grid.robin_nodes is not None:
+                sig = sig + unpack_faces(grid, grid.robin_nodes)[f]
+            if np.any(sig != 0.0):
+                data = data + sig * value_fn(X, Y, Z)
             faces.append(data)
+    return pack_faces(faces)
+
+
+def random_robin_nodes(grid: Grid, seed: int, lo: float = 0.2, hi: float = 2.0) -> np.ndarray:
+    """Per-node Robin coefficients (packed faces): uniform in [lo, hi] on the
+    Neumann faces, 0 on the Dirichlet faces."""
+    r = rng(seed)
+    faces = []
+    for f in range(6):
+        s = grid.face_shape(f)
+        faces.append(r.uniform(lo, hi, size=s) if grid.bc[f] == NEUMANN else np.zeros(s))
     return pack_faces(faces)
 
 
@@ -177,13 +193,20 @@ def manufactured_paper3d(n: int) -> Problem:
                    {"name": "paper-3d-poisson"})
 
 
-def thermal_nonlinear(n: int, alpha: float = 0.5) -> Problem:
+def thermal_nonlinear(n: int, alpha: float = 0.5, flux_form: bool = False) -> Problem:
     """The nonlinear thermal example of Section 3.4 on (0,1)^3, written for
     div(k(T) grad T) = f with k(T) = K0 / (1 + alpha T), K0 = 1:
     Phi = sin(pi x) sin(pi y) sin(pi z), T = (exp(alpha Phi) - 1) / alpha, so
     k(T) grad T = grad Phi and f = Laplacian(Phi) = -3 pi^2 Phi.  Dirichlet on
-    x=0 and y=0, Neumann (outward dT/dn) on x=1, y=1, z=0 and z=1.  Phi = 0 on
-    every face, so there T = 0, k = 1 and dT/dn equals the prescribed flux."""
+    x=0 and y=0; on x=1, y=1, z=0 and z=1 the prescribed outward flux
+    h = k(T) dT/dn = dPhi/dn.
+
+    flux_form False: the Neumann rows read dT/dn = h.  Phi = 0 on every face,
+    so there T = 0, k = 1 and the exact solution satisfies them.
+    flux_form True: the rows are the flux condition itself, k(T) dT/dn = h.
+    With 1/k = (1 + alpha T)/K0 it is linear in T: dT/dn - (alpha h/K0) T = h/K0,
+    a Robin row with the per-node coefficient -alpha h/K0 (grid.robin_nodes)
+    and data h/K0 (the same data here, K0 = 1)."""
     grid = Grid((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
                 (DIRICHLET, NEUMANN, DIRICHLET, NEUMANN, NEUMANN, NEUMANN))
     pi = math.pi
@@ -204,17 +227,26 @@ def thermal_nonlinear(n: int, alpha: float = 0.5) -> Problem:
     X, Y, Z = grid.mesh()
     ue = u(X, Y, Z)
     f = -3.0 * pi * pi * phi(X, Y, Z)
-    return Problem(grid, np.ones_like(ue), f, _faces_from(grid, u, grad), ue,
-                   {"name": "thermal-nonlinear", "alpha": alpha})
+    g = _faces_from(grid, u, grad)
+    if flux_form:
+        # sigma = -alpha h / K0 on the Neumann faces (K0 = 1); T = 0 there, so
+        # the data h/K0 of the Robin rows is g as formed above
+        grid.robin_nodes = pack_faces([-alpha * F if grid.bc[f_] == NEUMANN else np.zeros_like(F)
+                                       for f_, F in enumerate(unpack_faces(grid, g))])
+    return Problem(grid, np.ones_like(ue), f, g, ue,
+                   {"name": "thermal-nonlinear-flux" if flux_form else "thermal-nonlinear", "alpha": alpha})
 
 
 def manufactured_polynomial(n: int, bc, seed: int = 7, deg_u: int = 3,
-                            lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), robin=(0.0,) * 6) -> Problem:
+                            lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), robin=(0.0,) * 6,
+                            robin_nodes=None) -> Problem:
     """Random separable-sum polynomial u with polynomial K (degree 1); the
     discrete operator is exact for it when deg u + deg K - 1 <= N.  Neumann faces
-    with a nonzero robin[f] carry the data du/dn + robin[f] u."""
+    with a nonzero coefficient (robin[f] plus the face's entries of the packed
+    per-node array robin_nodes) carry the data du/dn + sigma u."""
     r = rng(seed)
-    grid = Grid((n, n, n), tuple(lo), tuple(hi), tuple(bc), tuple(float(v) for v in robin))
+    grid = Grid((n, n, n), tuple(lo), tuple(hi), tuple(bc), tuple(float(v) for v in robin),
+                None if robin_nodes is None else np.asarray(robin_nodes, dtype=np.float64))
     cu = r.normal(size=(deg_u + 1, deg_u + 1, deg_u + 1)) / 4
     ck = r.uniform(0.1, 0.3, size=3)
 

@@ -109,3 +109,73 @@ def test_sincos_robin_spectral_convergence():
         U = O.solve(G, P.K, P.f, P.g)
         err.append(np.max(np.abs(U - P.u_exact)))
     assert err[1] < 1e-4 * err[0] and err[1] < 1e-7
+
+
+# ---- Robin coefficients that vary from node to node along a face ----------
+
+def _node_grid(G, rn):
+    return O.Grid3(G.n, G.lo, G.hi, G.bc, G.robin, rn)
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_polynomial_exact_with_node_robin(bc, robin):
+    """Per-node coefficients on top of the per-face ones: the polynomial still
+    satisfies every row exactly, so the discrete solution is the polynomial.
+    The face data are formed from the analytic field on each face's own
+    coordinates, so a transposed or shifted coefficient array fails this."""
+    grid = W.Grid((7, 7, 7), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bc, robin)
+    rn = W.random_robin_nodes(grid, 21)
+    P = W.manufactured_polynomial(7, bc, seed=5, robin=robin, robin_nodes=rn)
+    G = O.Grid3(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, P.grid.robin, rn)
+    U = O.solve_dense(G, P.K, P.f, P.g)
+    np.testing.assert_allclose(U, P.u_exact, atol=1e-10 * np.abs(P.u_exact).max())
+    Ug = O.solve(G, P.K, P.f, P.g, method="gmres")
+    np.testing.assert_allclose(Ug, P.u_exact, atol=1e-9 * np.abs(P.u_exact).max())
+    # the face means instead of the node values are a different problem
+    Gm = O.Grid3(G.n, G.lo, G.hi, G.bc, G.sigma_mean())
+    assert np.abs(O.solve_dense(Gm, P.K, P.f, P.g) - P.u_exact).max() > 1e-4
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_constant_node_robin_is_face_robin(bc, robin):
+    """A per-node array that is constant on each face is the per-face
+    coefficient: lift, reduced operator, transpose and full rows agree."""
+    r = np.random.default_rng(22)
+    G = O.Grid3((6, 7, 5), (0, 0, 0), (1.0, 2.0, 0.5), bc, robin)
+    G0 = O.Grid3(G.n, G.lo, G.hi, G.bc)
+    rn = W.pack_faces([np.full(G.face_shape(f), robin[f]) for f in range(6)])
+    Gn = _node_grid(G0, rn)
+    x = r.standard_normal(G.n)
+    K = np.exp(0.3 * r.standard_normal(G.n))
+    g = W.random_faces(W.Grid(G.n, G.lo, G.hi, G.bc), 23)
+    np.testing.assert_allclose(O.lift(Gn, x, g), O.lift(G, x, g), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(O.apply_reduced(Gn, K, x), O.apply_reduced(G, K, x), rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(O.apply_reduced_transpose(Gn, K, x), O.apply_reduced_transpose(G, K, x),
+                               rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(O.apply_full(Gn, K, x), O.apply_full(G, K, x), rtol=1e-12, atol=1e-10)
+
+
+@pytest.mark.parametrize("bc,robin", ROBIN_CASES)
+def test_node_robin_elimination_and_transpose(bc, robin):
+    """With node-dependent coefficients the reduced operator is still the
+    Schur complement of the assembled matrix, and its transpose the
+    transposed complement."""
+    r = np.random.default_rng(24)
+    G0 = O.Grid3((5, 6, 7), (0, 0, 0), (1, 1.5, 2), bc, robin)
+    G = _node_grid(G0, W.random_robin_nodes(W.Grid(G0.n, G0.lo, G0.hi, G0.bc), 25, -0.5, 2.0))
+    K = np.exp(0.4 * r.standard_normal(G.n))
+    A = O.assemble_full(G, K)
+    k = np.nonzero(G.interior.ravel())[0]
+    rr = np.nonzero(~G.interior.ravel())[0]
+    Ared = A[np.ix_(k, k)] - A[np.ix_(k, rr)] @ np.linalg.solve(A[np.ix_(rr, rr)], A[np.ix_(rr, k)])
+    x = r.standard_normal(G.n)
+    v = r.standard_normal(G.n)
+    np.testing.assert_allclose(O.apply_reduced(G, K, x).ravel()[k], Ared @ x.ravel()[k],
+                               atol=1e-9 * np.abs(Ared).max())
+    np.testing.assert_allclose(O.apply_reduced_transpose(G, K, v).ravel()[k], Ared.T @ v.ravel()[k],
+                               atol=1e-9 * np.abs(Ared).max())
+    # the lift meets every owned row with its own node's coefficient
+    g = W.random_faces(W.Grid(G.n, G.lo, G.hi, G.bc), 26)
+    U = O.lift(G, x, g)
+    fv = O.face_values(G, g)
+    np.testing.assert_allclose(O.bc_rows(G, U)[~G.interior], fv[~G.interior], atol=1e-10)
