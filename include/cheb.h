@@ -146,6 +146,26 @@ int cheb_plan_set_workspace(cheb_plan* plan, void* dev_ptr, size_t bytes);
 /* Change the stream subsequent calls enqueue on. */
 int cheb_plan_set_stream(cheb_plan* plan, void* stream);
 
+/* Robin coefficients that vary along a face (Section 2.3.1's general linear
+ * row with node-dependent coefficients; the flux condition k(T) dT/dn = h of
+ * Section 3.4 with k = K0 / (1 + alpha T) is the row
+ * dT/dn - (alpha h / K0) T = h / K0, i.e. sigma = -alpha h / K0 at each node and
+ * data h / K0).  sigma_faces: FP64, the packed face layout of g_faces (faces
+ * x_lo .. z_hi, each n_b x n_c in the order of the two other axes); entry i of
+ * face f is added to grid.robin[f] at that node.  Entries on Dirichlet faces
+ * must be 0.  The library copies the array (device or host memory; the caller
+ * keeps ownership) into plan-owned device memory (FP64 and FP32 copies, one
+ * packed-face array each) and synchronises the plan's stream.  Every operator,
+ * lift, solve, adjoint and Newton call of the plan then uses the node's own
+ * row; the reduced operator runs on the FFT route (the lift reads each
+ * pencil's coefficients), and the preconditioner, rebuilt on its next use,
+ * uses each face's mean coefficient.  NULL removes the per-node part.
+ * Returns CHEB_ERR_INVALID_ARG for a null plan, a non-finite entry, a nonzero
+ * entry on a Dirichlet face, or coefficients that make some pencil's
+ * end-value elimination block singular (the plan is then unchanged), and
+ * CHEB_ERR_DEVICE on a HIP failure. */
+int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces);
+
 /* Choose how the reduced operator and its transpose evaluate the per-axis
  * derivatives (Section 2.2 defines the derivative; both routes compute it):
  *   CHEB_ROUTE_FFT    -- the DCT-I of each pencil through the FFT of its even

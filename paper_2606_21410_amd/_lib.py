@@ -61,6 +61,7 @@ _SIGS = {
     "cheb_plan_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "cheb_plan_set_stream": (ctypes.c_int, [_vp, _vp]),
     "cheb_plan_set_route": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cheb_plan_set_robin_nodes": (ctypes.c_int, [_vp, _vp]),
     "cheb_plan_set_tile_shape": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cheb_plan_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_int32]),

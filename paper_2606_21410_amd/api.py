@@ -55,10 +55,12 @@ class Plan:
     """One grid: sizes, box, face types, precision ('f64', 'f32', 'mixed').
 
     ``robin``: six coefficients sigma, one per face; a Neumann face with sigma != 0
-    carries the Robin row du/dn + sigma u = g (cheb_grid.robin)."""
+    carries the Robin row du/dn + sigma u = g (cheb_grid.robin).
+    ``robin_nodes``: optional per-node part of sigma (packed faces, the layout of
+    g; see set_robin_nodes)."""
 
     def __init__(self, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0,) * 6, precision="f64",
-                 device="cuda", route: str = "auto", robin=None):
+                 device="cuda", route: str = "auto", robin=None, robin_nodes=None):
         self.lib = L.load()
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
@@ -81,6 +83,27 @@ class Plan:
         self._ws = None
         self._ws_bytes = 0
         self.set_route(route)
+        self.robin_nodes = None
+        if robin_nodes is not None:
+            self.set_robin_nodes(robin_nodes)
+
+    def set_robin_nodes(self, sigma_faces):
+        """Robin coefficients that vary from node to node (cheb_plan_set_robin_nodes):
+        ``sigma_faces`` holds, in the packed face layout of g, the per-node part
+        added to ``robin[f]`` on each face (0 on Dirichlet faces); None removes
+        it.  The flux condition k(T) dT/dn = h of k = K0 / (1 + alpha T) is the
+        row with sigma = -alpha h / K0 and data h / K0."""
+        if sigma_faces is None:
+            L.check(self.lib.cheb_plan_set_robin_nodes(self._h, None))
+            self.robin_nodes = None
+            return
+        t = torch.as_tensor(sigma_faces, dtype=torch.float64).to(self.device).contiguous()
+        want = sum(self.n[b] * self.n[c] for b, c in ((1, 2), (1, 2), (0, 2), (0, 2), (0, 1), (0, 1)))
+        if t.numel() != want:
+            raise ValueError(f"robin_nodes: expected {want} packed face entries, got {t.numel()}")
+        self._sync_stream()
+        L.check(self.lib.cheb_plan_set_robin_nodes(self._h, ctypes.c_void_p(t.data_ptr())))
+        self.robin_nodes = t
 
     def set_route(self, route: str):
         """'auto', 'fft' or 'matrix': how the reduced operator evaluates the per-axis derivatives."""

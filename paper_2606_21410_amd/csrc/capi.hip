@@ -291,6 +291,96 @@ int cheb_plan_set_stream(cheb_plan* plan, void* stream) {
   return CHEB_OK;
 }
 
+static void drop_precond(cheb_plan* p) {
+  if (p->pc64) (void)hipFree(p->pc64);
+  if (p->pc32) (void)hipFree(p->pc32);
+  p->pc64 = nullptr;
+  p->pc32 = nullptr;
+  p->pc_ready = 0;
+}
+
+int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces) {
+  if (!plan) {
+    set_error("null plan");
+    return CHEB_ERR_INVALID_ARG;
+  }
+  const int* n = plan->g.n;
+  const size_t cnt = (size_t)face_offset(6, n);
+  if (!sigma_faces) {
+    if (plan->rn64) {
+      int rc = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+      if (rc) return rc;
+      (void)hipFree(plan->rn64);
+      (void)hipFree(plan->rn32);
+      plan->rn64 = nullptr;
+      plan->rn32 = nullptr;
+      drop_precond(plan);
+    }
+    return CHEB_OK;
+  }
+  std::vector<double> h(cnt);
+  int rc = hip_check(hipMemcpyAsync(h.data(), sigma_faces, cnt * sizeof(double), hipMemcpyDefault, plan->stream),
+                     "hipMemcpyAsync(Robin coefficients)");
+  if (!rc) rc = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  double mean[6];
+  for (int f = 0; f < 6; ++f) {
+    const long long o = face_offset(f, n), m = face_offset(f + 1, n) - o;
+    double s = 0.0;
+    for (long long i = 0; i < m; ++i) {
+      const double v = h[o + i];
+      if (!std::isfinite(v) || (plan->g.bc[f] == CHEB_DIRICHLET && v != 0.0)) {
+        set_error("per-node Robin coefficients must be finite, and 0 on Dirichlet faces");
+        return CHEB_ERR_INVALID_ARG;
+      }
+      s += v;
+    }
+    mean[f] = m > 0 ? s / double(m) : 0.0;
+  }
+  // every pencil's end-value block with its own nodes' coefficients (as the
+  // per-face check of cheb_plan_create)
+  for (int a = 0; a < 3; ++a) {
+    const AxisConst& c = plan->ax[a];
+    const bool nlo = plan->g.bc[2 * a] == CHEB_NEUMANN, nhi = plan->g.bc[2 * a + 1] == CHEB_NEUMANN;
+    if (!nlo && !nhi) continue;
+    const double r00 = c.m00 + plan->g.robin[2 * a], rNN = c.mNN - plan->g.robin[2 * a + 1];
+    const long long olo = face_offset(2 * a, n), ohi = face_offset(2 * a + 1, n);
+    for (int p = 0; p < pencil_count(a, n); ++p) {
+      const double m00 = c.m00 - h[olo + p], mNN = c.mNN + h[ohi + p];
+      const double det = m00 * mNN - c.m0N * c.mN0;
+      const double scale = std::fabs(m00 * mNN) + std::fabs(c.m0N * c.mN0);
+      if ((nlo && !(std::fabs(m00) > 1e-12 * std::fabs(r00))) || (nhi && !(std::fabs(mNN) > 1e-12 * std::fabs(rNN))) ||
+          (nlo && nhi && !(std::fabs(det) > 1e-12 * scale))) {
+        set_error("per-node Robin coefficients make a boundary elimination block singular");
+        return CHEB_ERR_INVALID_ARG;
+      }
+    }
+  }
+  std::vector<float> h32(cnt);
+  for (size_t i = 0; i < cnt; ++i) h32[i] = float(h[i]);
+  rc = CHEB_OK;
+  if (!plan->rn64) {
+    rc = hip_check(hipMalloc((void**)&plan->rn64, cnt * sizeof(double)), "hipMalloc(Robin coefficients)");
+    if (!rc) rc = hip_check(hipMalloc((void**)&plan->rn32, cnt * sizeof(float)), "hipMalloc(Robin coefficients)");
+    if (rc) {
+      if (plan->rn64) (void)hipFree(plan->rn64);
+      plan->rn64 = nullptr;
+      plan->rn32 = nullptr;
+      return rc;
+    }
+  }
+  rc = hip_check(hipMemcpyAsync(plan->rn64, h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, plan->stream),
+                 "hipMemcpyAsync(Robin coefficients)");
+  if (!rc)
+    rc = hip_check(hipMemcpyAsync(plan->rn32, h32.data(), cnt * sizeof(float), hipMemcpyHostToDevice, plan->stream),
+                   "hipMemcpyAsync(Robin coefficients)");
+  if (!rc) rc = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  for (int f = 0; f < 6; ++f) plan->rn_mean[f] = mean[f];
+  drop_precond(plan);
+  return CHEB_OK;
+}
+
 int cheb_plan_set_route(cheb_plan* plan, int32_t route) {
   if (!plan) {
     set_error("null plan");
@@ -335,6 +425,8 @@ int cheb_plan_destroy(cheb_plan* plan) {
   if (plan->hpinned) (void)hipHostFree(plan->hpinned);
   if (plan->pc64) (void)hipFree(plan->pc64);
   if (plan->pc32) (void)hipFree(plan->pc32);
+  if (plan->rn64) (void)hipFree(plan->rn64);
+  if (plan->rn32) (void)hipFree(plan->rn32);
   delete plan;
   return CHEB_OK;
 }

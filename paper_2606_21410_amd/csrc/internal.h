@@ -76,6 +76,12 @@ struct cheb_plan {
   const int* gate;
   double* dd64;
   float* dd32;
+  // per-node Robin coefficients (cheb_plan_set_robin_nodes): packed faces in the
+  // layout of g_faces, added to the grid's per-face coefficients; FP64 and FP32
+  // copies, null when unset.  rn_mean: their face means.
+  double* rn64;
+  float* rn32;
+  double rn_mean[6];
 };
 
 namespace cheb {
@@ -113,10 +119,15 @@ template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
                       hipStream_t s);
 // pi: 0 for the FP64 passes, 1 for the FP32 passes
+// (per-node Robin coefficients run on the FFT route, whose lift reads them per pencil)
 inline bool use_dense(const cheb_plan* p, int axis, int pi) {
-  if (!p->dd_ok[axis] || p->route == CHEB_ROUTE_FFT) return false;
+  if (!p->dd_ok[axis] || p->route == CHEB_ROUTE_FFT || p->rn64) return false;
   return p->route == CHEB_ROUTE_MATRIX || !p->auto_fft[pi];
 }
+
+// Robin coefficient of face f for the constant-coefficient preconditioner: the
+// face's own plus the mean of its per-node part
+inline double face_sigma(const cheb_plan* p, int f) { return p->g.robin[f] + (p->rn64 ? p->rn_mean[f] : 0.0); }
 
 // Arnoldi: a second Gram-Schmidt pass runs when ||w - V h||^2 <= kReorthEta2 ||w||^2
 constexpr double kReorthEta2 = 0.01;

@@ -35,7 +35,17 @@ struct LiftArgs {
   int bc[6];
   int bcmask;
   long long goff[6];
+  const double* rn;  // per-node Robin coefficients (packed like g) or null
 };
+
+// the end block's diagonal entries of pencil p along `axis` with its own
+// nodes' Robin coefficients
+__device__ inline void node_block(const LiftArgs& a, int axis, int p, double& m00, double& mNN) {
+  if (a.rn) {
+    m00 -= a.rn[a.goff[2 * axis] + p];
+    mNN += a.rn[a.goff[2 * axis + 1] + p];
+  }
+}
 
 template <typename T>
 __global__ void k_set_dirichlet(T* U, const T* g, int f, LiftArgs a) {
@@ -92,6 +102,7 @@ __global__ __launch_bounds__(512) void k_lift_axis(T* U, const T* g, int axis, c
   }
   const double glo = g ? double(g[a.goff[2 * axis] + p]) : 0.0;
   const double ghi = g ? double(g[a.goff[2 * axis + 1] + p]) : 0.0;
+  node_block(a, axis, p, m00, mNN);
   if (nlo && nhi) {
     const double r0 = -glo - s0, rN = ghi - sN;
     const double det = m00 * mNN - m0N * mN0;
@@ -138,6 +149,7 @@ __global__ __launch_bounds__(256) void k_lift_z_wave(T* U, const T* g, const T* 
   if (lane != 0) return;
   const double glo = g ? double(g[a.goff[4] + p]) : 0.0;
   const double ghi = g ? double(g[a.goff[5] + p]) : 0.0;
+  node_block(a, 2, p, m00, mNN);
   if (nlo && nhi) {
     const double r0 = -glo - s0, rN = ghi - sN;
     const double det = m00 * mNN - m0N * mN0;
@@ -169,6 +181,7 @@ __global__ void k_lift_t_axis(T* W, int axis, const T* drow0, const T* drowN, do
   const double z0 = double(w[0]), zN = double(w[N * st]);
   double mu0 = 0.0, muN = 0.0;
   int m_lo = 1, m_hi = N - 1;
+  node_block(a, axis, p, m00, mNN);
   if (nlo && nhi) {
     const double det = m00 * mNN - m0N * mN0;
     mu0 = (z0 * mNN - zN * mN0) / det;
@@ -200,6 +213,7 @@ LiftArgs make_args(const cheb_plan* p) {
     const int tb = ax == 0 ? 1 : 0, tc = ax == 2 ? 1 : 2;
     off += (long long)p->g.n[tb] * p->g.n[tc];
   }
+  a.rn = p->rn64;
   return a;
 }
 

@@ -50,6 +50,10 @@ struct PassArgs {
   T cscale;   // -1 / (N * L_axis)
   T m00, m0N, mN0, mNN;  // end-value block of the boundary rows (corner entries, Robin-shifted)
   T slo, shi;            // Robin coefficients of the axis' lo and hi faces (FULL rows)
+  // per-node Robin coefficients (packed faces) or null; rlo / rhi: offsets of
+  // the axis' lo and hi faces, whose entries follow the pencil numbering
+  const T* rnode;
+  int rlo, rhi;
   int npencils;
 };
 
@@ -489,15 +493,20 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
     const int fl = flags[pp];
     if (g == 0 && (fl & PF_TIN)) {
       const bool nlo = (a.bcmask >> (2 * axis)) & 1, nhi = (a.bcmask >> (2 * axis + 1)) & 1;
+      T m00 = a.m00, mNN = a.mNN;
+      if (a.rnode) {
+        m00 -= a.rnode[a.rlo + p0 + pp];
+        mNN += a.rnode[a.rhi + p0 + pp];
+      }
       T u0 = T(0), uN = T(0);
       if (nlo && nhi) {
-        const T det = a.m00 * a.mNN - a.m0N * a.mN0;
-        u0 = (-s0 * a.mNN + sN * a.m0N) / det;
-        uN = (-sN * a.m00 + s0 * a.mN0) / det;
+        const T det = m00 * mNN - a.m0N * a.mN0;
+        u0 = (-s0 * mNN + sN * a.m0N) / det;
+        uN = (-sN * m00 + s0 * a.mN0) / det;
       } else if (nlo) {
-        u0 = -s0 / a.m00;
+        u0 = -s0 / m00;
       } else if (nhi) {
-        uN = -sN / a.mNN;
+        uN = -sN / mNN;
       }
       pen[0] = u0;
       pen[N] = uN;
@@ -553,15 +562,20 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
     if (g == 0) {
       const bool nlo = (a.bcmask >> (2 * axis)) & 1, nhi = (a.bcmask >> (2 * axis + 1)) & 1;
       const T z0 = pen[0], zN = pen[N];
+      T m00 = a.m00, mNN = a.mNN;
+      if (a.rnode && (flags[pp] & PF_VALID)) {
+        m00 -= a.rnode[a.rlo + p0 + pp];
+        mNN += a.rnode[a.rhi + p0 + pp];
+      }
       T mu0 = T(0), muN = T(0);
       if (nlo && nhi) {
-        const T det = a.m00 * a.mNN - a.m0N * a.mN0;
-        mu0 = (z0 * a.mNN - zN * a.mN0) / det;
-        muN = (zN * a.m00 - z0 * a.m0N) / det;
+        const T det = m00 * mNN - a.m0N * a.mN0;
+        mu0 = (z0 * mNN - zN * a.mN0) / det;
+        muN = (zN * m00 - z0 * a.m0N) / det;
       } else if (nlo) {
-        mu0 = z0 / a.m00;
+        mu0 = z0 / m00;
       } else if (nhi) {
-        muN = zN / a.mNN;
+        muN = zN / mNN;
       }
       ends[4 * pp + 0] = mu0;
       ends[4 * pp + 1] = muN;
@@ -611,8 +625,12 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
           if (own) {
             const int bct = (a.bcmask >> (2 * axis + (m == 0 ? 0 : 1))) & 1;
             T r;
-            if (bct == 0) r = ends[4 * pl + (m == 0 ? 0 : 1)];
-            else r = (m == 0) ? a.slo * ends[4 * pl + 0] - ends[4 * pl + 2] : ends[4 * pl + 3] + a.shi * ends[4 * pl + 1];
+            if (bct == 0) {
+              r = ends[4 * pl + (m == 0 ? 0 : 1)];
+            } else {
+              const T sig = (m == 0 ? a.slo : a.shi) + (a.rnode ? a.rnode[(m == 0 ? a.rlo : a.rhi) + p0 + pl] : T(0));
+              r = (m == 0) ? sig * ends[4 * pl + 0] - ends[4 * pl + 2] : ends[4 * pl + 3] + sig * ends[4 * pl + 1];
+            }
             a.y[ad] = r;
           }
         }

@@ -69,6 +69,13 @@ template <>
 inline const float* drow<float>(const cheb_plan* p, int a, int slot) { return dconst32(p, a, slot); }
 
 template <typename T>
+static const T* robin_nodes(const cheb_plan* p);
+template <>
+inline const double* robin_nodes<double>(const cheb_plan* p) { return p->rn64; }
+template <>
+inline const float* robin_nodes<float>(const cheb_plan* p) { return p->rn32; }
+
+template <typename T>
 int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T* K, const T* u, T* y,
                      hipStream_t s) {
   if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && use_dense(p, axis, sizeof(T) == sizeof(double) ? 0 : 1))
@@ -93,6 +100,9 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
   a.mNN = T(p->ax[axis].mNN);
   a.slo = T(p->g.robin[2 * axis]);
   a.shi = T(p->g.robin[2 * axis + 1]);
+  a.rnode = robin_nodes<T>(p);
+  a.rlo = (int)face_offset(2 * axis, a.n);
+  a.rhi = (int)face_offset(2 * axis + 1, a.n);
   a.npencils = pencil_count(axis, a.n);
   return dispatch_pass<T>(a, mode, s);
 }

@@ -72,4 +72,12 @@ __host__ __device__ inline int pencil_count(int axis, const int* n) {
   return axis == 2 ? n[0] * n[1] : axis == 1 ? n[0] * n[2] : n[1] * n[2];
 }
 
+// offset of face f's block in the packed face layout (faces x_lo .. z_hi, each
+// indexed like the pencils along its axis)
+__host__ __device__ inline long long face_offset(int f, const int* n) {
+  long long off = 0;
+  for (int q = 0; q < f; ++q) off += pencil_count(q / 2, n);
+  return off;
+}
+
 }  // namespace cheb

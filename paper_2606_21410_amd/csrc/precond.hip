@@ -897,7 +897,7 @@ int precond_setup(cheb_plan* p) {
     for (int b = 0; b < a; ++b)
       if (src[b] == b && p->ax[b].N == p->ax[a].N && p->ax[b].L == p->ax[a].L &&
           p->g.bc[2 * b] == p->g.bc[2 * a] && p->g.bc[2 * b + 1] == p->g.bc[2 * a + 1] &&
-          p->g.robin[2 * b] == p->g.robin[2 * a] && p->g.robin[2 * b + 1] == p->g.robin[2 * a + 1]) {
+          face_sigma(p, 2 * b) == face_sigma(p, 2 * a) && face_sigma(p, 2 * b + 1) == face_sigma(p, 2 * a + 1)) {
         src[a] = b;
         break;
       }
@@ -911,10 +911,10 @@ int precond_setup(cheb_plan* p) {
       th.emplace_back([&, a]() {
         const int m = p->ax[a].N - 1;
         std::vector<double> A;
-        reduced_1d(p->ax[a].N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], p->g.robin[2 * a],
-                   p->g.robin[2 * a + 1], A);
+        reduced_1d(p->ax[a].N, p->ax[a].L, p->g.bc[2 * a], p->g.bc[2 * a + 1], face_sigma(p, 2 * a),
+                   face_sigma(p, 2 * a + 1), A);
         // the same face row at both ends: the 1-D operator is centro-symmetric
-        const bool centro = p->g.bc[2 * a] == p->g.bc[2 * a + 1] && p->g.robin[2 * a] == p->g.robin[2 * a + 1];
+        const bool centro = p->g.bc[2 * a] == p->g.bc[2 * a + 1] && face_sigma(p, 2 * a) == face_sigma(p, 2 * a + 1);
         okv[a] = centro ? eig_centro(m, A, lamv[a], Vv[a], Viv[a])
                                                       : eig_real(m, A, lamv[a], Vv[a]) && invert(m, Vv[a], Viv[a]);
       });
@@ -934,7 +934,7 @@ int precond_setup(cheb_plan* p) {
     // the even-odd contraction needs the centro-symmetric factors and whole
     // 16-row halves
     const int sa = src[a];
-    const bool centro_a = p->g.bc[2 * sa] == p->g.bc[2 * sa + 1] && p->g.robin[2 * sa] == p->g.robin[2 * sa + 1];
+    const bool centro_a = p->g.bc[2 * sa] == p->g.bc[2 * sa + 1] && face_sigma(p, 2 * sa) == face_sigma(p, 2 * sa + 1);
     ax[a].split = centro_a && m <= 128 && ((m + 1) / 2) % 16 == 0 ? 1 : 0;
     ax[a].off_V = off64;
     host.insert(host.end(), V.begin(), V.end());

@@ -98,3 +98,8 @@ def test_apparent_conductivity_rejects_null_plan():
     lib = _lib()
     out = (ctypes.c_double * 3)()
     assert lib.cheb_apparent_conductivity(None, None, None, 0, 1.0, out) == L.CHEB_ERR_INVALID_ARG
+
+
+def test_set_robin_nodes_rejects_null_plan():
+    lib = _lib()
+    assert lib.cheb_plan_set_robin_nodes(None, None) == L.CHEB_ERR_INVALID_ARG
