@@ -410,26 +410,36 @@ def picard_chain_section(dev, levels=(33, 65, 129, 257)):
     return out
 
 
-def thermal_newton_section(dev, levels=(8, 16, 32, 64, 128, 256), tol=1e-11, max_steps=20, maxiter=2000):
+def _thermal_plan(N, dev):
+    """The Section 3.4 problem at N with its flux rows k(T) dT/dn = h on the
+    Neumann faces (per-node Robin rows dT/dn - alpha h T = h), its inputs on the
+    GPU and its plan."""
+    import torch
+    from paper_2606_21410_amd import workloads as W
+    from paper_2606_21410_amd.api import Plan
+    P = W.thermal_nonlinear(N + 1, flux_form=True)
+    plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev, robin=P.grid.robin,
+                robin_nodes=P.grid.robin_nodes)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    return P, plan, t(P.K), t(P.f), t(P.g)
+
+
+def thermal_newton_section(dev, levels=(4, 8, 16, 32, 64, 128, 256), tol=1e-11, max_steps=20, maxiter=2000):
     """Section 3.4 nonlinear thermal problem, k(T) = 1 / (1 + T/2) on (0,1)^3
-    with the analytic T = (exp(Phi/2) - 1) * 2, Phi = sin(pi x) sin(pi y) sin(pi z):
-    Newton-LGMRES (FP64, fast-diagonalisation preconditioner) along the chain
-    N = 8 -> 16 -> ... -> 256 with the modal prolongation as warm start.  Per
+    with the analytic T = (exp(Phi/2) - 1) * 2, Phi = sin(pi x) sin(pi y) sin(pi z),
+    and the flux condition on the Neumann faces: Newton-LGMRES (FP64,
+    fast-diagonalisation preconditioner) along Table 1's chain
+    N = 4 -> 8 -> ... -> 256 with the modal prolongation as warm start.  Per
     level: Newton updates, LGMRES products (total and per update), max error
     against the analytic T, e_ref and the time of prolongation + Newton
     (inputs already on the GPU)."""
     import torch
-    from paper_2606_21410_amd import workloads as W
-    from paper_2606_21410_amd.api import Plan, SolveOptions, prolong
+    from paper_2606_21410_amd.api import SolveOptions, prolong
     opts = SolveOptions(rtol=1e-10, maxiter=maxiter, precond=True)
     out = []
     prev = None
     for N in levels:
-        P = W.thermal_nonlinear(N + 1)
-        K0 = torch.from_numpy(P.K).to(dev)
-        f = torch.from_numpy(P.f).to(dev)
-        g = torch.from_numpy(P.g).to(dev)
-        plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev)
+        P, plan, K0, f, g = _thermal_plan(N, dev)
         plan.ensure_workspace(opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -457,16 +467,11 @@ def thermal_newton_cold(dev, levels=(128, 256), tol=1e-11, max_steps=20, maxiter
     (the refinement chain reaches them with the prolonged solution already at
     the stopping rule)."""
     import torch
-    from paper_2606_21410_amd import workloads as W
-    from paper_2606_21410_amd.api import Plan, SolveOptions
+    from paper_2606_21410_amd.api import SolveOptions
     opts = SolveOptions(rtol=1e-10, maxiter=maxiter, precond=True)
     out = []
     for N in levels:
-        P = W.thermal_nonlinear(N + 1)
-        K0 = torch.from_numpy(P.K).to(dev)
-        f = torch.from_numpy(P.f).to(dev)
-        g = torch.from_numpy(P.g).to(dev)
-        plan = Plan(P.grid.n, P.grid.lo, P.grid.hi, P.grid.bc, "f64", dev)
+        P, plan, K0, f, g = _thermal_plan(N, dev)
         plan.ensure_workspace(opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -682,7 +687,7 @@ def main():
                          "calibration), then the FP64 applies only")
     ap.add_argument("--profile-newton", action="store_true",
                     help="for profiler runs: the Section 3.4 Newton solve from a cold start at N = 128, then "
-                         "the refinement chain N = 8 .. 128")
+                         "the refinement chain N = 4 .. 128 (flux rows on the Neumann faces)")
     ap.add_argument("--profile-precond", action="store_true",
                     help="for profiler runs: the preconditioner applications of the bench's precond section "
                          "only")
@@ -716,19 +721,18 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     if args.profile_newton:
-        T = W.thermal_nonlinear(129)
-        pl = Plan(T.grid.n, T.grid.lo, T.grid.hi, T.grid.bc, "f64", device=dev)
+        T, pl, K0t, ft, gt = _thermal_plan(128, dev)
         opts = SolveOptions(rtol=1e-10, precond=True)
         pl.ensure_workspace(opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        u, info = pl.newton(d(T.K), d(T.f), d(T.g), alpha=T.meta["alpha"], tol=1e-11, max_steps=20, opts=opts)
+        u, info = pl.newton(K0t, ft, gt, alpha=T.meta["alpha"], tol=1e-11, max_steps=20, opts=opts)
         torch.cuda.synchronize()
         cold = {"seconds": round(time.perf_counter() - t0, 4), "newton_steps": info["newton_steps"],
                 "mv_per_step": info["mv_per_step"], "status": info["rc"],
                 "max_error": float((u - d(T.u_exact)).abs().max().item())}
         _log(f"cold Newton N=128: {cold}")
-        chain = thermal_newton_section(dev, levels=(8, 16, 32, 64, 128))
+        chain = thermal_newton_section(dev, levels=(4, 8, 16, 32, 64, 128))
         print(json.dumps({"profile_newton": {"cold_128": cold, "chain": chain}}), flush=True)
         return
 
@@ -908,7 +912,7 @@ def main():
     thermal = None
     thermal_cold = None
     if not args.no_solve and n == 129:
-        _log("nonlinear thermal problem, Newton-LGMRES chain N = 8 .. 256")
+        _log("nonlinear thermal problem (flux rows), Newton-LGMRES chain N = 4 .. 256")
         thermal = thermal_newton_section(dev)
         _log("nonlinear thermal problem, cold-start Newton at N = 128 and 256")
         thermal_cold = thermal_newton_cold(dev)
