@@ -155,11 +155,11 @@ int cheb_plan_set_stream(cheb_plan* plan, void* stream);
  * face f is added to grid.robin[f] at that node.  Entries on Dirichlet faces
  * must be 0.  The library copies the array (device or host memory; the caller
  * keeps ownership) into plan-owned device memory (FP64 and FP32 copies, one
- * packed-face array each) and synchronises the plan's stream.  Every operator,
- * lift, solve, adjoint and Newton call of the plan then uses the node's own
- * row; the reduced operator runs on the FFT route (the lift reads each
- * pencil's coefficients), and the preconditioner, rebuilt on its next use,
- * uses each face's mean coefficient.  NULL removes the per-node part.
+ * packed-face array each, with each pencil's end-block inverse) and
+ * synchronises the plan's stream.  Every operator, lift, solve, adjoint and
+ * Newton call of the plan then uses the node's own row, on either derivative
+ * route; the preconditioner, rebuilt on its next use, uses each face's mean
+ * coefficient.  NULL removes the per-node part.
  * Returns CHEB_ERR_INVALID_ARG for a null plan, a non-finite entry, a nonzero
  * entry on a Dirichlet face, or coefficients that make some pencil's
  * end-value elimination block singular (the plan is then unchanged), and

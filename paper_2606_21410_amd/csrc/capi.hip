@@ -356,12 +356,36 @@ int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces) {
       }
     }
   }
-  std::vector<float> h32(cnt);
-  for (size_t i = 0; i < cnt; ++i) h32[i] = float(h[i]);
+  // each pencil's end-block inverse, for the matrix-core pass (the FFT route
+  // and the lifts solve the block from the coefficients themselves)
+  h.resize(3 * cnt, 0.0);
+  for (int a = 0; a < 3; ++a) {
+    const AxisConst& c = plan->ax[a];
+    const bool nlo = plan->g.bc[2 * a] == CHEB_NEUMANN, nhi = plan->g.bc[2 * a + 1] == CHEB_NEUMANN;
+    const long long olo = face_offset(2 * a, n), ohi = face_offset(2 * a + 1, n);
+    double* e = h.data() + robin_inv_offset(plan, a);
+    for (int p = 0; p < pencil_count(a, n); ++p, e += 4) {
+      const double m00 = c.m00 - h[olo + p], mNN = c.mNN + h[ohi + p];
+      if (nlo && nhi) {
+        const double det = m00 * mNN - c.m0N * c.mN0;
+        e[0] = mNN / det;
+        e[1] = -c.m0N / det;
+        e[2] = -c.mN0 / det;
+        e[3] = m00 / det;
+      } else if (nlo) {
+        e[0] = 1.0 / m00;
+      } else if (nhi) {
+        e[3] = 1.0 / mNN;
+      }
+    }
+  }
+  const size_t tot = 3 * cnt;
+  std::vector<float> h32(tot);
+  for (size_t i = 0; i < tot; ++i) h32[i] = float(h[i]);
   rc = CHEB_OK;
   if (!plan->rn64) {
-    rc = hip_check(hipMalloc((void**)&plan->rn64, cnt * sizeof(double)), "hipMalloc(Robin coefficients)");
-    if (!rc) rc = hip_check(hipMalloc((void**)&plan->rn32, cnt * sizeof(float)), "hipMalloc(Robin coefficients)");
+    rc = hip_check(hipMalloc((void**)&plan->rn64, tot * sizeof(double)), "hipMalloc(Robin coefficients)");
+    if (!rc) rc = hip_check(hipMalloc((void**)&plan->rn32, tot * sizeof(float)), "hipMalloc(Robin coefficients)");
     if (rc) {
       if (plan->rn64) (void)hipFree(plan->rn64);
       plan->rn64 = nullptr;
@@ -369,10 +393,10 @@ int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces) {
       return rc;
     }
   }
-  rc = hip_check(hipMemcpyAsync(plan->rn64, h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, plan->stream),
+  rc = hip_check(hipMemcpyAsync(plan->rn64, h.data(), tot * sizeof(double), hipMemcpyHostToDevice, plan->stream),
                  "hipMemcpyAsync(Robin coefficients)");
   if (!rc)
-    rc = hip_check(hipMemcpyAsync(plan->rn32, h32.data(), cnt * sizeof(float), hipMemcpyHostToDevice, plan->stream),
+    rc = hip_check(hipMemcpyAsync(plan->rn32, h32.data(), tot * sizeof(float), hipMemcpyHostToDevice, plan->stream),
                    "hipMemcpyAsync(Robin coefficients)");
   if (!rc) rc = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
   if (rc) return rc;

@@ -36,24 +36,42 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
   return hip_check(hipGetLastError(), "matrix-core pass launch");
 }
 
-template <typename T, int NC, int V, bool CG>
+template <typename T, int NC, int V, bool CG, bool RN>
 static int launch_dense_c(const DenseArgs<T>& a, int transpose, hipStream_t s) {
+  constexpr int MR = DENSE_REDUCED | (RN ? DENSE_NODE : 0), MT = DENSE_TRANSPOSE | (RN ? DENSE_NODE : 0);
   if (a.first)
-    return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, true, V, CG>(a, s)
-                     : launch_dense_inst<T, NC, DENSE_REDUCED, true, V, CG>(a, s);
-  return transpose ? launch_dense_inst<T, NC, DENSE_TRANSPOSE, false, V, CG>(a, s)
-                   : launch_dense_inst<T, NC, DENSE_REDUCED, false, V, CG>(a, s);
+    return transpose ? launch_dense_inst<T, NC, MT, true, V, CG>(a, s) : launch_dense_inst<T, NC, MR, true, V, CG>(a, s);
+  return transpose ? launch_dense_inst<T, NC, MT, false, V, CG>(a, s) : launch_dense_inst<T, NC, MR, false, V, CG>(a, s);
 }
 
-template <typename T, int NC, int V>
+template <typename T, int NC, int V, bool RN>
 static int launch_dense_v(const DenseArgs<T>& a, int transpose, hipStream_t s) {
-  return a.axis == 2 ? launch_dense_c<T, NC, V, true>(a, transpose, s) : launch_dense_c<T, NC, V, false>(a, transpose, s);
+  return a.axis == 2 ? launch_dense_c<T, NC, V, true, RN>(a, transpose, s)
+                     : launch_dense_c<T, NC, V, false, RN>(a, transpose, s);
 }
 
-template <typename T, int NC>
+template <typename T, int NC, bool RN>
 static int launch_dense_n(const DenseArgs<T>& a, int transpose, int variant, hipStream_t s) {
-  return variant == 1 ? launch_dense_v<T, NC, 1>(a, transpose, s) : launch_dense_v<T, NC, 0>(a, transpose, s);
+  return variant == 1 ? launch_dense_v<T, NC, 1, RN>(a, transpose, s) : launch_dense_v<T, NC, 0, RN>(a, transpose, s);
 }
+
+// every N and tile shape of the pass, with (RN) or without per-node Robin
+// inverses; the two sets are instantiated in separate files (dense_f64.hip /
+// dense_f64_rn.hip and the FP32 pair) so that they compile in parallel
+template <typename T, bool RN>
+int launch_dense_rn(const DenseArgs<T>& a, int N, int transpose, int variant, hipStream_t s) {
+  switch (N) {
+    case 16: return launch_dense_n<T, 16, RN>(a, transpose, variant, s);
+    case 32: return launch_dense_n<T, 32, RN>(a, transpose, variant, s);
+    case 48: return launch_dense_n<T, 48, RN>(a, transpose, variant, s);
+    case 64: return launch_dense_n<T, 64, RN>(a, transpose, variant, s);
+    case 96: return launch_dense_n<T, 96, RN>(a, transpose, variant, s);
+    case 128: return launch_dense_n<T, 128, RN>(a, transpose, variant, s);
+    default: set_error("matrix-core pass: unsupported N"); return CHEB_ERR_UNSUPPORTED;
+  }
+}
+extern template int launch_dense_rn<double, true>(const DenseArgs<double>&, int, int, int, hipStream_t);
+extern template int launch_dense_rn<float, true>(const DenseArgs<float>&, int, int, int, hipStream_t);
 
 template <typename T>
 static const T* dense_tab(const cheb_plan* p, int axis, int transpose);
@@ -103,16 +121,14 @@ static int launch_dense_common(const cheb_plan* p, int axis, int transpose, int 
     a.r00 = T(m00 != 0.0 ? 1.0 / m00 : 0.0);
     a.rNN = T(mNN != 0.0 ? 1.0 / mNN : 0.0);
   }
-  const int variant = p->dense_var[axis][sizeof(T) == sizeof(double) ? 0 : 1];
-  switch (p->ax[axis].N) {
-    case 16: return launch_dense_n<T, 16>(a, transpose, variant, s);
-    case 32: return launch_dense_n<T, 32>(a, transpose, variant, s);
-    case 48: return launch_dense_n<T, 48>(a, transpose, variant, s);
-    case 64: return launch_dense_n<T, 64>(a, transpose, variant, s);
-    case 96: return launch_dense_n<T, 96>(a, transpose, variant, s);
-    case 128: return launch_dense_n<T, 128>(a, transpose, variant, s);
-    default: set_error("matrix-core pass: unsupported N"); return CHEB_ERR_UNSUPPORTED;
+  a.rinv = nullptr;
+  if (!sys && p->rn64) {
+    if (sizeof(T) == sizeof(double)) a.rinv = (const T*)(p->rn64 + robin_inv_offset(p, axis));
+    else a.rinv = (const T*)(p->rn32 + robin_inv_offset(p, axis));
   }
+  const int variant = p->dense_var[axis][sizeof(T) == sizeof(double) ? 0 : 1];
+  return a.rinv ? launch_dense_rn<T, true>(a, p->ax[axis].N, transpose, variant, s)
+                : launch_dense_rn<T, false>(a, p->ax[axis].N, transpose, variant, s);
 }
 
 template <typename T>

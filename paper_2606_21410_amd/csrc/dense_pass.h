@@ -30,7 +30,9 @@
 
 namespace cheb {
 
-enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1 };
+// DENSE_NODE is or-ed into either mode when the plan has per-node Robin
+// coefficients: the lift then reads each pencil's own end-block inverse
+enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1, DENSE_NODE = 2 };
 
 // element i of a system's field at base (uniform): a system's field stays
 // below 4 GiB (at most 129^3 nodes per axis triple), so the byte offset fits
@@ -169,6 +171,11 @@ struct DenseArgs {
   // the face rows' 2 x 2 matrix M = [m00 m0N; mN0 mNN] of the lift: the
   // entries of M^{-1} (both ends Neumann) and 1 / m00, 1 / mNN (one end)
   T i00, i0N, iN0, iNN, r00, rNN;
+  // per-node Robin coefficients (modes with DENSE_NODE): each pencil's own
+  // inverse, 4 entries per pencil of the axis (face numbering), laid out as
+  // i00, i0N, iN0, iNN with 1 / m00 or 1 / mNN in place of the inverse when
+  // one end is Dirichlet; null otherwise (always for batches)
+  const T* rinv;
 };
 
 // tile element e -> (node j along the pencil, column c): pencil-contiguous for
@@ -226,6 +233,13 @@ struct DenseArgs {
     }                                                                              \
   } while (0)
 
+// face numbering of column c of tile t (the pencil's index among all pencils
+// along the axis, which indexes the packed face arrays); 0 past the last pencil
+__device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, int nbi) {
+  const int q = (t % tps) * C + c;
+  return q < npen ? (1 + q / nbi) * (nbi + 2) + 1 + q % nbi : 0;
+}
+
 // end values of the homogeneous lift (Section 2.3.1) of each column: the
 // first product's rows 0 and N are the face-row dot products s0 = D[0][:] u and
 // sN = D[N][:] u of the interior values, and [u0, uN] solves the face rows'
@@ -236,7 +250,11 @@ struct DenseArgs {
     if (mt == 0 && lk == 0) {                                               \
       const T s0_ = ACCO[0] + ACCE[0], sN_ = ACCO[0] - ACCE[0];             \
       T u0 = T(0), uN = T(0);                                               \
-      if (nlo && nhi) {                                                     \
+      if (RN) {                                                             \
+        const T* e_ = a.rinv + 4 * dense_face_index(tile, col, C, tps, npen, nbi); \
+        u0 = -(e_[0] * s0_ + e_[1] * sN_);                                  \
+        uN = -(e_[2] * s0_ + e_[3] * sN_);                                  \
+      } else if (nlo && nhi) {                                              \
         u0 = -(a.i00 * s0_ + a.i0N * sN_);                                  \
         uN = -(a.iN0 * s0_ + a.iNN * sN_);                                  \
       } else if (nlo) {                                                     \
@@ -365,6 +383,8 @@ struct DenseArgs {
 template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(DenseArgs<T> a) {
   if (a.gate && !*a.gate) return;
+  constexpr int BASE = MODE & 1;                   // DENSE_REDUCED or DENSE_TRANSPOSE
+  constexpr bool RN = (MODE & DENSE_NODE) != 0;    // per-pencil end-block inverses
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int N = NC, n = NC + 1;
   constexpr int NT = 64 * S.NW;
@@ -577,9 +597,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
 #pragma unroll
     for (int ks = S.KE4; ks < (PREF ? NL : 0); ++ks) DENSE_PREF1(ks);
     DENSE_VDOT(midv);
-    if (MODE == DENSE_REDUCED) DENSE_LIFTVALS(acco, acce);
+    if (BASE == DENSE_REDUCED) DENSE_LIFTVALS(acco, acce);
     lds_barrier();
-    DENSE_EPI(acco, acce, midv, true, MODE == DENSE_REDUCED);
+    DENSE_EPI(acco, acce, midv, true, BASE == DENSE_REDUCED);
     lds_barrier();
 
     // divergence part
@@ -591,12 +611,16 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_EPI(acco, acce, midv, false, false);  // into the K tile: no barrier needed before it
     lds_barrier();
 
-    if (MODE == DENSE_TRANSPOSE) {
+    if (BASE == DENSE_TRANSPOSE) {
       // transposed lift: mu = M^{-T} [z_0, z_N]; interior -= mu0 D[0][:] + muN D[N][:]
       if (tid < C) {
         const T z0 = Kt[tid], zN = Kt[N * SC + tid];
         T mu0 = T(0), muN = T(0);
-        if (nlo && nhi) {
+        if (RN) {
+          const T* e = a.rinv + 4 * dense_face_index(tile, tid, C, tps, npen, nbi);
+          mu0 = e[0] * z0 + e[2] * zN;
+          muN = e[1] * z0 + e[3] * zN;
+        } else if (nlo && nhi) {
           mu0 = a.i00 * z0 + a.iN0 * zN;
           muN = a.i0N * z0 + a.iNN * zN;
         } else if (nlo) {
@@ -626,7 +650,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         const bool ok = b >= 0 && tid + q * NT < TOT;
         const bool in = j != 0 && j != N;
         T x = Kt[j * SC + c];
-        if (MODE == DENSE_TRANSPOSE && (nlo || nhi)) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
+        if (BASE == DENSE_TRANSPOSE && (nlo || nhi)) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
         if (!FIRST) x += yreg[q];
         ov[q] = in ? x : T(0);
         op[q] = ok ? (unsigned)(b + j * stride) : 0u;

@@ -10,6 +10,7 @@
 
 #include "../../include/cheb.h"
 #include "../../include/cheb_debug.h"
+#include "pencil.h"
 
 namespace cheb {
 
@@ -77,8 +78,9 @@ struct cheb_plan {
   double* dd64;
   float* dd32;
   // per-node Robin coefficients (cheb_plan_set_robin_nodes): packed faces in the
-  // layout of g_faces, added to the grid's per-face coefficients; FP64 and FP32
-  // copies, null when unset.  rn_mean: their face means.
+  // layout of g_faces, added to the grid's per-face coefficients, followed by
+  // each axis' per-pencil end-block inverses (robin_inv_offset); FP64 and FP32
+  // copies, null when unset.  rn_mean: the coefficients' face means.
   double* rn64;
   float* rn32;
   double rn_mean[6];
@@ -119,10 +121,16 @@ template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
                       hipStream_t s);
 // pi: 0 for the FP64 passes, 1 for the FP32 passes
-// (per-node Robin coefficients run on the FFT route, whose lift reads them per pencil)
 inline bool use_dense(const cheb_plan* p, int axis, int pi) {
-  if (!p->dd_ok[axis] || p->route == CHEB_ROUTE_FFT || p->rn64) return false;
+  if (!p->dd_ok[axis] || p->route == CHEB_ROUTE_FFT) return false;
   return p->route == CHEB_ROUTE_MATRIX || !p->auto_fft[pi];
+}
+
+// offset (entries) in rn64 / rn32 of axis a's per-pencil end-block inverses:
+// 4 per pencil (i00, i0N, iN0, iNN of M^{-1}; 1 / m00 or 1 / mNN alone when the
+// other end is Dirichlet), pencils in face numbering
+inline size_t robin_inv_offset(const cheb_plan* p, int a) {
+  return (size_t)face_offset(6, p->g.n) + 2 * (size_t)face_offset(2 * a, p->g.n);
 }
 
 // Robin coefficient of face f for the constant-coefficient preconditioner: the

@@ -24,22 +24,25 @@ CASES = {
 SIZES = [(5, 4, 3), (17, 17, 17), (33, 17, 9), (13, 6, 65), (65, 65, 65), (129, 129, 129)]
 
 
-def _setup(n, name, prec, seed, lo=0.2, hi=2.0):
+def _setup(n, name, prec, seed, lo=0.2, hi=2.0, route="auto"):
     from paper_2606_21410_amd.api import Plan
     bc, robin = CASES[name]
     rn = W.random_robin_nodes(W.Grid(n, LO, HI, bc), seed, lo, hi)
-    plan = Plan(n, LO, HI, bc, prec, robin=robin, robin_nodes=rn)
+    plan = Plan(n, LO, HI, bc, prec, route=route, robin=robin, robin_nodes=rn)
     return plan, O.Grid3(n, LO, HI, bc, robin, rn)
 
 
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("name", list(CASES))
-def test_apply_full_reduced_transpose_f64(n, name):
+@pytest.mark.parametrize("route", ["fft", "matrix"])
+def test_apply_full_reduced_transpose_f64(n, name, route):
+    """Both derivative routes: the FFT route's lift solves each pencil's block
+    from its coefficients, the matrix-core pass reads the pencil's inverse."""
     require_gpu()
     import torch
     d = lambda a: to_dev(a, torch.float64)
-    log(f"node robin apply n={n} {name}")
-    plan, G = _setup(n, name, "f64", 500, -0.5, 2.0)
+    log(f"node robin apply n={n} {name} {route}")
+    plan, G = _setup(n, name, "f64", 500, -0.5, 2.0, route)
     u = W.random_field(n, 501)
     K = W.random_conductivity(n, 502, 0.5)
     for mode, fn in (("full", O.apply_full), ("reduced", O.apply_reduced),
@@ -50,11 +53,12 @@ def test_apply_full_reduced_transpose_f64(n, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_apply_f32(name):
+@pytest.mark.parametrize("route", ["fft", "matrix"])
+def test_apply_f32(name, route):
     require_gpu()
     import torch
     n = (33, 17, 9)
-    plan, G = _setup(n, name, "f32", 510)
+    plan, G = _setup(n, name, "f32", 510, route=route)
     u = W.random_field(n, 511).astype(np.float32).astype(np.float64)
     K = W.random_conductivity(n, 512, 0.5).astype(np.float32).astype(np.float64)
     for mode, fn in (("full", O.apply_full), ("reduced", O.apply_reduced)):
@@ -75,7 +79,7 @@ def test_constant_nodes_equal_face_coefficients_and_clearing():
     extra = (0.3, 0.0, 1.1, 0.7, 0.0, 2.0)
     rn = W.pack_faces([np.full(grid.face_shape(f), extra[f]) for f in range(6)])
     face = Plan(n, LO, HI, bc, "f64", route="fft", robin=tuple(r + e for r, e in zip(robin, extra)))
-    node = Plan(n, LO, HI, bc, "f64", robin=robin, robin_nodes=rn)
+    node = Plan(n, LO, HI, bc, "f64", route="fft", robin=robin, robin_nodes=rn)
     plain = Plan(n, LO, HI, bc, "f64", robin=robin)
     u = d(W.random_field(n, 520))
     K = d(W.random_conductivity(n, 521, 0.5))
@@ -83,6 +87,7 @@ def test_constant_nodes_equal_face_coefficients_and_clearing():
         a, b = to_host(face.apply(K, u, mode=mode)), to_host(node.apply(K, u, mode=mode))
         assert rel_l2(b, a) <= 1e-13, mode
     node.set_robin_nodes(None)
+    node.set_route("auto")
     for mode in ("full", "reduced"):
         assert rel_l2(to_host(node.apply(K, u, mode=mode)), to_host(plain.apply(K, u, mode=mode))) <= 1e-13
 
