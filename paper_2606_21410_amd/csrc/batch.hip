@@ -37,6 +37,7 @@ struct ApplyGroup {
   float tuned_us[2][2] = {{-1.f, -1.f}, {-1.f, -1.f}};  // its timings per shape
   std::vector<int> members;   // system ids
   DenseSys* dsys = nullptr;   // device table, one entry per member
+  std::vector<DenseSys> htab; // its host copy
   int* dact = nullptr;        // device list of active member indices
   std::vector<int> hact;      // host copy of the active list last uploaded
 };
@@ -58,6 +59,10 @@ struct cheb_batch {
   hipStream_t stream;
   std::vector<cheb_plan*> plans;
   std::vector<size_t> off, npts;
+  // offset of each system's conductivity in the packed K: its own field's
+  // offset, or that of the first system given the same K pointer and grid
+  // size, which then holds the one packed copy (set per solve)
+  std::vector<size_t> koff;
   size_t P;  // packed length in elements
   std::vector<cheb::ApplyGroup> groups;
   std::vector<cheb::PrecGroup> pgroups;
@@ -424,7 +429,7 @@ int bapply(cheb_batch* B, const T* K, const T* x, T* y) {
       for (int k : g.hact) {
         const int s = g.members[k];
         const size_t o = B->off[s];
-        int rc = apply_t<T>(B->plans[s], K + o, x + o, y + o, 1, B->stream);
+        int rc = apply_t<T>(B->plans[s], K + B->koff[s], x + o, y + o, 1, B->stream);
         if (rc) return rc;
       }
     }
@@ -820,9 +825,11 @@ int cheb_batch_create(const cheb_grid* grids, int32_t nprob, int32_t precision, 
     std::vector<DenseSys> tab(nm);
     for (size_t k = 0; k < nm; ++k) {
       tab[k].off = (long long)B->off[g.members[k]];
+      tab[k].koff = tab[k].off;
       tab[k].bcmask = bc_mask(grids[g.members[k]].bc);
       tab[k].pad_ = 0;
     }
+    g.htab = tab;
     if (!rc) rc = hip_check(hipMalloc((void**)&g.dsys, nm * sizeof(DenseSys)), "hipMalloc(batch table)");
     if (!rc) rc = hip_check(hipMalloc((void**)&g.dact, nm * sizeof(int)), "hipMalloc(batch table)");
     if (!rc) rc = hip_check(hipMemcpy(g.dsys, tab.data(), nm * sizeof(DenseSys), hipMemcpyHostToDevice), "hipMemcpy");
@@ -957,11 +964,35 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
   rc = fill<double>(w.K64, 1.0, round_up(B->P, 64), st);
   if (!rc) rc = fill<double>(w.bt, 0.0, round_up(B->P, 64), st);
   if (!rc) rc = fill<double>(w.x, 0.0, round_up(B->P, 64), st);
+  // systems given the same K (and grid size) share one packed copy, so a
+  // batched pass over them reads the same conductivity lines
+  B->koff.assign(ns, 0);
+  for (int s = 0; s < ns; ++s) {
+    B->koff[s] = B->off[s];
+    for (int q = 0; q < s; ++q)
+      if (K[q] == K[s] && B->npts[q] == B->npts[s] && B->koff[q] == B->off[q]) {
+        B->koff[s] = B->off[q];
+        break;
+      }
+  }
+  for (auto& g : B->groups) {
+    bool changed = false;
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      const long long ko = (long long)B->koff[g.members[k]];
+      changed = changed || g.htab[k].koff != ko;
+      g.htab[k].koff = ko;
+    }
+    if (changed && g.dsys)
+      rc = hip_check(hipMemcpyAsync(g.dsys, g.htab.data(), g.htab.size() * sizeof(DenseSys), hipMemcpyHostToDevice, st),
+                     "hipMemcpyAsync(batch table)");
+    if (!rc) rc = bsync(B);  // the host table is pageable: the copy completes before it changes
+    if (rc) return rc;
+  }
   for (int s = 0; s < ns && !rc; ++s) {
     cheb_plan* p = B->plans[s];
     const size_t o = B->off[s];
     const double* Ks = (const double*)K[s];
-    rc = copy_scale<double>(w.K64 + o, Ks, 1.0, p->npts, st);
+    if (B->koff[s] == o) rc = copy_scale<double>(w.K64 + o, Ks, 1.0, p->npts, st);
     if (!rc) rc = fill<double>(w.t1 + o, 0.0, p->npts, st);
     if (!rc) rc = lift_full<double>(p, w.t1 + o, (const double*)g_faces[s], st);
     if (!rc) rc = apply_t<double>(p, Ks, w.t1 + o, w.bt + o, 0, st);

@@ -130,9 +130,12 @@ __host__ __device__ constexpr int dense_lds_bytes(int N, int V) {
 }
 
 // one system of a batched pass (same N, box and tile shape as the others): its
-// offset in the packed fields and its face types
+// offset in the packed fields, the offset of its conductivity in the packed K
+// (systems given the same K, e.g. the load cases of one microstructure, share
+// one copy) and its face types
 struct DenseSys {
   long long off;
+  long long koff;
   int bcmask;
   int pad_;
 };
@@ -149,6 +152,7 @@ __device__ inline DenseSys dense_sys_at(const DenseArgs<T>& a, int i) {
   const DenseSys* e = a.sys + ((ci4*)a.act)[i];
   DenseSys s;
   s.off = *(cl4*)&e->off;
+  s.koff = *(cl4*)&e->koff;
   s.bcmask = *(ci4*)&e->bcmask;
   s.pad_ = 0;
   return s;
@@ -365,7 +369,7 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
     if (a.sys) {                                          \
       const DenseSys s_ = dense_sys_at(a, (TILE) / tps);  \
       PU = a.u + s_.off;                                  \
-      PK = a.K + s_.off;                                  \
+      PK = a.K + s_.koff;                                 \
       PY = a.y + s_.off;                                  \
       BM = s_.bcmask;                                     \
     } else {                                              \

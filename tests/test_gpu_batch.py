@@ -63,6 +63,37 @@ def test_batch_matches_single_solves_f64():
 
 
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_shared_K_equals_separate_copies(prec):
+    """The three load cases of a microstructure given one K tensor share one
+    packed copy (their tiles read the same conductivity lines); the results,
+    statuses and matvec counts are those of the same batch given three
+    separate copies of K, bit for bit (matrix-core groups 17^3 and 33^3 and
+    the FFT-route 25^3)."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Batch, SolveOptions
+    d = lambda a: to_dev(a, torch.float64)
+    systems = _systems([17, 25, 33], 7)
+    opts = SolveOptions(rtol=1e-10, maxiter=4000, precond=True)
+    grids = [(n, BOX[0], BOX[1], bc) for n, bc, _, _, _ in systems]
+    Ks_shared = []
+    for i in range(0, len(systems), 3):
+        Kt = d(systems[i][2])
+        Ks_shared += [Kt, Kt, Kt]
+    Ks_sep = [d(s[2]) for s in systems]
+    fs = [d(s[3]) for s in systems]
+    gs = [d(s[4]) for s in systems]
+    B = Batch(grids, prec)
+    u1, i1 = B.solve(Ks_shared, fs, gs, opts=opts)
+    u2, i2 = B.solve(Ks_sep, fs, gs, opts=opts)
+    u3, i3 = B.solve(Ks_shared, fs, gs, opts=opts)
+    for a, b, c, ia, ib, ic in zip(u1, u2, u3, i1, i2, i3):
+        assert ia["status"] == 0 and ia["matvecs"] == ib["matvecs"] == ic["matvecs"]
+        np.testing.assert_array_equal(to_host(a), to_host(b))
+        np.testing.assert_array_equal(to_host(a), to_host(c))
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
 def test_batch_precond_vs_oracle(prec):
     """Preconditioned batched solves (FP64, and FP32 inner / FP64 refinement)
     reach the oracle's exact solutions to 1e-8."""
