@@ -532,13 +532,16 @@ def solve_1d(K, f, g, lo=-1.0, hi=1.0, bc=(L.CHEB_DIRICHLET,) * 2, precision="f6
 
 
 def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", opts=None, device="cuda",
-               details=None):
+               details=None, batch=None):
     """Apparent conductivity tensors of several microstructures (Section 3.3):
     three load cases per microstructure (unit mean gradient along x, y, z
     through Dirichlet faces, zero flux elsewhere) solved together in one batch,
     then K_app[b][a] = <K du^(a)/dx_b>_CC / G_a with Clenshaw-Curtis volume
     averages (cheb_apparent_conductivity).  Returns (list of 3x3 nested lists, per-system infos, solutions);
-    a dict passed as `details` receives the batch's tuned tile shapes."""
+    a dict passed as `details` receives the batch's tuned tile shapes and the
+    batch itself ("batch"), which a later call on microstructures of the same
+    sizes may pass back as `batch` to skip its set-up (plans, preconditioner
+    factors, tile-shape tuning)."""
     grids, KK, ff, gg = [], [], [], []
     for K in Ks:
         n = tuple(K.shape)
@@ -548,9 +551,11 @@ def homogenize(Ks, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), precision="mixed", op
             KK.append(K)
             ff.append(torch.zeros(n, dtype=torch.float64, device=device))
             gg.append(g)
-    batch = Batch(grids, precision, device)
+    if batch is None:
+        batch = Batch(grids, precision, device)
     us, infos = batch.solve(KK, ff, gg, opts=opts)
     if details is not None:
+        details["batch"] = batch
         details["tile_shapes_f64"] = batch.tile_shapes("f64")
         if precision == "mixed":
             details["tile_shapes_f32"] = batch.tile_shapes("f32")

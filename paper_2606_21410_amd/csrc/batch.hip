@@ -29,6 +29,7 @@ namespace {
 constexpr int kChunk = 8192;  // elements per block of the segmented vector kernels
 constexpr int kBT = 256;
 constexpr int kMaxCoef = 80;  // per-system coefficient slots (m + k + 2 <= 72)
+constexpr int kSide = 3;      // side streams the preconditioner groups run on
 
 struct ApplyGroup {
   int rep;                    // system whose plan supplies N, box and tables
@@ -45,6 +46,7 @@ struct ApplyGroup {
 struct PrecGroup {
   int rep;
   std::vector<int> members;
+  size_t pack_off = 0;         // its region of the packed preconditioner scratch
   long long* doffs = nullptr;  // device: packed offsets of the active members
   int* dsys = nullptr;         // device: their system ids
   std::vector<int> hact;
@@ -84,6 +86,12 @@ struct cheb_batch {
   double* hpin;   // pinned host staging: nprob x (kMaxCoef + 8) x 2 doubles
   void* ws;
   size_t ws_bytes;
+  // the preconditioner groups are independent: they run on side streams
+  // (default priority) forked from and joined to `stream` by events, so one
+  // group's small contractions fill the dispatch gaps of another's
+  hipStream_t side[cheb::kSide];
+  hipEvent_t ev_fork, ev_join[cheb::kSide];
+  int side_ok;
 };
 
 namespace cheb {
@@ -413,39 +421,76 @@ int set_active(cheb_batch* B, const std::vector<char>& on) {
   return CHEB_OK;
 }
 
-// y = A x for the active systems (reduced operator, packed fields)
+// fork: the side streams wait for the work enqueued so far on the batch's
+// stream; join: the batch's stream waits for what the first `used` side
+// streams were given
+int side_fork(cheb_batch* B) {
+  int rc = hip_check(hipEventRecord(B->ev_fork, B->stream), "hipEventRecord");
+  for (int k = 0; k < kSide && !rc; ++k) rc = hip_check(hipStreamWaitEvent(B->side[k], B->ev_fork, 0), "hipStreamWaitEvent");
+  return rc;
+}
+int side_join(cheb_batch* B, int used) {
+  int rc = CHEB_OK;
+  for (int k = 0; k < kSide && k < used && !rc; ++k) {
+    rc = hip_check(hipEventRecord(B->ev_join[k], B->side[k]), "hipEventRecord");
+    if (!rc) rc = hip_check(hipStreamWaitEvent(B->stream, B->ev_join[k], 0), "hipStreamWaitEvent");
+  }
+  return rc;
+}
+
+// y = A x for the active systems (reduced operator, packed fields); the
+// groups are independent and run on the side streams
 template <typename T>
 int bapply(cheb_batch* B, const T* K, const T* x, T* y) {
+  int nact = 0;
+  for (auto& g : B->groups) nact += g.hact.empty() ? 0 : 1;
+  const bool fork = B->side_ok && nact > 1;
+  int rc = fork ? side_fork(B) : CHEB_OK;
+  int i = 0;
   for (auto& g : B->groups) {
+    if (rc) return rc;
     if (g.hact.empty()) continue;
+    hipStream_t st = fork ? B->side[i % kSide] : B->stream;
+    ++i;
     const cheb_plan* rep = B->plans[g.rep];
     if (g.dense) {
-      for (int pass = 0; pass < 3; ++pass) {
+      for (int pass = 0; pass < 3 && !rc; ++pass) {
         const int axis = 2 - pass;
-        int rc = launch_dense_batch<T>(rep, axis, pass == 0, K, x, y, g.dsys, g.dact, (int)g.hact.size(), B->stream);
-        if (rc) return rc;
+        rc = launch_dense_batch<T>(rep, axis, pass == 0, K, x, y, g.dsys, g.dact, (int)g.hact.size(), st);
       }
     } else {
       for (int k : g.hact) {
         const int s = g.members[k];
         const size_t o = B->off[s];
-        int rc = apply_t<T>(B->plans[s], K + B->koff[s], x + o, y + o, 1, B->stream);
+        rc = apply_t<T>(B->plans[s], K + B->koff[s], x + o, y + o, 1, st);
         if (rc) return rc;
       }
     }
   }
-  return CHEB_OK;
+  if (!rc && fork) rc = side_join(B, i);
+  return rc;
 }
 
+// each group packs its members' interiors into its own region of pa / pb, so
+// the groups can run concurrently on the side streams
 template <typename T>
 int bprec(cheb_batch* B, const T* in, T* out, T* pa, T* pb) {
+  int nact = 0;
+  for (auto& g : B->pgroups) nact += g.hact.empty() ? 0 : 1;
+  const bool fork = B->side_ok && nact > 1;
+  int rc = fork ? side_fork(B) : CHEB_OK;
+  if (rc) return rc;
+  int i = 0;
   for (auto& g : B->pgroups) {
     if (g.hact.empty()) continue;
-    int rc = precond_apply_batch<T>(B->plans[g.rep], in, out, g.doffs, g.dsys, B->dkc, (int)g.hact.size(), B->P,
-                                    pa, pb, B->stream);
+    hipStream_t st = fork ? B->side[i % kSide] : B->stream;
+    ++i;
+    rc = precond_apply_batch<T>(B->plans[g.rep], in, out, g.doffs, g.dsys, B->dkc, (int)g.hact.size(), B->P,
+                                pa + g.pack_off, pb + g.pack_off, st);
     if (rc) return rc;
   }
-  return CHEB_OK;
+  if (fork) rc = side_join(B, i);
+  return rc;
 }
 
 // Autotuner of the batched operator: for every matrix-core size group not yet
@@ -767,6 +812,7 @@ int cheb_batch_create(const cheb_grid* grids, int32_t nprob, int32_t precision, 
   B->stream = (hipStream_t)stream;
   B->ws = nullptr;
   B->ws_bytes = 0;
+  B->side_ok = 0;
   int rc = CHEB_OK;
   auto fail = [&](int code) {
     cheb_batch_destroy(B);
@@ -834,10 +880,38 @@ int cheb_batch_create(const cheb_grid* grids, int32_t nprob, int32_t precision, 
     if (!rc) rc = hip_check(hipMalloc((void**)&g.dact, nm * sizeof(int)), "hipMalloc(batch table)");
     if (!rc) rc = hip_check(hipMemcpy(g.dsys, tab.data(), nm * sizeof(DenseSys), hipMemcpyHostToDevice), "hipMemcpy");
   }
+  size_t pack = 0;
   for (auto& g : B->pgroups) {
     const size_t nm = g.members.size();
     if (!rc) rc = hip_check(hipMalloc((void**)&g.doffs, nm * sizeof(long long)), "hipMalloc(batch table)");
     if (!rc) rc = hip_check(hipMalloc((void**)&g.dsys, nm * sizeof(int)), "hipMalloc(batch table)");
+    // room for every member's packed interior; the regions add up to at most P
+    const cheb_grid& gr = grids[g.rep];
+    g.pack_off = pack;
+    pack += round_up((size_t)(gr.n[0] - 2) * (gr.n[1] - 2) * (gr.n[2] - 2) * nm, 64);
+  }
+  // side streams and their fork / join events (without them the groups run in
+  // order on the batch's stream)
+  {
+    int made = 0;
+    bool ok = hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (; ok && made < kSide; ++made) {
+      if (hipStreamCreateWithFlags(&B->side[made], hipStreamNonBlocking) != hipSuccess) break;
+      if (hipEventCreateWithFlags(&B->ev_join[made], hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(B->side[made]);
+        break;
+      }
+    }
+    if (ok && made == kSide) {
+      B->side_ok = 1;
+    } else {
+      for (int k = 0; k < made; ++k) {
+        (void)hipStreamDestroy(B->side[k]);
+        (void)hipEventDestroy(B->ev_join[k]);
+      }
+      if (ok) (void)hipEventDestroy(B->ev_fork);
+      (void)hipGetLastError();
+    }
   }
   // chunk table of the segmented kernels
   std::vector<int> chs, chl, c0(nprob), nc(nprob);
@@ -1005,10 +1079,11 @@ int cheb_batch_solve(cheb_batch* batch, const void* const* K, const void* const*
   if (rc) return rc;
   if (bp.precond) {
     std::vector<double> kc(ns);
-    for (int s = 0; s < ns && !rc; ++s) {
-      rc = precond_setup(B->plans[s]);
-      if (!rc) rc = vsum<double>((const double*)K[s], B->npts[s], w.sc.partials, w.sc.dots + s, st);
-    }
+    // a group's batched contractions read only its representative's factors
+    for (const auto& g : B->pgroups)
+      if (!rc) rc = precond_setup(B->plans[g.rep]);
+    for (int s = 0; s < ns && !rc; ++s)
+      rc = vsum<double>((const double*)K[s], B->npts[s], w.sc.partials, w.sc.dots + s, st);
     double* hp = B->hpin;
     if (!rc) rc = hip_check(hipMemcpyAsync(hp, w.sc.dots, ns * sizeof(double), hipMemcpyDeviceToHost, st), "D2H");
     if (!rc) rc = bsync(B);
@@ -1186,6 +1261,13 @@ int cheb_batch_destroy(cheb_batch* batch) {
   if (batch->dkc) (void)hipFree(batch->dkc);
   if (batch->dflag) (void)hipFree(batch->dflag);
   if (batch->hpin) (void)hipHostFree(batch->hpin);
+  if (batch->side_ok) {
+    for (int k = 0; k < kSide; ++k) {
+      (void)hipStreamDestroy(batch->side[k]);
+      (void)hipEventDestroy(batch->ev_join[k]);
+    }
+    (void)hipEventDestroy(batch->ev_fork);
+  }
   for (cheb_plan* p : batch->plans) cheb_plan_destroy(p);
   delete batch;
   return CHEB_OK;
