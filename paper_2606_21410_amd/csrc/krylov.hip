@@ -158,6 +158,7 @@ __device__ void arnoldi_column_wave(ArnoldiState* st, const double* dots, int j,
 constexpr int kGsThreads = 256;
 constexpr int kGsEPT = 8;
 constexpr int kGsChunk = kGsThreads * kGsEPT;
+constexpr int kColThreads = 1024;  // the column kernel: one wave per column of partial sums (j < 16 in one round)
 
 template <typename T, int PASS>
 __global__ __launch_bounds__(kGsThreads) void k_gram_schmidt(const T* __restrict__ V, size_t ld, int nv, T* w,
@@ -246,7 +247,7 @@ __device__ __forceinline__ void head_to_host(const ArnoldiState* st, ArnoldiHead
 }
 
 template <int PASS>
-__global__ __launch_bounds__(kGsThreads) void k_gs_column(const double* __restrict__ partials, int nb, int nv,
+__global__ __launch_bounds__(kColThreads) void k_gs_column(const double* __restrict__ partials, int nb, int nv,
                                                           double* dots, ArnoldiState* st, int j,
                                                           ArnoldiHead* host_head) {
   __shared__ double hs[kMaxKrylovCols + 2];
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_column(const double* __restri
     if (host_head && tid == 0) head_to_host(st, host_head);
     return;
   }
-  for (int c = wave; c <= nv; c += kGsThreads / 64) {
+  for (int c = wave; c <= nv; c += kColThreads / 64) {
     const double* pc = partials + (size_t)c * nb;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     int r = lane;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kGsThreads) void k_gs_column(const double* __restri
     if (lane == 0) hs[c] = sum;
   }
   __syncthreads();
-  for (int v = tid; v <= nv; v += kGsThreads) dots[v] = hs[v];
+  for (int v = tid; v <= nv; v += kColThreads) dots[v] = hs[v];
   if (wave == 0) {
     arnoldi_column_wave(st, hs, j, PASS, lane, col);
     // lane 0 wrote the head's scalars; the other lanes' H writes are not in it
@@ -332,12 +333,12 @@ int gram_schmidt(const T* V, size_t ld, int j, T* w, size_t npts, const double* 
   if (pass == 0) {
     hipLaunchKernelGGL((k_gram_schmidt<T, 0>), dim3(nb), dim3(kGsThreads), 0, s, V, ld, j + 1, w, npts, h0,
                        partials, st);
-    hipLaunchKernelGGL(k_gs_column<0>, dim3(1), dim3(kGsThreads), 0, s, partials, nb, j + 1, dots, st, j,
+    hipLaunchKernelGGL(k_gs_column<0>, dim3(1), dim3(kColThreads), 0, s, partials, nb, j + 1, dots, st, j,
                        host_head);
   } else {
     hipLaunchKernelGGL((k_gram_schmidt<T, 1>), dim3(nb), dim3(kGsThreads), 0, s, V, ld, j + 1, w, npts, h0,
                        partials, st);
-    hipLaunchKernelGGL(k_gs_column<1>, dim3(1), dim3(kGsThreads), 0, s, partials, nb, j + 1, dots, st, j,
+    hipLaunchKernelGGL(k_gs_column<1>, dim3(1), dim3(kColThreads), 0, s, partials, nb, j + 1, dots, st, j,
                        host_head);
   }
   return hip_check(hipGetLastError(), "gram_schmidt");
