@@ -278,16 +278,12 @@ def solve_section(P, d, dev, shape, uref_host, ref_info):
     return out
 
 
-def homogenisation_section(dev, n_struct=32, rtol=1e-10):
-    """Batched homogenisation workload: 32 log-normal microstructures (sigma 1,
-    correlation length 0.2) on grids drawn uniformly from {33, 49, 65, 97}^3
-    (seed 1004), three load cases each = 96 systems, FP32 inner / FP64
-    refinement with the fast-diagonalisation preconditioner, solved as one
-    batch; against the same solver looped over the 96 systems one by one."""
-    import numpy as np
+def _homog_inputs(dev, n_struct=32, rtol=1e-10):
+    """The homogenisation workload's microstructures (sizes from {33, 49, 65, 97}^3, seed 1004,
+    log-normal sigma 1, length 0.2) on the GPU and the solver options of its batch."""
     import torch
     from paper_2606_21410_amd import workloads as W
-    from paper_2606_21410_amd.api import Plan, SolveOptions, homogenize, load_case
+    from paper_2606_21410_amd.api import SolveOptions
     r = W.rng(1004)
     sizes = [int(v) for v in r.choice([33, 49, 65, 97], size=n_struct)]
     Ks = []
@@ -297,6 +293,18 @@ def homogenisation_section(dev, n_struct=32, rtol=1e-10):
     # restart length 20 and (MIXED) inner tolerance 1e-4, as for the preconditioned 129^3 runs
     # (a sweep on this batch: FP64 1.30 -> 1.20 s, MIXED 1.36 -> 1.21 s against 30 / 1e-3)
     opts = SolveOptions(rtol=rtol, maxiter=20000, precond=True, inner_m=20, ir_inner_rtol=1e-4)
+    return sizes, Ks, opts
+
+
+def homogenisation_section(dev, n_struct=32, rtol=1e-10):
+    """Batched homogenisation workload: 32 log-normal microstructures (sigma 1,
+    correlation length 0.2) on grids drawn uniformly from {33, 49, 65, 97}^3
+    (seed 1004), three load cases each = 96 systems, FP32 inner / FP64
+    refinement with the fast-diagonalisation preconditioner, solved as one
+    batch; against the same solver looped over the 96 systems one by one."""
+    import torch
+    from paper_2606_21410_amd.api import Plan, homogenize, load_case
+    sizes, Ks, opts = _homog_inputs(dev, n_struct, rtol)
     out = {"structures": n_struct, "systems": 3 * n_struct, "sizes": sizes,
            "points": int(sum(3 * n ** 3 for n in sizes)), "rtol": rtol}
     for label, prec in (("batched_mixed", "mixed"), ("batched_fp64", "f64")):
@@ -721,6 +729,9 @@ def main():
     ap.add_argument("--profile-precond", action="store_true",
                     help="for profiler runs: the preconditioner applications of the bench's precond section "
                          "only")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="for profiler runs: the 96-system homogenisation batch (MIXED), solved twice on "
+                         "one batch (the first with set-up and tile tuning)")
     ap.add_argument("--profile-solve", action="store_true",
                     help="for profiler runs: the preconditioned FP64 and mixed solves only, each twice on "
                          "one plan (the first with plan and preconditioner set-up)")
@@ -764,6 +775,22 @@ def main():
         _log(f"cold Newton N=128: {cold}")
         chain = thermal_newton_section(dev, levels=(4, 8, 16, 32, 64, 128))
         print(json.dumps({"profile_newton": {"cold_128": cold, "chain": chain}}), flush=True)
+        return
+
+    if args.profile_batch:
+        from paper_2606_21410_amd.api import homogenize
+        _, Ks, hopts = _homog_inputs(dev)
+        rec = {}
+        det = {}
+        for label in ("first", "second"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos, _ = homogenize(Ks, precision="mixed", opts=hopts, details=det, batch=det.get("batch"))
+            torch.cuda.synchronize()
+            rec[label] = {"seconds": round(time.perf_counter() - t0, 4),
+                          "max_matvecs": max(i["matvecs"] for i in infos),
+                          "all_converged": all(i["status"] == 0 for i in infos)}
+        print(json.dumps({"profile_batch": rec}), flush=True)
         return
 
     if args.profile_precond:
