@@ -163,7 +163,7 @@ int cheb_plan_set_stream(cheb_plan* plan, void* stream);
  * Returns CHEB_ERR_INVALID_ARG for a null plan, a non-finite entry, a nonzero
  * entry on a Dirichlet face, or coefficients that make some pencil's
  * end-value elimination block singular (the plan is then unchanged), and
- * CHEB_ERR_DEVICE on a HIP failure. */
+ * CHEB_ERR_DEVICE on a HIP failure (the plan then has no per-node part). */
 int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces);
 
 /* Choose how the reduced operator and its transpose evaluate the per-axis

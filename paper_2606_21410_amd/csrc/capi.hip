@@ -399,7 +399,15 @@ int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces) {
     rc = hip_check(hipMemcpyAsync(plan->rn32, h32.data(), tot * sizeof(float), hipMemcpyHostToDevice, plan->stream),
                    "hipMemcpyAsync(Robin coefficients)");
   if (!rc) rc = hip_check(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
-  if (rc) return rc;
+  if (rc) {
+    // the arrays may hold part of the new values: the plan drops its per-node part
+    (void)hipFree(plan->rn64);
+    (void)hipFree(plan->rn32);
+    plan->rn64 = nullptr;
+    plan->rn32 = nullptr;
+    drop_precond(plan);
+    return rc;
+  }
   for (int f = 0; f < 6; ++f) plan->rn_mean[f] = mean[f];
   drop_precond(plan);
   return CHEB_OK;
