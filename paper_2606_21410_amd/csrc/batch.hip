@@ -446,9 +446,10 @@ int bapply(cheb_batch* B, const T* K, const T* x, T* y) {
   for (auto& g : B->groups) nact += g.hact.empty() ? 0 : 1;
   const bool fork = B->side_ok && nact > 1;
   int rc = fork ? side_fork(B) : CHEB_OK;
+  if (rc) return rc;
   int i = 0;
   for (auto& g : B->groups) {
-    if (rc) return rc;
+    if (rc) break;
     if (g.hact.empty()) continue;
     hipStream_t st = fork ? B->side[i % kSide] : B->stream;
     ++i;
@@ -463,11 +464,15 @@ int bapply(cheb_batch* B, const T* K, const T* x, T* y) {
         const int s = g.members[k];
         const size_t o = B->off[s];
         rc = apply_t<T>(B->plans[s], K + B->koff[s], x + o, y + o, 1, st);
-        if (rc) return rc;
+        if (rc) break;
       }
     }
   }
-  if (!rc && fork) rc = side_join(B, i);
+  // joined also after an error, so nothing enqueued here outlives the call's stream order
+  if (fork) {
+    const int rj = side_join(B, i);
+    if (!rc) rc = rj;
+  }
   return rc;
 }
 
@@ -487,9 +492,12 @@ int bprec(cheb_batch* B, const T* in, T* out, T* pa, T* pb) {
     ++i;
     rc = precond_apply_batch<T>(B->plans[g.rep], in, out, g.doffs, g.dsys, B->dkc, (int)g.hact.size(), B->P,
                                 pa + g.pack_off, pb + g.pack_off, st);
-    if (rc) return rc;
+    if (rc) break;
   }
-  if (fork) rc = side_join(B, i);
+  if (fork) {
+    const int rj = side_join(B, i);
+    if (!rc) rc = rj;
+  }
   return rc;
 }
 
