@@ -28,8 +28,10 @@
 
 namespace cheb {
 
-// MODE_DERIV_ACC: y += D_a (K * u) on the interior nodes of interior-transverse
-// pencils (the Newton Jacobian's k'(T) term, K standing for k'(T) D_a T)
+// MODE_DERIV_ACC: y += D_a (K * V) on the interior nodes of interior-transverse
+// pencils, V the homogeneous lift of u's interior values, formed in the pencil
+// as in MODE_REDUCED (the Newton Jacobian's k'(T) term, K standing for
+// k'(T) D_a T)
 enum PassMode { MODE_FULL = 0, MODE_REDUCED = 1, MODE_TRANSPOSE = 2, MODE_DERIV = 3, MODE_DERIV_T = 4,
                 MODE_DERIV_ACC = 5 };
 
@@ -446,10 +448,13 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
         const int fl = flags[pl];
         if (fl & PF_VALID) {
           const int ad = base[pl] + m * stride;
-          const bool ld = (MODE == MODE_FULL || MODE == MODE_DERIV || MODE == MODE_DERIV_T ||
-                           MODE == MODE_DERIV_ACC) || (fl & PF_TIN);
-          if (MODE == MODE_DERIV_ACC) v[c] = a.u[ad] * a.K[ad];
-          else if (ld) v[c] = a.u[ad];
+          const bool ld = (MODE == MODE_FULL || MODE == MODE_DERIV || MODE == MODE_DERIV_T) || (fl & PF_TIN);
+          if (MODE == MODE_DERIV_ACC) {
+            // interior values times K; the end values come from the lift below
+            if ((fl & PF_TIN) && m != 0 && m != N) v[c] = a.u[ad] * a.K[ad];
+          } else if (ld) {
+            v[c] = a.u[ad];
+          }
           if (PRE_K) kv[PRE_K ? c : 0] = a.K[ad];
           if (PRE_Y && !a.first && (fl & PF_TIN) && m != 0 && m != N) yv[c] = a.y[ad];
         }
@@ -480,11 +485,13 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
   const int pp = tid / G, g = tid - pp * G;
   T* pen = sv + pp * SVS;
 
-  if (MODE == MODE_REDUCED) {
-    // homogeneous lift of the pencil's end values (Neumann rows, Section 2.3.1)
+  if (MODE == MODE_REDUCED || MODE == MODE_DERIV_ACC) {
+    // homogeneous lift of the pencil's end values (Neumann rows, Section 2.3.1);
+    // MODE_DERIV_ACC holds K * u in the tile, so its row sums read u itself
     T s0 = T(0), sN = T(0);
+    const int pb = base[pp];
     for (int m = 1 + g; m < N; m += G) {
-      const T v = pen[m];
+      const T v = MODE == MODE_DERIV_ACC ? ((flags[pp] & PF_TIN) ? a.u[pb + m * stride] : T(0)) : pen[m];
       s0 += a.drow0[m] * v;
       sN += a.drowN[m] * v;
     }
@@ -507,6 +514,10 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
         u0 = -s0 / m00;
       } else if (nhi) {
         uN = -sN / mNN;
+      }
+      if (MODE == MODE_DERIV_ACC) {
+        u0 *= a.K[pb];
+        uN *= a.K[pb + N * stride];
       }
       pen[0] = u0;
       pen[N] = uN;

@@ -525,15 +525,12 @@ int newton_linearise(cheb_plan* p, const double* K0, double alpha, const double*
 
 // y = J(T) v on interior rows (boundary rows 0): the reduced operator with
 // coefficient k(T), plus sum_a D_a (c_a V) with V the homogeneous lift of v;
-// each axis' term is one accumulating derivative pass that multiplies by c_a
-// as it loads V.
+// each axis' term is one accumulating derivative pass that lifts v's interior
+// values in the pencil (as the reduced operator does) and multiplies by c_a.
 int newton_jv(cheb_plan* p, NewtonWS& w, const double* v, double* y) {
   hipStream_t s = p->stream;
   int rc = apply_t<double>(p, w.k, v, y, 1, s);
-  if (!rc) rc = copy_scale<double>(w.V, v, 1.0, p->npts, s);
-  if (!rc) rc = mask_interior<double>(w.V, p->g.n, s);
-  if (!rc) rc = lift_full<double>(p, w.V, nullptr, s);
-  for (int a = 0; a < 3 && !rc; ++a) rc = launch_axis_pass<double>(p, a, 5, 0, w.c[a], w.V, y, s);
+  for (int a = 0; a < 3 && !rc; ++a) rc = launch_axis_pass<double>(p, a, 5, 0, w.c[a], v, y, s);
   return rc;
 }
 
