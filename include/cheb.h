@@ -318,7 +318,9 @@ int cheb_newton_jacobian(cheb_plan* plan, const void* K0, double alpha, const vo
                          void* work);
 
 /* Newton-LGMRES solve of div(k(T) grad T) = f with the boundary rows of
- * cheb_solve (Dirichlet values; Neumann outward dT/dn).  The state is
+ * cheb_solve (Dirichlet values; Neumann outward dT/dn plus the plan's Robin
+ * coefficients, per face and per node: the flux condition k(T) dT/dn = h of
+ * Section 3.4 is such a row, see cheb_plan_set_robin_nodes).  The state is
  * T_m = lift(x_m, g).  The scale is r_ref = ||R(lift(0, g))||, the residual of
  * the cold start, also when a warm start is given.  The iteration stops once
  * ||R(T_m)|| <= newton_tol r_ref (CHEB_OK) or after max_steps updates
