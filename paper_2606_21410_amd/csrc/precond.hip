@@ -289,8 +289,14 @@ bool eig_centro(int m, const std::vector<double>& A, std::vector<double>& lam, s
     S[(size_t)p * ps + p] = a(p, p);
   }
   std::vector<double> ls, Vs, Vsi, lw, Vw, Vwi;
-  if (!eig_real(ps, S, ls, Vs) || !invert(ps, Vs, Vsi)) return false;
-  if (p > 0 && (!eig_real(p, W, lw, Vw) || !invert(p, Vw, Vwi))) return false;
+  // the two half-size problems are independent: the antisymmetric one on a
+  // thread of its own
+  bool okw = true;
+  std::thread tw;
+  if (p > 0) tw = std::thread([&]() { okw = eig_real(p, W, lw, Vw) && invert(p, Vw, Vwi); });
+  const bool oks = eig_real(ps, S, ls, Vs) && invert(ps, Vs, Vsi);
+  if (tw.joinable()) tw.join();
+  if (!oks || !okw) return false;
   lam.assign(m, 0.0);
   V.assign((size_t)m * m, 0.0);
   Vi.assign((size_t)m * m, 0.0);
