@@ -232,3 +232,28 @@ def test_rejections():
         plan.set_robin_nodes(np.zeros(5))
     assert plan.robin_nodes is None
     plan.close()
+
+
+def test_refine_with_node_robin():
+    """Hierarchical refinement (cheb_refine) on levels whose plans carry their
+    own per-node coefficients: a degree-3 field with per-node Robin data is
+    exact on every level, so each solved level reproduces it and the
+    refinement indicator of the finer level is at rounding level."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan, SolveOptions, refine
+    d = lambda a: to_dev(a, torch.float64)
+    bc, robin = CASES["mixed"]
+    plans, Ks, fs, gs, exact = [], [], [], [], []
+    for n in (9, 17):
+        grid = W.Grid((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bc)
+        rn = W.random_robin_nodes(grid, 570 + n)
+        P = W.manufactured_polynomial(n, bc, seed=5, robin=robin, robin_nodes=rn)
+        plans.append(Plan(P.grid.n, P.grid.lo, P.grid.hi, bc, "f64", robin=robin, robin_nodes=rn))
+        Ks.append(d(P.K)); fs.append(d(P.f)); gs.append(d(P.g)); exact.append(P.u_exact)
+    us, e, solved, infos = refine(plans, Ks, fs, gs, 0.0, SolveOptions(rtol=1e-12, precond=True))
+    assert solved == [1, 1]
+    for u, ue in zip(us, exact):
+        assert np.max(np.abs(to_host(u) - ue)) <= 1e-9 * np.max(np.abs(ue))
+    # the degree-3 field is exact on the coarse level, so its prolongation already is the fine solution
+    assert e[1] <= 1e-9
