@@ -7,17 +7,20 @@
 namespace cheb {
 
 // Persistent launch: as many workgroups as the device holds at once (resident
-// workgroups per CU x CUs, queried once per kernel), at most one per tile.
+// workgroups per CU x CUs, queried once per kernel and device), at most one per
+// tile.
 template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int lds = dense_lds_bytes<T>(NC, V);
   static_assert(lds <= 160 * 1024, "matrix-core tile exceeds LDS");
-  static int resident = 0;
+  static DeviceCache cache;
+  int dev = 0;
+  if (int rc = current_device(&dev)) return rc;
+  int resident = cache.v[dev].load(std::memory_order_relaxed);
   if (resident == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
-    if (!rc && lds > 64 * 1024)
+    int cus = 0, per_cu = 0, rc = CHEB_OK;
+    if (lds > 64 * 1024)
       rc = hip_check(hipFuncSetAttribute((const void*)k_dense_pass<T, NC, MODE, FIRST, V, CG>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, lds),
                      "matrix-core pass LDS attribute");
@@ -28,6 +31,7 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
                      "occupancy query");
     if (rc) return rc;
     resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    cache.v[dev].store(resident, std::memory_order_relaxed);
   }
   const int ta = a.axis == 0 ? a.n[1] : a.n[0], tb = a.axis == 2 ? a.n[1] : a.n[2];
   const int tiles = ((ta - 2) * (tb - 2) + S.C - 1) / S.C * (a.sys ? a.nact : 1);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -24,6 +25,24 @@ struct AxisConst {
 
 void set_error(const std::string& msg);
 int hip_check(hipError_t e, const char* what);
+
+// Launch facts of one kernel instantiation (resident workgroups, whether its
+// LDS attribute is set), one slot per device, filled on the first launch on
+// that device; concurrent first launches compute and store the same value.
+constexpr int kMaxDevices = 64;
+struct DeviceCache {
+  std::atomic<int> v[kMaxDevices];
+};
+
+// ordinal of the calling thread's current device, within the cache's slots
+inline int current_device(int* dev) {
+  int rc = hip_check(hipGetDevice(dev), "hipGetDevice");
+  if (!rc && (*dev < 0 || *dev >= kMaxDevices)) {
+    set_error("device ordinal beyond the launch caches (64 devices)");
+    rc = CHEB_ERR_UNSUPPORTED;
+  }
+  return rc;
+}
 
 // Workspace carving: fields padded to 256 bytes.
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

@@ -16,8 +16,12 @@ static int launch_pass_inst(const PassArgs<T>& a, hipStream_t s) {
     set_error("axis pass tile does not fit in LDS");
     return CHEB_ERR_UNSUPPORTED;
   }
-  static bool attr_done = false;
-  if (lay.bytes > 64 * 1024 && !attr_done) {
+  static DeviceCache attr_set;  // 1 once the LDS attribute is set on the device
+  int dev = 0;
+  if (lay.bytes > 64 * 1024) {
+    if (int rc = current_device(&dev)) return rc;
+  }
+  if (lay.bytes > 64 * 1024 && !attr_set.v[dev].load(std::memory_order_relaxed)) {
     hipError_t e = hipFuncSetAttribute((const void*)k_axis_pass<T, NC, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lay.bytes);
     if (e != hipSuccess) {
@@ -25,7 +29,7 @@ static int launch_pass_inst(const PassArgs<T>& a, hipStream_t s) {
       set_error("axis pass tile needs more LDS than the device grants");
       return CHEB_ERR_UNSUPPORTED;
     }
-    attr_done = true;
+    attr_set.v[dev].store(1, std::memory_order_relaxed);
   }
   hipLaunchKernelGGL((k_axis_pass<T, NC, MODE>), dim3(tiles), dim3(NT), lay.bytes, s, a);
   return hip_check(hipGetLastError(), "axis pass launch");

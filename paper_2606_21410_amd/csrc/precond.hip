@@ -1014,16 +1014,18 @@ template <>
 const float* pc_base<float>(const cheb_plan* p) { return p->pc32; }
 
 // persistent launch: at most as many workgroups as the device holds at once
-// (queried once per instantiation), no more than the tasks need
+// (queried once per instantiation and device), no more than the tasks need
 template <typename T, int MP, int MODE, int SPLIT>
 static int launch_fdm(const FdmArgs& f, hipStream_t s) {
   constexpr int lds = fdm_lds_bytes<T>(MP, MODE, SPLIT);
   static_assert(lds <= 160 * 1024, "contraction tables exceed LDS");
-  static int resident = 0;
+  static DeviceCache cache;
+  int dev = 0;
+  if (int rc = current_device(&dev)) return rc;
+  int resident = cache.v[dev].load(std::memory_order_relaxed);
   if (resident == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
-    if (!rc && lds > 64 * 1024)
+    int cus = 0, per_cu = 0, rc = CHEB_OK;
+    if (lds > 64 * 1024)
       rc = hip_check(hipFuncSetAttribute((const void*)k_fdm_wave<T, MP, MODE, SPLIT>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, lds),
                      "contraction LDS attribute");
@@ -1034,6 +1036,7 @@ static int launch_fdm(const FdmArgs& f, hipStream_t s) {
                      "occupancy query");
     if (rc) return rc;
     resident = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    cache.v[dev].store(resident, std::memory_order_relaxed);
   }
   const long long npen = (long long)f.m0 * f.m1 * f.m2 / f.m * f.nb;
   const long long wgs = ((npen + 15) / 16 + kFdmWaves - 1) / kFdmWaves;
