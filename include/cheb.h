@@ -33,8 +33,10 @@
  *     solution does not depend on the choice.)
  *   - All calls are asynchronous on the plan's HIP stream unless stated; the
  *     caller keeps every buffer alive until the stream has finished with it.
- *   - The caller owns all field buffers and the workspace; the plan owns only a
- *     few kilobytes of device constants allocated at creation.
+ *   - The caller owns all field buffers and the workspace.  The plan owns its
+ *     device constants and tables (allocated at creation, see
+ *     cheb_plan_create), the preconditioner's factors (allocated when a call
+ *     first needs them) and per-node Robin coefficients (when set).
  *   - Errors are return codes, never exceptions.  0 = success; negative = hard
  *     error, outputs untouched; positive = soft status with valid outputs.
  *     cheb_last_error() gives a thread-local message for the last failure.
@@ -132,7 +134,12 @@ typedef struct cheb_plan cheb_plan;
  * Robin coefficients, and rejects all-Neumann problems without a Robin
  * coefficient with CHEB_ERR_SINGULAR_BC.  `stream` is a
  * hipStream_t (NULL = default stream).  Allocates a few KB of device constants
- * (boundary rows of the differentiation matrix). */
+ * (boundary rows of the differentiation matrix), the matrix-core route's
+ * fragment tables when an axis has N <= 128, and, when all three axes can take
+ * that route and axes x and y have the same N, one field-sized buffer
+ * (n0*n1*n2 values, 4 bytes each for CHEB_F32 plans, 8 otherwise) that holds
+ * the second partial sum of an apply whose x and y passes share one launch.
+ * Nothing is allocated after creation except where a call says so. */
 int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, cheb_plan** out);
 
 /* Bytes of device workspace needed by cheb_solve / cheb_adjoint / cheb_picard

@@ -260,6 +260,7 @@ int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, che
     if (p->dconst32) (void)hipFree(p->dconst32);
     if (p->dd64) (void)hipFree(p->dd64);
     if (p->dd32) (void)hipFree(p->dd32);
+    if (p->pair_buf) (void)hipFree(p->pair_buf);
     if (p->hpinned) (void)hipHostFree(p->hpinned);
     delete p;
     return rc;
@@ -450,6 +451,7 @@ int cheb_plan_destroy(cheb_plan* plan) {
   if (plan->dconst32) (void)hipFree(plan->dconst32);
   if (plan->dd64) (void)hipFree(plan->dd64);
   if (plan->dd32) (void)hipFree(plan->dd32);
+  if (plan->pair_buf) (void)hipFree(plan->pair_buf);
   if (plan->kev_ok) {
     (void)hipEventDestroy(plan->kev[0]);
     (void)hipEventDestroy(plan->kev[1]);

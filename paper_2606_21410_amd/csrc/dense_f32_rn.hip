@@ -4,6 +4,6 @@
 
 namespace cheb {
 
-template int launch_dense_rn<float, true>(const DenseArgs<float>&, int, int, int, hipStream_t);
+template int launch_dense_rn<float, true>(const DenseArgs<float>&, int, int, int, int, hipStream_t);
 
 }  // namespace cheb

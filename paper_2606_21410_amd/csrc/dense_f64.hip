@@ -10,7 +10,9 @@ namespace cheb {
 template int launch_dense_batch<double>(const cheb_plan*, int, int, const double*, const double*, double*, const DenseSys*,
                                       const int*, int, hipStream_t);
 template int launch_dense_pass<double>(const cheb_plan*, int, int, int, const double*, const double*, double*,
-                                       hipStream_t);
+                                       const double*, hipStream_t);
+template int launch_dense_pair<double>(const cheb_plan*, int, const double*, const double*, double*, double*, hipStream_t);
+template bool dense_pair_ok<double>(const cheb_plan*);
 
 // Ao / Ae / middle-row fragment table of a centro-antisymmetric n x n matrix M
 // (row-major), in the lane order the kernel loads: entry (mt, ks, lane) holds
@@ -81,6 +83,13 @@ int dense_setup(cheb_plan* p) {
   if (!rc)
     rc = hip_check(hipMemcpy(p->dd32, h32.data(), total * sizeof(float), hipMemcpyHostToDevice),
                    "hipMemcpy(matrix-core tables)");
+  // second output of the two-axis launch (x and y passes together), for plans
+  // whose three axes can all take the matrix-core route with equal N on x, y
+  if (!rc && p->dd_ok[0] && p->dd_ok[1] && p->dd_ok[2] && p->ax[0].N == p->ax[1].N) {
+    const size_t bytes = p->npts * (p->prec == CHEB_F32 ? sizeof(float) : sizeof(double));
+    rc = hip_check(hipMalloc(&p->pair_buf, bytes), "hipMalloc(two-axis pass buffer)");
+    if (rc) p->pair_buf = nullptr;
+  }
   return rc;
 }
 

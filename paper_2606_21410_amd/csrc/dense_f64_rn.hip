@@ -4,6 +4,6 @@
 
 namespace cheb {
 
-template int launch_dense_rn<double, true>(const DenseArgs<double>&, int, int, int, hipStream_t);
+template int launch_dense_rn<double, true>(const DenseArgs<double>&, int, int, int, int, hipStream_t);
 
 }  // namespace cheb

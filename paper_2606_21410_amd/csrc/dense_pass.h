@@ -158,28 +158,43 @@ __device__ inline DenseSys dense_sys_at(const DenseArgs<T>& a, int i) {
   return s;
 }
 
+// one axis of a launch: its tables, the lift's end-block entries and its output
 template <typename T>
-struct DenseArgs {
-  const int* gate;  // null, or a device flag: the pass does nothing while it reads 0
-  const T* u;  // single system (sys == nullptr)
-  const T* K;
-  T* y;
-  const DenseSys* sys;  // batched: system table (device) and the active systems' indices
-  const int* act;
-  int nact;
+struct DenseAxis {
   const T* tab;    // fragment table of D (reduced) or D^T (transpose)
   const T* drow0;  // face rows D[0][:], D[N][:] for the lift
   const T* drowN;
-  int n[3];
-  int axis, first, bcmask, npencils;  // bcmask of the single system
-  // the face rows' 2 x 2 matrix M = [m00 m0N; mN0 mNN] of the lift: the
-  // entries of M^{-1} (both ends Neumann) and 1 / m00, 1 / mNN (one end)
-  T i00, i0N, iN0, iNN, r00, rNN;
+  T* y;            // output (single system; batches: the packed base)
   // per-node Robin coefficients (modes with DENSE_NODE): each pencil's own
   // inverse, 4 entries per pencil of the axis (face numbering), laid out as
   // i00, i0N, iN0, iNN with 1 / m00 or 1 / mNN in place of the inverse when
   // one end is Dirichlet; null otherwise (always for batches)
   const T* rinv;
+  // the face rows' 2 x 2 matrix M = [m00 m0N; mN0 mNN] of the lift: the
+  // entries of M^{-1} (both ends Neumann) and 1 / m00, 1 / mNN (one end)
+  T i00, i0N, iN0, iNN, r00, rNN;
+  int axis;
+};
+
+template <typename T>
+struct DenseArgs {
+  const int* gate;  // null, or a device flag: the pass does nothing while it reads 0
+  const T* u;  // single system (sys == nullptr)
+  const T* K;
+  const DenseSys* sys;  // batched: system table (device) and the active systems' indices
+  const int* act;
+  int nact;
+  int n[3];
+  int bcmask;  // face types of the single system
+  // nseg = 2 (first passes of a single system): the launch serves two axes,
+  // ax[0] and ax[1], each into its own output; workgroup b takes axis
+  // ax[(b >> 3) & 1], so every XCD holds workgroups of both (the grid is a
+  // multiple of 16)
+  int nseg;
+  // accumulating pass along the unit-stride axis: y += yadd + this pass (yadd
+  // is the second output of a two-axis launch); unused by the other passes
+  const T* yadd;
+  DenseAxis<T> ax[2];
 };
 
 // tile element e -> (node j along the pencil, column c): pencil-contiguous for
@@ -255,16 +270,16 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
       const T s0_ = ACCO[0] + ACCE[0], sN_ = ACCO[0] - ACCE[0];             \
       T u0 = T(0), uN = T(0);                                               \
       if (RN) {                                                             \
-        const T* e_ = a.rinv + 4 * dense_face_index(tile, col, C, tps, npen, nbi); \
+        const T* e_ = A.rinv + 4 * dense_face_index(tile, col, C, tps, npen, nbi); \
         u0 = -(e_[0] * s0_ + e_[1] * sN_);                                  \
         uN = -(e_[2] * s0_ + e_[3] * sN_);                                  \
       } else if (nlo && nhi) {                                              \
-        u0 = -(a.i00 * s0_ + a.i0N * sN_);                                  \
-        uN = -(a.iN0 * s0_ + a.iNN * sN_);                                  \
+        u0 = -(A.i00 * s0_ + A.i0N * sN_);                                  \
+        uN = -(A.iN0 * s0_ + A.iNN * sN_);                                  \
       } else if (nlo) {                                                     \
-        u0 = -a.r00 * s0_;                                                  \
+        u0 = -A.r00 * s0_;                                                  \
       } else if (nhi) {                                                     \
-        uN = -a.rNN * sN_;                                                  \
+        uN = -A.rNN * sN_;                                                  \
       }                                                                     \
       cend[2 * col] = u0;                                                   \
       cend[2 * col + 1] = uN;                                               \
@@ -370,12 +385,12 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
       const DenseSys s_ = dense_sys_at(a, (TILE) / tps);  \
       PU = a.u + s_.off;                                  \
       PK = a.K + s_.koff;                                 \
-      PY = a.y + s_.off;                                  \
+      PY = A.y + s_.off;                                  \
       BM = s_.bcmask;                                     \
     } else {                                              \
       PU = a.u;                                           \
       PK = a.K;                                           \
-      PY = a.y;                                           \
+      PY = A.y;                                           \
       BM = a.bcmask;                                      \
     }                                                     \
   } while (0)
@@ -389,6 +404,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   if (a.gate && !*a.gate) return;
   constexpr int BASE = MODE & 1;                   // DENSE_REDUCED or DENSE_TRANSPOSE
   constexpr bool RN = (MODE & DENSE_NODE) != 0;    // per-pencil end-block inverses
+  constexpr bool YADD = CG && !FIRST;              // the last pass of a two-axis apply adds yadd
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int N = NC, n = NC + 1;
   constexpr int NT = 64 * S.NW;
@@ -421,7 +437,13 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   const int li = lane & 15, lk = lane >> 4;
   const int col = cg * 16 + li;  // this lane's B column / accumulator column
   const int lc = tid / LPC, lg = tid - lc * LPC;
-  const int axis = a.axis;
+  // segment of a two-axis launch, and this workgroup's index and the grid size
+  // within it (XCD bits kept: vb & 7 == blockIdx.x & 7)
+  const int seg = a.nseg == 2 ? (blockIdx.x >> 3) & 1 : 0;
+  const int vb = a.nseg == 2 ? (int)(((blockIdx.x >> 4) << 3) | (blockIdx.x & 7)) : (int)blockIdx.x;
+  const int vg = a.nseg == 2 ? (int)(gridDim.x >> 1) : (int)gridDim.x;
+  const DenseAxis<T> A = seg ? a.ax[1] : a.ax[0];
+  const int axis = A.axis;
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   // CG: the pass runs along the unit-stride axis (axis 2)
   const int stride = CG ? 1 : axis == 1 ? n2 : n1 * n2;
@@ -437,18 +459,18 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   T ao[V == 1 ? S.KO4 : 1], ae[V == 1 ? S.KE4 : 1];
   if (V == 1) {
 #pragma unroll
-    for (int ks = 0; ks < S.KO4; ++ks) ao[ks] = a.tab[(mt * S.KO4 + ks) * 64 + lane];
+    for (int ks = 0; ks < S.KO4; ++ks) ao[ks] = A.tab[(mt * S.KO4 + ks) * 64 + lane];
 #pragma unroll
-    for (int ks = 0; ks < S.KE4; ++ks) ae[ks] = a.tab[S.OFF_E + (mt * S.KE4 + ks) * 64 + lane];
+    for (int ks = 0; ks < S.KE4; ++ks) ae[ks] = A.tab[S.OFF_E + (mt * S.KE4 + ks) * 64 + lane];
   }
 
   if (FIRST) {
     // pencils in a face: every node is a boundary node of the reduced system
     const int na = nai + 2, nb = nbi + 2;
     const int nface = na * nb - npen;
-    for (int fs = blockIdx.x; fs < nsys * nface; fs += gridDim.x) {
+    for (int fs = vb; fs < nsys * nface; fs += vg) {
       const int f = fs % nface;
-      T* ys = a.sys ? a.y + a.sys[a.act[fs / nface]].off : a.y;
+      T* ys = a.sys ? A.y + a.sys[a.act[fs / nface]].off : A.y;
       int ia, ib;
       if (f < 2 * nb) {
         ia = f < nb ? 0 : na - 1;
@@ -468,18 +490,18 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   constexpr int TI = (S.TAB - TB + NT - 1) / NT;
   T tv[TI];
 #pragma unroll
-  for (int i = 0; i < TI; ++i) tv[i] = a.tab[TB + (tid + i * NT < S.TAB - TB ? tid + i * NT : S.TAB - TB - 1)];
+  for (int i = 0; i < TI; ++i) tv[i] = A.tab[TB + (tid + i * NT < S.TAB - TB ? tid + i * NT : S.TAB - TB - 1)];
   const int jr = tid < n ? tid : n - 1;
-  const T r0v = a.drow0[jr], rNv = a.drowN[jr];
+  const T r0v = A.drow0[jr], rNv = A.drowN[jr];
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
   // workgroup b serves a contiguous range of tiles of XCD b % 8 and tiles that
   // share cache lines at their edges meet in the same L2
-  int t_step = gridDim.x, t_end = ntiles, tile = blockIdx.x;
-  if ((gridDim.x & 7) == 0 && ntiles >= (int)gridDim.x) {
+  int t_step = vg, t_end = ntiles, tile = vb;
+  if ((vg & 7) == 0 && ntiles >= vg) {
     const int per = (ntiles + 7) >> 3;
-    const int x = blockIdx.x & 7;
-    tile = x * per + (blockIdx.x >> 3);
-    t_step = gridDim.x >> 3;
+    const int x = vb & 7;
+    tile = x * per + (vb >> 3);
+    t_step = vg >> 3;
     t_end = min(ntiles, (x + 1) * per);
   }
   int slot = 0;
@@ -508,8 +530,8 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     drw[n + tid] = rNv;
   }
   for (int j = tid + NT; j < n; j += NT) {
-    drw[j] = a.drow0[j];
-    drw[n + j] = a.drowN[j];
+    drw[j] = A.drow0[j];
+    drw[n + j] = A.drowN[j];
   }
   // registers -> LDS: u in split form (e_jp in row jp, o_jp in row N/2 + 1 + jp)
   // with its end nodes cleared (the interior values of the lift), K as it is.
@@ -547,7 +569,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     // addresses are formed here and the loads are issued a few at a time
     // between the products' matrix instructions, so the matrix cores keep
     // working while load issue waits for queue space.
-    T unx[PREF ? 2 * EPP : 1], knx[PREF ? 2 * EPP : 1], yreg[EPT];
+    T unx[PREF ? 2 * EPP : 1], knx[PREF ? 2 * EPP : 1], yreg[EPT], y2reg[YADD ? EPT : 1];
     {
       T* ny_;
       int nbm_;
@@ -588,9 +610,14 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   do {                                       \
     if (PREF && (KS) < NL) DENSE_PREF1(KS);  \
   } while (0)
-#define DENSE_ISSUE2(KS)                                                           \
-  do {                                                                             \
-    if (!FIRST && (KS) < EPT) yreg[(KS) < EPT ? (KS) : 0] = dense_at(cy, DENSE_AD(slot, (KS) < EPT ? (KS) : 0)); \
+#define DENSE_ISSUE2(KS)                                              \
+  do {                                                                \
+    if (!FIRST && (KS) < EPT) {                                       \
+      const int q_ = (KS) < EPT ? (KS) : 0;                           \
+      const int o_ = DENSE_AD(slot, q_);                              \
+      yreg[q_] = dense_at(cy, o_);                                    \
+      if (YADD) y2reg[YADD ? q_ : 0] = dense_at(a.yadd, o_);          \
+    }                                                                 \
   } while (0)
 
     V4 acco, acce;
@@ -610,7 +637,11 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_GEMM(acco, acce, DENSE_ISSUE2);
 #pragma unroll
     for (int q = S.KE4; q < EPT; ++q)
-      if (!FIRST) yreg[q] = dense_at(cy, DENSE_AD(slot, q));
+      if (!FIRST) {
+        const int o_ = DENSE_AD(slot, q);
+        yreg[q] = dense_at(cy, o_);
+        if (YADD) y2reg[YADD ? q : 0] = dense_at(a.yadd, o_);
+      }
     DENSE_VDOT(midv);
     DENSE_EPI(acco, acce, midv, false, false);  // into the K tile: no barrier needed before it
     lds_barrier();
@@ -621,16 +652,16 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         const T z0 = Kt[tid], zN = Kt[N * SC + tid];
         T mu0 = T(0), muN = T(0);
         if (RN) {
-          const T* e = a.rinv + 4 * dense_face_index(tile, tid, C, tps, npen, nbi);
+          const T* e = A.rinv + 4 * dense_face_index(tile, tid, C, tps, npen, nbi);
           mu0 = e[0] * z0 + e[2] * zN;
           muN = e[1] * z0 + e[3] * zN;
         } else if (nlo && nhi) {
-          mu0 = a.i00 * z0 + a.iN0 * zN;
-          muN = a.i0N * z0 + a.iNN * zN;
+          mu0 = A.i00 * z0 + A.iN0 * zN;
+          muN = A.i0N * z0 + A.iNN * zN;
         } else if (nlo) {
-          mu0 = a.r00 * z0;
+          mu0 = A.r00 * z0;
         } else if (nhi) {
-          muN = a.rNN * zN;
+          muN = A.rNN * zN;
         }
         cend[2 * tid] = mu0;
         cend[2 * tid + 1] = muN;
@@ -656,6 +687,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
         T x = Kt[j * SC + c];
         if (BASE == DENSE_TRANSPOSE && (nlo || nhi)) x -= cend[2 * c] * drw[j] + cend[2 * c + 1] * drw[n + j];
         if (!FIRST) x += yreg[q];
+        if (YADD) x += y2reg[YADD ? q : 0];
         ov[q] = in ? x : T(0);
         op[q] = ok ? (unsigned)(b + j * stride) : 0u;
         if (!ok) ov[q] = T(0);

@@ -103,6 +103,10 @@ struct cheb_plan {
   double* rn64;
   float* rn32;
   double rn_mean[6];
+  // the two-axis launch's second output: one field (n0 n1 n2 values of the
+  // plan's widest precision), allocated at creation when axes 0 and 1 have
+  // the same N on the matrix-core route; null otherwise
+  void* pair_buf;
 };
 
 namespace cheb {
@@ -135,10 +139,19 @@ struct DenseSys;
 template <typename T>
 int launch_dense_batch(const cheb_plan* rep, int axis, int first, const T* K, const T* u, T* y,
                        const DenseSys* sys, const int* act, int nact, hipStream_t s);
-// transpose: 0 reduced pass, 1 transposed reduced pass
+// transpose: 0 reduced pass, 1 transposed reduced pass.  yadd: a second
+// partial sum that the accumulating pass along the unit-stride axis (axis 2,
+// first = 0) adds, and only that pass (null otherwise)
 template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
-                      hipStream_t s);
+                      const T* yadd, hipStream_t s);
+// the first passes along axes 0 and 1 in one launch, into y0 and y1; possible
+// when all three axes take the matrix-core route, axes 0 and 1 have the same N
+// and tile shape, and the plan holds pair_buf (dense_pair_ok)
+template <typename T>
+bool dense_pair_ok(const cheb_plan* p);
+template <typename T>
+int launch_dense_pair(const cheb_plan* p, int transpose, const T* K, const T* u, T* y0, T* y1, hipStream_t s);
 // pi: 0 for the FP64 passes, 1 for the FP32 passes
 inline bool use_dense(const cheb_plan* p, int axis, int pi) {
   if (!p->dd_ok[axis] || p->route == CHEB_ROUTE_FFT) return false;

@@ -83,7 +83,7 @@ template <typename T>
 int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T* K, const T* u, T* y,
                      hipStream_t s) {
   if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && use_dense(p, axis, sizeof(T) == sizeof(double) ? 0 : 1))
-    return launch_dense_pass<T>(p, axis, mode == MODE_TRANSPOSE ? 1 : 0, first, K, u, y, s);
+    return launch_dense_pass<T>(p, axis, mode == MODE_TRANSPOSE ? 1 : 0, first, K, u, y, nullptr, s);
   PassArgs<T> a;
   a.gate = p->gate;
   a.u = u;
@@ -113,6 +113,16 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
 
 template <typename T>
 int apply_t(const cheb_plan* p, const T* K, const T* u, T* y, int mode, hipStream_t s) {
+  if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && dense_pair_ok<T>(p)) {
+    // matrix-core route: the x and y passes in one launch (x into y, y into
+    // the plan's second buffer; each initialises every row it owns), then the
+    // z pass adds both to its own
+    const int tr = mode == MODE_TRANSPOSE ? 1 : 0;
+    T* y1 = (T*)p->pair_buf;
+    int rc = launch_dense_pair<T>(p, tr, K, u, y, y1, s);
+    if (rc) return rc;
+    return launch_dense_pass<T>(p, 2, tr, 0, K, u, y, y1, s);
+  }
   // z pass first (it initialises every row it owns), then y, then x
   int rc = launch_axis_pass<T>(p, 2, mode, 1, K, u, y, s);
   if (rc) return rc;
