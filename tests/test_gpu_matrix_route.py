@@ -18,9 +18,11 @@ pytestmark = pytest.mark.gpu
 F64_TOL = 1e-12
 F32_TOL = 1e-5
 
-# every N the matrix route supports (16..128), ragged mixes with FFT-route axes
+# every N the matrix route supports (16..128), ragged mixes with FFT-route axes;
+# x and y of equal N share one launch (the last three: with another N on z),
+# the other mixes take three
 SIZES = [(17, 17, 17), (33, 33, 33), (49, 49, 49), (65, 65, 65), (97, 97, 97), (129, 129, 129),
-         (33, 24, 65), (129, 17, 49), (13, 97, 33)]
+         (33, 24, 65), (129, 17, 49), (13, 97, 33), (65, 65, 33), (33, 33, 129), (17, 17, 97)]
 BCS = ["DDNNNN", "NDNNDN", "NNNDNN", "DDDDDD"]
 
 
@@ -54,7 +56,8 @@ def test_matrix_route_f64(n, bcname):
     assert rel_l2(to_host(plan.apply(Kd, ud, mode="transpose")), yt) <= 1e-13
 
 
-@pytest.mark.parametrize("n", [(17, 17, 17), (33, 33, 33), (65, 65, 65), (129, 129, 129), (49, 24, 97)])
+@pytest.mark.parametrize("n", [(17, 17, 17), (33, 33, 33), (65, 65, 65), (129, 129, 129), (49, 24, 97),
+                               (65, 65, 33)])
 @pytest.mark.parametrize("bcname", ["DDNNNN", "NDNNDN"])
 def test_matrix_route_f32(n, bcname):
     require_gpu()
