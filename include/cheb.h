@@ -138,7 +138,8 @@ typedef struct cheb_plan cheb_plan;
  * fragment tables when an axis has N <= 128, and, when all three axes can take
  * that route and axes x and y have the same N, one field-sized buffer
  * (n0*n1*n2 values, 4 bytes each for CHEB_F32 plans, 8 otherwise) that holds
- * the second partial sum of an apply whose x and y passes share one launch.
+ * the second partial sum of an apply whose x and y passes share one launch
+ * (if that allocation fails, applies take three launches instead).
  * Nothing is allocated after creation except where a call says so. */
 int cheb_plan_create(const cheb_grid* grid, int32_t precision, void* stream, cheb_plan** out);
 

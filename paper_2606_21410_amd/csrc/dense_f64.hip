@@ -84,11 +84,14 @@ int dense_setup(cheb_plan* p) {
     rc = hip_check(hipMemcpy(p->dd32, h32.data(), total * sizeof(float), hipMemcpyHostToDevice),
                    "hipMemcpy(matrix-core tables)");
   // second output of the two-axis launch (x and y passes together), for plans
-  // whose three axes can all take the matrix-core route with equal N on x, y
+  // whose three axes can all take the matrix-core route with equal N on x, y;
+  // optional: without it an apply takes three launches
   if (!rc && p->dd_ok[0] && p->dd_ok[1] && p->dd_ok[2] && p->ax[0].N == p->ax[1].N) {
     const size_t bytes = p->npts * (p->prec == CHEB_F32 ? sizeof(float) : sizeof(double));
-    rc = hip_check(hipMalloc(&p->pair_buf, bytes), "hipMalloc(two-axis pass buffer)");
-    if (rc) p->pair_buf = nullptr;
+    if (hipMalloc(&p->pair_buf, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p->pair_buf = nullptr;
+    }
   }
   return rc;
 }
