@@ -141,8 +141,10 @@ def cpu_detail(P, seconds_budget=4.0):
 
 
 def _solve_once(P, shape, prec, opts, K, f, g, u0, dev):
-    """One timed solve on a fresh plan (plan set-up, preconditioner set-up and
-    the solve are inside the timed region; the workspace is allocated before)."""
+    """One timed solve on a fresh plan: the plan is created and its workspace
+    allocated before the timed region; the preconditioner's set-up (its host
+    eigen-decompositions and tables, done on first use) and the solve are
+    inside it."""
     import torch
     from paper_2606_21410_amd.api import Plan
     pl = Plan(shape, P.grid.lo, P.grid.hi, P.grid.bc, prec, dev)

@@ -103,12 +103,19 @@ bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vect
     double vn = 0.0;
     for (int i = k + 1; i < m; ++i) vn += v[i] * v[i];
     if (vn == 0.0) continue;
-    // H = P H P, P = I - 2 v v^T / vn
-    for (int j = 0; j < m; ++j) {
-      double s = 0.0;
-      for (int i = k + 1; i < m; ++i) s += v[i] * H(i, j);
-      s *= 2.0 / vn;
-      for (int i = k + 1; i < m; ++i) H(i, j) -= s * v[i];
+    // H = P H P, P = I - 2 v v^T / vn; the left product row by row:
+    // zs_j = sum_i v_i H(i, j) (i ascending), then H(i, j) -= (2/vn) v_i zs_j
+    std::fill(zs.begin(), zs.end(), 0.0);
+    for (int i = k + 1; i < m; ++i) {
+      const double vi = v[i];
+      const double* hr = &H(i, 0);
+      for (int j = 0; j < m; ++j) zs[j] += vi * hr[j];
+    }
+    for (int j = 0; j < m; ++j) zs[j] *= 2.0 / vn;
+    for (int i = k + 1; i < m; ++i) {
+      const double vi = v[i];
+      double* hr = &H(i, 0);
+      for (int j = 0; j < m; ++j) hr[j] -= zs[j] * vi;
     }
     for (int i = 0; i < m; ++i) {
       double s = 0.0;
@@ -166,7 +173,9 @@ bool eig_real(int m, std::vector<double>& A, std::vector<double>& lam, std::vect
     if (iter % 11 == 10) mu += std::fabs(H(hi, hi - 1));  // exceptional shift
     double x = H(lo, lo) - mu, z = H(lo + 1, lo);
     for (int k = lo; k < hi; ++k) {
-      const double r = std::hypot(x, z);
+      // (the entries of these operators stay far from overflow and underflow
+      // when squared, so the plain root serves in place of hypot)
+      const double r = std::sqrt(x * x + z * z);
       const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
       // rows k, k+1 (columns from max(lo, k-1) to m-1: full Schur form)
       for (int j = std::max(lo, k - 1); j < m; ++j) {
@@ -243,19 +252,20 @@ bool invert(int m, const std::vector<double>& A, std::vector<double>& Ainv) {
         std::swap(W[(size_t)piv * m + j], W[(size_t)c * m + j]);
         std::swap(Ainv[(size_t)piv * m + j], Ainv[(size_t)c * m + j]);
       }
+    // columns < c of W hold the identity by now, so W's rows change from column c on
     const double inv = 1.0 / W[(size_t)c * m + c];
-    for (int j = 0; j < m; ++j) {
-      W[(size_t)c * m + j] *= inv;
-      Ainv[(size_t)c * m + j] *= inv;
-    }
+    for (int j = c; j < m; ++j) W[(size_t)c * m + j] *= inv;
+    for (int j = 0; j < m; ++j) Ainv[(size_t)c * m + j] *= inv;
     for (int r = 0; r < m; ++r) {
       if (r == c) continue;
       const double f = W[(size_t)r * m + c];
       if (f == 0.0) continue;
-      for (int j = 0; j < m; ++j) {
-        W[(size_t)r * m + j] -= f * W[(size_t)c * m + j];
-        Ainv[(size_t)r * m + j] -= f * Ainv[(size_t)c * m + j];
-      }
+      double* wr = &W[(size_t)r * m];
+      const double* wc = &W[(size_t)c * m];
+      for (int j = c; j < m; ++j) wr[j] -= f * wc[j];
+      double* ar = &Ainv[(size_t)r * m];
+      const double* ac = &Ainv[(size_t)c * m];
+      for (int j = 0; j < m; ++j) ar[j] -= f * ac[j];
     }
   }
   return true;
