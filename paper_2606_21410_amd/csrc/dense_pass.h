@@ -395,10 +395,13 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
     }                                                     \
   } while (0)
 
-// Persistent: each workgroup walks tiles blockIdx.x, +gridDim.x, ... over the
-// interior-transverse pencils and keeps the next tile's u and K loads in flight
-// in registers while it computes the current one.  In the first pass it also
-// clears the pencils that lie in a face (all their nodes are boundary nodes).
+// Persistent: each workgroup walks its XCD's contiguous range of tiles over
+// the interior-transverse pencils (in a two-axis launch, within its axis'
+// half of the grid) and, with V = 0, keeps the next tile's u and K loads in
+// flight in registers while it computes the current one.  A first pass also
+// clears the pencils of its axis that lie in a face (all their nodes are
+// boundary nodes).  The accumulating pass along the unit-stride axis adds the
+// second partial sum yadd of a two-axis launch.
 template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(DenseArgs<T> a) {
   if (a.gate && !*a.gate) return;
