@@ -519,12 +519,26 @@ def thermal_newton_cold(dev, levels=(128, 256), tol=1e-11, max_steps=20, maxiter
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         err = float((u - torch.from_numpy(P.u_exact).to(dev)).abs().max().item())
+        # one Jacobian call (coefficients k, c_a at the solution, then J v),
+        # event-timed: the per-product cost, which does not move with the
+        # LGMRES counts near the tolerance floor
+        v = torch.randn(P.grid.n, device=dev, dtype=torch.float64)
+        y = torch.empty_like(v)
+        for _ in range(3):
+            plan.newton_jacobian(K0, u, v, alpha=P.meta["alpha"], out=y)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            plan.newton_jacobian(K0, u, v, alpha=P.meta["alpha"], out=y)
+        ev1.record()
+        torch.cuda.synchronize()
         rec = {"N": N, "start": "cold", "newton_steps": info["newton_steps"],
                "lgmres_total": sum(info["mv_per_step"]), "lgmres_per_step": info["mv_per_step"],
-               "max_error": err, "seconds": round(el, 4), "status": info["rc"]}
+               "max_error": err, "seconds": round(el, 4), "status": info["rc"],
+               "jacobian_call_us": round(ev0.elapsed_time(ev1) * 1e3 / 10, 1)}
         _log(f"thermal newton cold {rec}")
         out.append(rec)
-        del K0, f, g, u, plan
+        del K0, f, g, u, v, y, plan
         torch.cuda.empty_cache()
     return out
 

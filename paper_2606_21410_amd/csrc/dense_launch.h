@@ -6,6 +6,10 @@
 
 namespace cheb {
 
+// `kind` of the dispatch below: 0 reduced pass, 1 transposed reduced pass,
+// kDenseDacc the Newton Jacobian's derivative pass (DENSE_DACC)
+constexpr int kDenseDacc = 2;
+
 // Persistent launch: as many workgroups as the device holds at once (resident
 // workgroups per CU x CUs, queried once per kernel and device), at most one per
 // tile.  A two-axis launch gives each axis half of them, a multiple of 8 (the
@@ -55,37 +59,44 @@ static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T, int NC, int V, bool CG, bool RN>
-static int launch_dense_c(const DenseArgs<T>& a, int first, int transpose, hipStream_t s) {
+static int launch_dense_c(const DenseArgs<T>& a, int first, int kind, hipStream_t s) {
   constexpr int MR = DENSE_REDUCED | (RN ? DENSE_NODE : 0), MT = DENSE_TRANSPOSE | (RN ? DENSE_NODE : 0);
+  if (kind == kDenseDacc) {
+    // the Newton Jacobian's accumulating derivative pass (FP64 plans only)
+    if constexpr (sizeof(T) == sizeof(double))
+      return launch_dense_inst<T, NC, MR | DENSE_DACC, false, V, CG>(a, s);
+    set_error("matrix-core derivative pass: FP64 only");
+    return CHEB_ERR_UNSUPPORTED;
+  }
   if (first)
-    return transpose ? launch_dense_inst<T, NC, MT, true, V, CG>(a, s) : launch_dense_inst<T, NC, MR, true, V, CG>(a, s);
-  return transpose ? launch_dense_inst<T, NC, MT, false, V, CG>(a, s) : launch_dense_inst<T, NC, MR, false, V, CG>(a, s);
+    return kind ? launch_dense_inst<T, NC, MT, true, V, CG>(a, s) : launch_dense_inst<T, NC, MR, true, V, CG>(a, s);
+  return kind ? launch_dense_inst<T, NC, MT, false, V, CG>(a, s) : launch_dense_inst<T, NC, MR, false, V, CG>(a, s);
 }
 
 template <typename T, int NC, int V, bool RN>
-static int launch_dense_v(const DenseArgs<T>& a, int first, int transpose, hipStream_t s) {
-  return a.ax[0].axis == 2 ? launch_dense_c<T, NC, V, true, RN>(a, first, transpose, s)
-                           : launch_dense_c<T, NC, V, false, RN>(a, first, transpose, s);
+static int launch_dense_v(const DenseArgs<T>& a, int first, int kind, hipStream_t s) {
+  return a.ax[0].axis == 2 ? launch_dense_c<T, NC, V, true, RN>(a, first, kind, s)
+                           : launch_dense_c<T, NC, V, false, RN>(a, first, kind, s);
 }
 
 template <typename T, int NC, bool RN>
-static int launch_dense_n(const DenseArgs<T>& a, int first, int transpose, int variant, hipStream_t s) {
-  return variant == 1 ? launch_dense_v<T, NC, 1, RN>(a, first, transpose, s)
-                      : launch_dense_v<T, NC, 0, RN>(a, first, transpose, s);
+static int launch_dense_n(const DenseArgs<T>& a, int first, int kind, int variant, hipStream_t s) {
+  return variant == 1 ? launch_dense_v<T, NC, 1, RN>(a, first, kind, s)
+                      : launch_dense_v<T, NC, 0, RN>(a, first, kind, s);
 }
 
 // every N and tile shape of the pass, with (RN) or without per-node Robin
 // inverses; the two sets are instantiated in separate files (dense_f64.hip /
 // dense_f64_rn.hip and the FP32 pair) so that they compile in parallel
 template <typename T, bool RN>
-int launch_dense_rn(const DenseArgs<T>& a, int N, int first, int transpose, int variant, hipStream_t s) {
+int launch_dense_rn(const DenseArgs<T>& a, int N, int first, int kind, int variant, hipStream_t s) {
   switch (N) {
-    case 16: return launch_dense_n<T, 16, RN>(a, first, transpose, variant, s);
-    case 32: return launch_dense_n<T, 32, RN>(a, first, transpose, variant, s);
-    case 48: return launch_dense_n<T, 48, RN>(a, first, transpose, variant, s);
-    case 64: return launch_dense_n<T, 64, RN>(a, first, transpose, variant, s);
-    case 96: return launch_dense_n<T, 96, RN>(a, first, transpose, variant, s);
-    case 128: return launch_dense_n<T, 128, RN>(a, first, transpose, variant, s);
+    case 16: return launch_dense_n<T, 16, RN>(a, first, kind, variant, s);
+    case 32: return launch_dense_n<T, 32, RN>(a, first, kind, variant, s);
+    case 48: return launch_dense_n<T, 48, RN>(a, first, kind, variant, s);
+    case 64: return launch_dense_n<T, 64, RN>(a, first, kind, variant, s);
+    case 96: return launch_dense_n<T, 96, RN>(a, first, kind, variant, s);
+    case 128: return launch_dense_n<T, 128, RN>(a, first, kind, variant, s);
     default: set_error("matrix-core pass: unsupported N"); return CHEB_ERR_UNSUPPORTED;
   }
 }
@@ -177,6 +188,20 @@ template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
                       const T* yadd, hipStream_t s) {
   return launch_dense_common<T>(p, axis, transpose, first, K, u, y, yadd, nullptr, nullptr, 0, s);
+}
+
+// y += D_a (c .* L v) on the interior nodes of interior-transverse pencils
+// along axis a (L v: v's interior values with the end values of the
+// homogeneous lift), accumulating: the matrix-core form of the FFT route's
+// MODE_DERIV_ACC pass
+template <typename T>
+int launch_dense_dacc(const cheb_plan* p, int axis, const T* c, const T* v, T* y, hipStream_t s) {
+  DenseArgs<T> a = dense_args<T>(p, c, v, nullptr, nullptr, 0);
+  a.ax[0] = dense_axis<T>(p, axis, 0, false, y);
+  a.ax[1] = a.ax[0];
+  const int variant = p->dense_var[axis][sizeof(T) == sizeof(double) ? 0 : 1];
+  return a.ax[0].rinv ? launch_dense_rn<T, true>(a, p->ax[axis].N, 0, kDenseDacc, variant, s)
+                      : launch_dense_rn<T, false>(a, p->ax[axis].N, 0, kDenseDacc, variant, s);
 }
 
 template <typename T>

@@ -31,8 +31,12 @@
 namespace cheb {
 
 // DENSE_NODE is or-ed into either mode when the plan has per-node Robin
-// coefficients: the lift then reads each pencil's own end-block inverse
-enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1, DENSE_NODE = 2 };
+// coefficients: the lift then reads each pencil's own end-block inverse.
+// DENSE_DACC (with DENSE_REDUCED, accumulating passes only): y += D (K .* L v)
+// on the interior nodes, one derivative of the pointwise product of K with the
+// lifted pencil -- the Newton Jacobian's k'(T) term, K standing for
+// k'(T) D_a T.  The first product then serves only for the lift's face-row sums.
+enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1, DENSE_NODE = 2, DENSE_DACC = 4 };
 
 // element i of a system's field at base (uniform): a system's field stays
 // below 4 GiB (at most 129^3 nodes per axis triple), so the byte offset fits
@@ -288,7 +292,10 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
 
 // accumulators -> LDS tile rows i and N-i.  FLUX (first product): add the
 // lift's rank-2 correction u0 M[:][0] + uN M[:][N] (LIFT, on axes with a
-// Neumann end), multiply by K and store the flux split into the u tile.  M is
+// Neumann end), multiply by K and store the flux split into the u tile.  With
+// DACC the first product's rows are not used: rows i and N-i are the lifted
+// pencil itself, (e_i +- o_i) / 2 from the split tile (u0 and uN at i = 0),
+// times K.  M is
 // centro-antisymmetric, so row N-i of the correction is -(u0 M[i][N] +
 // uN M[i][0]).  Otherwise (second product) the rows go to the K tile, dead
 // since the first epilogue, so the second product's reads of the u tile need
@@ -306,7 +313,17 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
       if (i < S.RM) {                                                        \
         const T o = ACCO[r], e = ACCE[r];                                    \
         T lo = o + e, hi = o - e;                                            \
-        if (lift_) {                                                         \
+        if (DACC && (FLUX)) {                                                \
+          if (i == 0) {                                                      \
+            lo = cend[2 * col];                                              \
+            hi = cend[2 * col + 1];                                          \
+          } else {                                                           \
+            const T ev_ = U[i * SC + col];                                   \
+            const T od_ = 2 * i == N ? T(0) : U[(S.KE + i) * SC + col];      \
+            lo = T(0.5) * (ev_ + od_);                                       \
+            hi = T(0.5) * (ev_ - od_);                                       \
+          }                                                                  \
+        } else if (lift_) {                                                  \
           const T c0_ = dc0[i], cN_ = dcN[i];                                \
           lo += u0_ * c0_ + uN_ * cN_;                                       \
           hi -= u0_ * cN_ + uN_ * c0_;                                       \
@@ -331,7 +348,8 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
     }                                                                        \
     if (S.MIDV && lc < C && lg == 0) {                                       \
       T m_ = MIDVAL;                                                         \
-      if (lift_) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
+      if (DACC && (FLUX)) m_ = T(0.5) * U[S.HALF * SC + lc];                 \
+      else if (lift_) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
       if (FLUX) m_ *= Kt[S.HALF * SC + lc];                                  \
       if (FLUX) U[S.HALF * SC + lc] = m_ + m_;                               \
       else Kt[S.HALF * SC + lc] = m_;                                        \
@@ -407,7 +425,9 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   if (a.gate && !*a.gate) return;
   constexpr int BASE = MODE & 1;                   // DENSE_REDUCED or DENSE_TRANSPOSE
   constexpr bool RN = (MODE & DENSE_NODE) != 0;    // per-pencil end-block inverses
-  constexpr bool YADD = CG && !FIRST;              // the last pass of a two-axis apply adds yadd
+  constexpr bool DACC = (MODE & DENSE_DACC) != 0;  // one derivative of K .* (lifted u)
+  static_assert(!DACC || (BASE == DENSE_REDUCED && !FIRST), "DENSE_DACC: accumulating reduced passes only");
+  constexpr bool YADD = CG && !FIRST && !DACC;     // the last pass of a two-axis apply adds yadd
   constexpr DenseDims S = dense_dims(NC, V);
   constexpr int N = NC, n = NC + 1;
   constexpr int NT = 64 * S.NW;
@@ -630,7 +650,8 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     // whatever did not fit between the k-steps
 #pragma unroll
     for (int ks = S.KE4; ks < (PREF ? NL : 0); ++ks) DENSE_PREF1(ks);
-    DENSE_VDOT(midv);
+    if (DACC) midv = T(0);  // the middle row comes from the tile itself
+    else DENSE_VDOT(midv);
     if (BASE == DENSE_REDUCED) DENSE_LIFTVALS(acco, acce);
     lds_barrier();
     DENSE_EPI(acco, acce, midv, true, BASE == DENSE_REDUCED);

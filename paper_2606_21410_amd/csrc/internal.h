@@ -150,6 +150,10 @@ int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, co
 // and tile shape, and the plan holds pair_buf (dense_pair_ok)
 template <typename T>
 bool dense_pair_ok(const cheb_plan* p);
+// y += D_a (c .* L v) on interior nodes (the Newton Jacobian's k'(T) term on
+// the matrix-core route; FP64)
+template <typename T>
+int launch_dense_dacc(const cheb_plan* p, int axis, const T* c, const T* v, T* y, hipStream_t s);
 template <typename T>
 int launch_dense_pair(const cheb_plan* p, int transpose, const T* K, const T* u, T* y0, T* y1, hipStream_t s);
 // pi: 0 for the FP64 passes, 1 for the FP32 passes

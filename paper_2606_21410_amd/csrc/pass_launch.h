@@ -84,6 +84,9 @@ int launch_axis_pass(const cheb_plan* p, int axis, int mode, int first, const T*
                      hipStream_t s) {
   if ((mode == MODE_REDUCED || mode == MODE_TRANSPOSE) && use_dense(p, axis, sizeof(T) == sizeof(double) ? 0 : 1))
     return launch_dense_pass<T>(p, axis, mode == MODE_TRANSPOSE ? 1 : 0, first, K, u, y, nullptr, s);
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (mode == MODE_DERIV_ACC && !first && use_dense(p, axis, 0)) return launch_dense_dacc<T>(p, axis, K, u, y, s);
+  }
   PassArgs<T> a;
   a.gate = p->gate;
   a.u = u;
