@@ -184,8 +184,9 @@ int cheb_plan_set_robin_nodes(cheb_plan* plan, const double* sigma_faces);
  *                        matrix cores (even-odd split), other axes use the FFT;
  *   CHEB_ROUTE_AUTO   -- the default; currently identical to CHEB_ROUTE_MATRIX.
  * The two routes agree to rounding.  FULL applies, derivatives and the adjoint
- * gradient always use the FFT route.  Returns CHEB_ERR_INVALID_ARG for an
- * unknown route. */
+ * gradient always use the FFT route; the Newton Jacobian's derivative term
+ * follows the plan's route like the reduced operator.  Returns
+ * CHEB_ERR_INVALID_ARG for an unknown route. */
 int cheb_plan_set_route(cheb_plan* plan, int32_t route);
 
 /* Autotuner of the reduced operator: times the FFT route and the two tile
