@@ -14,6 +14,8 @@ template int launch_dense_pass<double>(const cheb_plan*, int, int, int, const do
 template int launch_dense_pair<double>(const cheb_plan*, int, const double*, const double*, double*, double*, hipStream_t);
 template bool dense_pair_ok<double>(const cheb_plan*);
 template int launch_dense_dacc<double>(const cheb_plan*, int, const double*, const double*, double*, hipStream_t);
+template int launch_dense_jac<double>(const cheb_plan*, const double*, const double* const*, const double*, double*,
+                                      hipStream_t);
 
 // Ao / Ae / middle-row fragment table of a centro-antisymmetric n x n matrix M
 // (row-major), in the lane order the kernel loads: entry (mt, ks, lane) holds

@@ -7,8 +7,10 @@
 namespace cheb {
 
 // `kind` of the dispatch below: 0 reduced pass, 1 transposed reduced pass,
-// kDenseDacc the Newton Jacobian's derivative pass (DENSE_DACC)
+// kDenseDacc the Newton Jacobian's derivative pass (DENSE_DACC), kDenseJac the
+// Jacobian's whole axis term (DENSE_JAC)
 constexpr int kDenseDacc = 2;
+constexpr int kDenseJac = 3;
 
 // Persistent launch: as many workgroups as the device holds at once (resident
 // workgroups per CU x CUs, queried once per kernel and device), at most one per
@@ -17,7 +19,7 @@ constexpr int kDenseDacc = 2;
 template <typename T, int NC, int MODE, bool FIRST, int V, bool CG>
 static int launch_dense_inst(const DenseArgs<T>& a, hipStream_t s) {
   constexpr DenseDims S = dense_dims(NC, V);
-  constexpr int lds = dense_lds_bytes<T>(NC, V);
+  constexpr int lds = dense_lds_bytes<T>(NC, V, (MODE & DENSE_JAC) != 0);
   static_assert(lds <= 160 * 1024, "matrix-core tile exceeds LDS");
   static DeviceCache cache;
   int dev = 0;
@@ -66,6 +68,14 @@ static int launch_dense_c(const DenseArgs<T>& a, int first, int kind, hipStream_
     if constexpr (sizeof(T) == sizeof(double))
       return launch_dense_inst<T, NC, MR | DENSE_DACC, false, V, CG>(a, s);
     set_error("matrix-core derivative pass: FP64 only");
+    return CHEB_ERR_UNSUPPORTED;
+  }
+  if (kind == kDenseJac) {
+    // the Newton Jacobian's axis terms (FP64 plans, 4-wave tiles)
+    if constexpr (sizeof(T) == sizeof(double) && V == 1)
+      return first ? launch_dense_inst<T, NC, MR | DENSE_JAC, true, V, CG>(a, s)
+                   : launch_dense_inst<T, NC, MR | DENSE_JAC, false, V, CG>(a, s);
+    set_error("matrix-core Jacobian pass: FP64 and tile shape 1 only");
     return CHEB_ERR_UNSUPPORTED;
   }
   if (first)
@@ -129,6 +139,7 @@ static DenseAxis<T> dense_axis(const cheb_plan* p, int axis, int transpose, bool
     x.drowN = (const T*)(p->dconst32 + slotN);
   }
   x.y = y;
+  x.c = nullptr;
   x.axis = axis;
   {
     const double m00 = p->ax[axis].m00, m0N = p->ax[axis].m0N, mN0 = p->ax[axis].mN0, mNN = p->ax[axis].mNN;
@@ -188,6 +199,36 @@ template <typename T>
 int launch_dense_pass(const cheb_plan* p, int axis, int transpose, int first, const T* K, const T* u, T* y,
                       const T* yadd, hipStream_t s) {
   return launch_dense_common<T>(p, axis, transpose, first, K, u, y, yadd, nullptr, nullptr, 0, s);
+}
+
+// y = sum_a D_a (K .* D_a L v + c_a .* L v) on interior nodes, 0 on boundary
+// nodes: the Newton Jacobian's action (the reduced operator at K plus the
+// k'(T) terms) in the two launches of the reduced apply, the c_a term added
+// in each flux epilogue.  CHEB_ERR_UNSUPPORTED when the plan's passes cannot
+// take that form (FP64 only; all axes on the matrix-core route with tile shape
+// 1, the x and y passes sharing a launch); the caller then takes the separate
+// passes.
+template <typename T>
+int launch_dense_jac(const cheb_plan* p, const T* K, const T* const* c, const T* v, T* y, hipStream_t s) {
+  if (sizeof(T) != sizeof(double) || !dense_pair_ok<T>(p) || p->dense_var[0][0] != 1 || p->dense_var[2][0] != 1)
+    return CHEB_ERR_UNSUPPORTED;
+  T* y1 = (T*)p->pair_buf;
+  DenseArgs<T> a = dense_args<T>(p, K, v, nullptr, nullptr, 0);
+  a.nseg = 2;
+  a.ax[0] = dense_axis<T>(p, 0, 0, false, y);
+  a.ax[1] = dense_axis<T>(p, 1, 0, false, y1);
+  a.ax[0].c = c[0];
+  a.ax[1].c = c[1];
+  int rc = a.ax[0].rinv ? launch_dense_rn<T, true>(a, p->ax[0].N, 1, kDenseJac, 1, s)
+                        : launch_dense_rn<T, false>(a, p->ax[0].N, 1, kDenseJac, 1, s);
+  if (rc) return rc;
+  DenseArgs<T> z = dense_args<T>(p, K, v, nullptr, nullptr, 0);
+  z.ax[0] = dense_axis<T>(p, 2, 0, false, y);
+  z.ax[0].c = c[2];
+  z.ax[1] = z.ax[0];
+  z.yadd = y1;
+  return z.ax[0].rinv ? launch_dense_rn<T, true>(z, p->ax[2].N, 0, kDenseJac, 1, s)
+                      : launch_dense_rn<T, false>(z, p->ax[2].N, 0, kDenseJac, 1, s);
 }
 
 // y += D_a (c .* L v) on the interior nodes of interior-transverse pencils

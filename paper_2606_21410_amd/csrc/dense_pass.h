@@ -36,7 +36,10 @@ namespace cheb {
 // on the interior nodes, one derivative of the pointwise product of K with the
 // lifted pencil -- the Newton Jacobian's k'(T) term, K standing for
 // k'(T) D_a T.  The first product then serves only for the lift's face-row sums.
-enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1, DENSE_NODE = 2, DENSE_DACC = 4 };
+// DENSE_JAC (with DENSE_REDUCED, 4-wave tiles, FP64): the Newton Jacobian's
+// whole axis term, y (+)= D (K .* D L v + C .* L v), the flux epilogue adding
+// C .* (lifted v) from a third LDS tile that holds the axis' C = k'(T) D_a T.
+enum DenseMode { DENSE_REDUCED = 0, DENSE_TRANSPOSE = 1, DENSE_NODE = 2, DENSE_DACC = 4, DENSE_JAC = 8 };
 
 // element i of a system's field at base (uniform): a system's field stays
 // below 4 GiB (at most 129^3 nodes per axis triple), so the byte offset fits
@@ -122,15 +125,15 @@ __host__ __device__ constexpr int pow2_floor(int x) {
   return p;
 }
 
-// LDS carve of one workgroup (bytes): fragment table, u tile, K tile, face
-// rows, the per-column lift values / transposed-lift multipliers, column
-// bookkeeping
+// LDS carve of one workgroup (bytes): fragment table, u tile, K tile (and the
+// C tile of DENSE_JAC), face rows, the per-column lift values / transposed-lift
+// multipliers, column bookkeeping
 template <typename T>
-__host__ __device__ constexpr int dense_lds_bytes(int N, int V) {
+__host__ __device__ constexpr int dense_lds_bytes(int N, int V, bool jac = false) {
   const DenseDims d = dense_dims(N, V);
   const int n = N + 1, SC = d.C + 1;
   const int tabl = V == 0 ? d.TAB : d.TAB - d.OFF_MID;  // V = 1: only the middle row and end columns
-  return (tabl + 2 * n * SC + 2 * n + 2 * d.C) * (int)sizeof(T) + 2 * d.C * (int)sizeof(int);
+  return (tabl + (jac ? 3 : 2) * n * SC + 2 * n + 2 * d.C) * (int)sizeof(T) + 2 * d.C * (int)sizeof(int);
 }
 
 // one system of a batched pass (same N, box and tile shape as the others): its
@@ -169,6 +172,7 @@ struct DenseAxis {
   const T* drow0;  // face rows D[0][:], D[N][:] for the lift
   const T* drowN;
   T* y;            // output (single system; batches: the packed base)
+  const T* c;      // DENSE_JAC: the axis' coefficient C of the lifted direction; null otherwise
   // per-node Robin coefficients (modes with DENSE_NODE): each pencil's own
   // inverse, 4 entries per pencil of the axis (face numbering), laid out as
   // i00, i0N, iN0, iNN with 1 / m00 or 1 / mNN in place of the inverse when
@@ -330,8 +334,25 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
         }                                                                    \
         if (FLUX) {                                                          \
           /* flux K * (M u), stored split for the second product */          \
+          T vlo_ = T(0), vhi_ = T(0);                                        \
+          if (JAC) {                                                         \
+            /* the lifted pencil itself, before its rows are overwritten */  \
+            if (i == 0) {                                                    \
+              vlo_ = cend[2 * col];                                          \
+              vhi_ = cend[2 * col + 1];                                      \
+            } else {                                                         \
+              const T ev_ = U[i * SC + col];                                 \
+              const T od_ = 2 * i == N ? T(0) : U[(S.KE + i) * SC + col];    \
+              vlo_ = T(0.5) * (ev_ + od_);                                   \
+              vhi_ = T(0.5) * (ev_ - od_);                                   \
+            }                                                                \
+          }                                                                  \
           lo *= Kt[i * SC + col];                                            \
           hi *= Kt[(N - i) * SC + col];                                      \
+          if (JAC) {                                                         \
+            lo += Ct[i * SC + col] * vlo_;                                   \
+            hi += Ct[(N - i) * SC + col] * vhi_;                             \
+          }                                                                  \
           if (2 * i == N) {                                                  \
             U[i * SC + col] = lo + lo;                                       \
           } else {                                                           \
@@ -351,6 +372,7 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
       if (DACC && (FLUX)) m_ = T(0.5) * U[S.HALF * SC + lc];                 \
       else if (lift_) m_ += cend[2 * lc] * dc0[S.HALF] + cend[2 * lc + 1] * dcN[S.HALF]; \
       if (FLUX) m_ *= Kt[S.HALF * SC + lc];                                  \
+      if (JAC && (FLUX)) m_ += Ct[S.HALF * SC + lc] * (T(0.5) * U[S.HALF * SC + lc]); \
       if (FLUX) U[S.HALF * SC + lc] = m_ + m_;                               \
       else Kt[S.HALF * SC + lc] = m_;                                        \
     }                                                                        \
@@ -376,7 +398,7 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
 // to LDS).  Every load is issued (off-tile pairs read node 0 and their columns
 // are discarded), so the number of outstanding loads is static and the
 // compiler's waits stay exact; nothing here waits for the loads.
-#define DENSE_LOAD(SLOT, UR, KR, PU, PK)                              \
+#define DENSE_LOAD(SLOT, UR, KR, PU, PK, CR, PC)                      \
   do {                                                                \
     int alo_[EPP], ahi_[EPP];                                         \
     _Pragma("unroll") for (int q = 0; q < EPP; ++q) {                 \
@@ -392,6 +414,10 @@ __device__ inline int dense_face_index(int t, int c, int C, int tps, int npen, i
       UR[2 * q + 1] = dense_at(PU, ahi_[q]);                          \
       KR[2 * q] = dense_at(PK, alo_[q]);                              \
       KR[2 * q + 1] = dense_at(PK, ahi_[q]);                          \
+      if (JAC) {                                                      \
+        CR[JAC ? 2 * q : 0] = dense_at(PC, alo_[q]);                  \
+        CR[JAC ? 2 * q + 1 : 0] = dense_at(PC, ahi_[q]);              \
+      }                                                               \
     }                                                                 \
   } while (0)
 
@@ -426,6 +452,8 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   constexpr int BASE = MODE & 1;                   // DENSE_REDUCED or DENSE_TRANSPOSE
   constexpr bool RN = (MODE & DENSE_NODE) != 0;    // per-pencil end-block inverses
   constexpr bool DACC = (MODE & DENSE_DACC) != 0;  // one derivative of K .* (lifted u)
+  constexpr bool JAC = (MODE & DENSE_JAC) != 0;    // reduced operator plus C .* (lifted u) in the flux
+  static_assert(!JAC || (BASE == DENSE_REDUCED && !DACC && V == 1), "DENSE_JAC: reduced passes, 4-wave tiles");
   static_assert(!DACC || (BASE == DENSE_REDUCED && !FIRST), "DENSE_DACC: accumulating reduced passes only");
   constexpr bool YADD = CG && !FIRST && !DACC;     // the last pass of a two-axis apply adds yadd
   constexpr DenseDims S = dense_dims(NC, V);
@@ -448,7 +476,8 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   T* tab = (T*)smem - TB;
   T* U = tab + S.TAB;
   T* Kt = U + n * SC;
-  T* drw = Kt + n * SC;  // face rows D[0][:], D[N][:]
+  T* Ct = Kt + n * SC;   // DENSE_JAC: the C tile (natural node order, like K)
+  T* drw = Ct + (JAC ? n * SC : 0);  // face rows D[0][:], D[N][:]
   T* cend = drw + 2 * n;
   int(*cbase)[C] = (int(*)[C])(cend + 2 * C);
   const T* amid = tab + S.OFF_MID;
@@ -543,8 +572,8 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
   // into registers (during the first product, or after the second epilogue)
   // and into a second LDS buffer pair all measured slower at 129^3.
   constexpr bool PREF = V == 0;
-  T ureg[2 * EPP], kreg[2 * EPP];
-  if (PREF) DENSE_LOAD(0, ureg, kreg, cu, cK);
+  T ureg[2 * EPP], kreg[2 * EPP], creg[JAC ? 2 * EPP : 1];
+  if (PREF) DENSE_LOAD(0, ureg, kreg, cu, cK, creg, A.c);
 #pragma unroll
   for (int i = 0; i < TI; ++i)
     if (tid + i * NT < S.TAB - TB) tab[TB + tid + i * NT] = tv[i];
@@ -573,6 +602,10 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
       if (2 * jp != N) (DU)[(S.KE + jp) * SC + c] = ua - ub;  \
       Kt[jp * SC + c] = KR[2 * q];                            \
       Kt[(N - jp) * SC + c] = KR[2 * q + 1];                  \
+      if (JAC) {                                              \
+        Ct[jp * SC + c] = creg[JAC ? 2 * q : 0];              \
+        Ct[(N - jp) * SC + c] = creg[JAC ? 2 * q + 1 : 0];    \
+      }                                                       \
     }                                                         \
   } while (0)
 
@@ -582,7 +615,7 @@ __global__ __launch_bounds__(64 * dense_dims(NC, V).NW, 2) void k_dense_pass(Den
     DENSE_SYS(tile, cu, cK, cy, cbm);
     nlo = (cbm >> (2 * axis)) & 1;
     nhi = (cbm >> (2 * axis + 1)) & 1;
-    if (!PREF) DENSE_LOAD(slot, ureg, kreg, cu, cK);
+    if (!PREF) DENSE_LOAD(slot, ureg, kreg, cu, cK, creg, A.c);
     DENSE_PUT(U, ureg, kreg);
     if (nxt < ntiles) DENSE_COLS(slot ^ 1, nxt);
     else if (tid < C) cbase[slot ^ 1][tid] = -1;  // loads of the next tile all read node 0

@@ -154,6 +154,10 @@ bool dense_pair_ok(const cheb_plan* p);
 // the matrix-core route; FP64)
 template <typename T>
 int launch_dense_dacc(const cheb_plan* p, int axis, const T* c, const T* v, T* y, hipStream_t s);
+// the Newton Jacobian's action in the two launches of the reduced apply (the
+// c_a terms in the flux epilogues); CHEB_ERR_UNSUPPORTED when the plan cannot
+template <typename T>
+int launch_dense_jac(const cheb_plan* p, const T* K, const T* const* c, const T* v, T* y, hipStream_t s);
 template <typename T>
 int launch_dense_pair(const cheb_plan* p, int transpose, const T* K, const T* u, T* y0, T* y1, hipStream_t s);
 // pi: 0 for the FP64 passes, 1 for the FP32 passes

@@ -524,11 +524,18 @@ int newton_linearise(cheb_plan* p, const double* K0, double alpha, const double*
 }
 
 // y = J(T) v on interior rows (boundary rows 0): the reduced operator with
-// coefficient k(T), plus sum_a D_a (c_a V) with V the homogeneous lift of v;
-// each axis' term is one accumulating derivative pass that lifts v's interior
-// values in the pencil (as the reduced operator does) and multiplies by c_a.
+// coefficient k(T), plus sum_a D_a (c_a V) with V the homogeneous lift of v.
+// On the matrix-core route the c_a terms join the reduced apply's flux
+// epilogues; otherwise each axis' term is one accumulating derivative pass
+// that lifts v's interior values in the pencil (as the reduced operator does)
+// and multiplies by c_a.
 int newton_jv(cheb_plan* p, NewtonWS& w, const double* v, double* y) {
   hipStream_t s = p->stream;
+  // matrix-core route with the x and y passes in one launch: the c_a terms
+  // ride in the reduced apply's flux epilogues (two launches in all)
+  const double* c[3] = {w.c[0], w.c[1], w.c[2]};
+  const int r = launch_dense_jac<double>(p, w.k, c, v, y, s);
+  if (r != CHEB_ERR_UNSUPPORTED) return r;
   int rc = apply_t<double>(p, w.k, v, y, 1, s);
   for (int a = 0; a < 3 && !rc; ++a) rc = launch_axis_pass<double>(p, a, 5, 0, w.c[a], v, y, s);
   return rc;
