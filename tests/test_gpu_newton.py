@@ -16,13 +16,46 @@ CASES = [((17, 17, 17), THERMAL_BC, (0, 0, 0), (1, 1, 1)),
          ((19, 13, 9), BC_SETS["NDNNDN"], (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)),
          ((33, 17, 65), BC_SETS["DDNNNN"], (0, 0, 0), (1, 2, 1)),
          ((5, 4, 3), BC_SETS["NNNNND"], (0, 0, 0), (1, 1, 1)),
-         ((129, 129, 129), THERMAL_BC, (0, 0, 0), (1, 1, 1))]
+         ((129, 129, 129), THERMAL_BC, (0, 0, 0), (1, 1, 1)),
+         # x and y share a launch (their own tables and c_a), z another N
+         ((33, 33, 65), BC_SETS["NDNNDN"], (0.0, -1.0, 0.5), (1.0, 1.0, 2.0))]
 
 
 def _state(n, seed):
     """A full nodal state with 1 + 0.5 T > 0.4 everywhere, and a random K0."""
     T = 0.4 * np.tanh(W.random_field(n, seed))
     return T, W.random_conductivity(n, seed + 1)
+
+
+@pytest.mark.parametrize("n", [(33, 33, 33), (65, 65, 33), (129, 129, 129)])
+def test_jacobian_forms_agree(n):
+    """The Jacobian action in its three forms on one plan: the k' terms in the
+    matrix-core apply's flux epilogues (tile shape 1, x and y in one launch),
+    one matrix-core derivative pass per axis (tile shape 0), and the FFT
+    route's derivative passes; all against the oracle's Jacobian."""
+    require_gpu()
+    import torch
+    from paper_2606_21410_amd.api import Plan
+    d = lambda a: to_dev(a, torch.float64)
+    bc = BC_SETS["NDNNDN"]
+    lo, hi = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+    G = O.Grid3(n, lo, hi, bc)
+    T, K0 = _state(n, 41)
+    v = W.random_field(n, 44)
+    y_o = O.newton_jacobian(G, K0, 0.5, T, v)
+    scale = np.max(np.abs(y_o))
+    plan = Plan(n, lo, hi, bc, "f64")
+    ys = {}
+    for name, setup in (("fused", lambda: plan.set_tile_shape(1, "f64")),
+                        ("passes", lambda: plan.set_tile_shape(0, "f64")),
+                        ("fft", lambda: plan.set_route("fft"))):
+        setup()
+        log(f"jacobian form {name} n={n}")
+        ys[name] = to_host(plan.newton_jacobian(d(K0), d(T), d(v), 0.5))
+        assert np.max(np.abs(ys[name] - y_o)) <= 1e-12 * scale
+        assert np.all(ys[name][~G.interior] == 0.0)
+    for name in ("passes", "fft"):
+        assert np.max(np.abs(ys[name] - ys["fused"])) <= 1e-13 * scale
 
 
 @pytest.mark.parametrize("n,bc,lo,hi", CASES)
