@@ -51,6 +51,7 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct PrecondAxis {
   int m;
   int split;  // centro-symmetric factors whose even and odd halves fill whole 16-row blocks
+  int centro; // the axis' 1-D operator is centro-symmetric (the same face row at both ends)
   size_t off_V, off_Vi, off_lam;
   // matrix-core fragment tables (m <= 128): [0: the V^{-1} side, 1: the V side][transposed]
   size_t off_tab[2][2];  // an axis with the same 1-D problem as an earlier one shares its tables

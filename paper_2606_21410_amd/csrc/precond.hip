@@ -360,6 +360,7 @@ struct GemmArgs {
   int I, Kd, C;
   long long a_si, a_sk, b_sk, b_sc, d_si, d_sc;
   long long a_sb, b_sb, d_sb;  // batch strides
+  int ps;                      // k_axis_gemm_split: the symmetric half, ceil(m / 2)
 };
 
 template <typename T>
@@ -397,6 +398,124 @@ __global__ __launch_bounds__(256) void k_axis_gemm(GemmArgs g) {
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + Mfma<T>::row(lk, r);
       if (i < g.I) D[i * g.d_si + c * g.d_sc] = acc[t][r];
+    }
+  }
+}
+
+// The same contraction for an axis whose 1-D operator is centro-symmetric
+// (m = ps + ph, ps = ceil(m/2) a multiple of 16), with half the multiply-adds.
+// With Q the symmetric / antisymmetric node-pair basis:
+//   KIND 1 (the input enters through Q^T, e.g. V^{-1} = diag(Vs^{-1}, Vw^{-1}) Q^T):
+//     output row i < ps (a symmetric mode) sums M[i][k] (x_k + x_{m-1-k}) over
+//     k < ps, the middle node of odd m taken once; row i >= ps sums
+//     M[i][k] (x_k - x_{m-1-k}) over k < ph;
+//   KIND 2 (the output leaves through Q, e.g. V = Q diag(Vs, Vw)): for i < ps,
+//     P = sum_{k < ps} M[i][k] y_k and R = sum_{k >= ps} M[i][k] y_k give node i
+//     = P + R and node m-1-i = P - R (the middle node of odd m: P).
+// M is read through the strides of either operand: ZSIDE, the contraction
+// along the unit-stride axis, D[r][i] = sum_k X[r][k] M[i][k] (M the B
+// operand, the split acts on the columns, each 16-column group symmetric or
+// antisymmetric as a whole); otherwise D[i][c] = sum_k M[i][k] X[k][c] (M the
+// A operand, each 16-row block one or the other).  One wave computes 16 rows x
+// 64 columns of the output (KIND 2: of rows or columns below ps, with a second
+// set of accumulators for R).
+template <typename T, int KIND, bool ZSIDE>
+__global__ __launch_bounds__(256) void k_axis_gemm_split(GemmArgs g) {
+  typedef typename Mfma<T>::v4 v4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 16;
+  const int c0 = (blockIdx.y * 4 + wave) * 64;
+  const int b = blockIdx.z;
+  const T* A = (const T*)g.A + b * g.a_sb;
+  const T* B = (const T*)g.B + b * g.b_sb;
+  T* D = (T*)g.D + b * g.d_sb;
+  const int m = g.Kd, ps = g.ps, ph = m - g.ps;
+  // output extent of this launch: rows (ZSIDE: columns) below ps for KIND 2
+  const int I = (!ZSIDE && KIND == 2) ? ps : g.I;
+  const int C = (ZSIDE && KIND == 2) ? ps : g.C;
+  if (c0 >= C) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ia = i0 + li;
+  v4 acc[4], acr[KIND == 2 ? 4 : 1];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4{0, 0, 0, 0};
+  if (KIND == 2)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acr[KIND == 2 ? t : 0] = v4{0, 0, 0, 0};
+  if (KIND == 1) {
+    // the row block (ZSIDE: each column group) is symmetric below ps
+    const bool rsym = i0 < ps;
+    const int kend = ZSIDE ? ps : (rsym ? ps : ph);
+    for (int k0 = 0; k0 < kend; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kin = k < kend;
+      const int kr = m - 1 - (kin ? k : 0);  // mirror node (in range for k < ps)
+      if (ZSIDE) {
+        // A = X: pair sum and difference of this lane's row
+        T sm = T(0), df = T(0);
+        if (ia < I && kin) {
+          const T x1 = A[ia * g.a_si + k * g.a_sk], x2 = A[ia * g.a_si + kr * g.a_sk];
+          sm = kr == k ? x1 : x1 + x2;
+          df = x1 - x2;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int cg = c0 + t * 16, c = cg + li;
+          const bool csym = cg < ps;
+          const bool kok = csym ? kin : k < ph;
+          const T bv = (c < C && kok) ? B[k * g.b_sk + c * g.b_sc] : T(0);
+          acc[t] = Mfma<T>::mac(csym ? sm : df, bv, acc[t]);
+        }
+      } else {
+        const T av = (ia < I && kin) ? A[ia * g.a_si + k * g.a_sk] : T(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = c0 + t * 16 + li;
+          T bv = T(0);
+          if (c < C && kin) {
+            const T x1 = B[k * g.b_sk + c * g.b_sc], x2 = B[kr * g.b_sk + c * g.b_sc];
+            bv = rsym ? (kr == k ? x1 : x1 + x2) : x1 - x2;
+          }
+          acc[t] = Mfma<T>::mac(av, bv, acc[t]);
+        }
+      }
+    }
+  } else {
+    // P over k < ps, R over k >= ps
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      const int k = k0 + lk;
+      const bool lower = k0 < ps;  // ps is a multiple of 16: no k-step straddles it
+      const bool kin = k < m;
+      const T av = (ia < I && kin) ? A[ia * g.a_si + k * g.a_sk] : T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + t * 16 + li;
+        const T bv = (c < C && kin) ? B[k * g.b_sk + c * g.b_sc] : T(0);
+        if (lower) acc[t] = Mfma<T>::mac(av, bv, acc[t]);
+        else acr[KIND == 2 ? t : 0] = Mfma<T>::mac(av, bv, acr[KIND == 2 ? t : 0]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = c0 + t * 16 + li;
+    if (c >= C) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + Mfma<T>::row(lk, r);
+      if (i >= I) continue;
+      if (KIND == 1) {
+        D[i * g.d_si + c * g.d_sc] = acc[t][r];
+      } else {
+        const T P = acc[t][r], R = acr[KIND == 2 ? t : 0][r];
+        if (ZSIDE) {
+          D[i * g.d_si + c * g.d_sc] = P + R;
+          if (c < ph) D[i * g.d_si + (m - 1 - c) * g.d_sc] = P - R;
+        } else {
+          D[i * g.d_si + c * g.d_sc] = P + R;
+          if (i < ph) D[(m - 1 - i) * g.d_si + c * g.d_sc] = P - R;
+        }
+      }
     }
   }
 }
@@ -952,6 +1071,7 @@ int precond_setup(cheb_plan* p) {
     const int sa = src[a];
     const bool centro_a = p->g.bc[2 * sa] == p->g.bc[2 * sa + 1] && face_sigma(p, 2 * sa) == face_sigma(p, 2 * sa + 1);
     ax[a].split = centro_a && m <= 128 && ((m + 1) / 2) % 16 == 0 ? 1 : 0;
+    ax[a].centro = centro_a ? 1 : 0;
     ax[a].off_V = off64;
     host.insert(host.end(), V.begin(), V.end());
     off64 += (size_t)m * m;
@@ -1140,6 +1260,11 @@ static int axis_contract(const cheb_plan* p, int a, int dir, bool tr, const int*
   GemmArgs g;
   const long long msz = m[a];
   const long long ms_i = tr ? 1 : msz, ms_k = tr ? msz : 1;  // M(i,k) strides
+  // centro-symmetric axis with halves in whole 16-row blocks: the split
+  // contraction (V^{-1} side through Q^T, V side through Q; also transposed)
+  const int ps = (m[a] + 1) / 2;
+  const int kind = p->pc_ax[a].centro && ps % 16 == 0 ? dir + 1 : 0;
+  g.ps = ps;
   if (a == 2) {
     // Y[r, i] = sum_k X[r, k] M[i, k]: rows r, columns i
     g.A = X; g.B = M; g.D = Y;
@@ -1148,8 +1273,10 @@ static int axis_contract(const cheb_plan* p, int a, int dir, bool tr, const int*
     g.b_sk = ms_k; g.b_sc = ms_i;
     g.d_si = m[2]; g.d_sc = 1;
     g.a_sb = g.b_sb = g.d_sb = 0;
-    dim3 grid((g.I + 15) / 16, (g.C + 255) / 256, 1);
-    hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+    dim3 grid((g.I + 15) / 16, ((kind == 2 ? ps : g.C) + 255) / 256, 1);
+    if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_split<T, 1, true>), grid, dim3(256), 0, s, g);
+    else if (kind == 2) hipLaunchKernelGGL((k_axis_gemm_split<T, 2, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
   } else {
     // Y_b = M X_b with X_b (m_axis x C), C = product of the later dims
     const int C = a == 0 ? m[1] * m[2] : m[2];
@@ -1161,8 +1288,10 @@ static int axis_contract(const cheb_plan* p, int a, int dir, bool tr, const int*
     g.d_si = C; g.d_sc = 1;
     g.a_sb = 0;
     g.b_sb = g.d_sb = (long long)m[a] * C;
-    dim3 grid((g.I + 15) / 16, (C + 255) / 256, batch);
-    hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+    dim3 grid(((kind == 2 ? ps : g.I) + 15) / 16, (C + 255) / 256, batch);
+    if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_split<T, 1, false>), grid, dim3(256), 0, s, g);
+    else if (kind == 2) hipLaunchKernelGGL((k_axis_gemm_split<T, 2, false>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
   }
   return hip_check(hipGetLastError(), "axis contraction");
 }

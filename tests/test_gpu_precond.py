@@ -125,6 +125,7 @@ def test_precond_exact_for_constant_K_shapes(shape, bcname, prec):
     ((34, 66, 98), None),                          # interior sizes 32, 64, 96
     ((130, 97, 129), None),                        # 128, 95, 127
     ((66, 130, 34), (0.0, 0.0, 0.7, 0.7, 0.0, 0.0)),  # Robin pair of equal sigma on the y faces
+    ((258, 20, 257), None),                        # 256 and 255 on the generic path's split
 ])
 def test_precond_exact_even_split_widths(shape, robin):
     """Same face type at both ends of every axis, so every axis takes the
@@ -152,8 +153,13 @@ def test_precond_exact_even_split_widths(shape, robin):
         log(f"  forward {info}")
         assert info["status"] == 0 and info["matvecs"] <= 4
         if prec == "f64":
+            # the transposed operator's rounding floors the adjoint's relative
+            # residual at 1.2e-11 when x has 258 nodes (measured the same with
+            # and without the even-odd split of the m > 128 contractions), so
+            # that grid's adjoint is held to 1e-10
+            artol = 1e-10 if shape[0] > 200 else 1e-11
             r = W.random_field(shape, 83)
-            _, _, ainfo = plan.adjoint(d(K), u, d(r), SolveOptions(rtol=1e-11, precond=True))
+            _, _, ainfo = plan.adjoint(d(K), u, d(r), SolveOptions(rtol=artol, maxiter=50, precond=True))
             log(f"  adjoint {ainfo}")
             assert ainfo["status"] == 0 and ainfo["matvecs"] <= 4
 
@@ -164,6 +170,12 @@ def test_precond_exact_even_split_widths(shape, robin):
     ((97, 20, 129), (1, 0, 1, 1, 0, 1), None),            # faces not mirror-symmetric: plain 96, 32, 128
     ((129, 129, 129), (0,) * 6, None),                    # the 129^3 workload's grid: split width 128
     ((17, 20, 257), (0,) * 6, None),                      # z interior 255: the generic contraction path
+    # the generic path's even-odd split (m > 128, ceil(m/2) a multiple of 16)
+    # on the x and y sides too, odd and even m, and with a Robin pair
+    ((257, 17, 20), (0,) * 6, None),                      # x interior 255 (a middle node)
+    ((20, 258, 17), (0, 0, 1, 1, 0, 0), None),            # y interior 256 (no middle node)
+    ((17, 20, 226), (0, 0, 0, 0, 1, 1), None),            # z interior 224, halves of 112
+    ((20, 17, 257), (0, 0, 0, 0, 1, 1), (0.0, 0.0, 0.0, 0.0, 0.7, 0.7)),  # z 255, Robin pair
     ((66, 130, 34), (0, 0, 1, 1, 0, 0), (0.0, 0.0, 0.7, 0.7, 0.0, 0.0)),  # Robin pair, even widths
     # y and z axes with one 1-D problem (cubic y-z box), which share their
     # fragment tables
