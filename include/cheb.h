@@ -198,7 +198,8 @@ int cheb_plan_set_route(cheb_plan* plan, int32_t route);
  * plans).  report (host, may be NULL when report_len is 0) receives up to 4
  * values: microseconds per apply for [FFT route, matrix tile shape 0, matrix
  * tile shape 1] (-1 where not applicable) and the index chosen.  Synchronises
- * the plan's stream.  Without this call AUTO uses fixed tile shapes. */
+ * the plan's stream.  Without this call AUTO uses tile shape 1 (the faster one
+ * at every N measured, both precisions). */
 int cheb_plan_autotune(cheb_plan* plan, int32_t field_precision, const void* K, const void* u, void* y,
                        double* report, int32_t report_len);
 
