@@ -520,6 +520,119 @@ __global__ __launch_bounds__(256) void k_axis_gemm_split(GemmArgs g) {
   }
 }
 
+// The same contractions (KIND 0 plain, 1 and 2 the even-odd split as above)
+// with the operands staged through LDS: a workgroup of four waves computes a
+// 64 x 64 output tile (each wave 32 x 32, 2 x 2 matrix-core blocks) over
+// k-chunks of 16, so every loaded element feeds several matrix instructions.
+// The split forms its pair sums and differences while staging; it needs ps a
+// multiple of 64 so that a tile's rows (ZSIDE: columns) are all symmetric or
+// all antisymmetric modes.
+constexpr int kGt = 64, kGk = 16;  // output tile edge, k-chunk
+template <typename T, int KIND, bool ZSIDE>
+__global__ __launch_bounds__(256) void k_axis_gemm_lds(GemmArgs g) {
+  typedef typename Mfma<T>::v4 v4;
+  __shared__ T As[kGt][kGk + 1];
+  __shared__ T Bs[kGk][kGt + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = blockIdx.x * kGt, c0 = blockIdx.y * kGt, b = blockIdx.z;
+  const T* A = (const T*)g.A + b * g.a_sb;
+  const T* B = (const T*)g.B + b * g.b_sb;
+  T* D = (T*)g.D + b * g.d_sb;
+  const int m = g.Kd, ps = g.ps, ph = m - g.ps;
+  // output extent: rows (ZSIDE: columns) below ps for KIND 2
+  const int I = (!ZSIDE && KIND == 2) ? ps : g.I;
+  const int C = (ZSIDE && KIND == 2) ? ps : g.C;
+  // KIND 1: the tile's modes are symmetric below ps; their k range
+  const bool tsym = ZSIDE ? c0 < ps : i0 < ps;
+  const int kend = KIND == 1 ? (tsym ? ps : ph) : m;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4 acc[2][2], acr[KIND == 2 ? 2 : 1][KIND == 2 ? 2 : 1];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      acc[x][y] = v4{0, 0, 0, 0};
+      if (KIND == 2) acr[KIND == 2 ? x : 0][KIND == 2 ? y : 0] = v4{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < kend; k0 += kGk) {
+    // stage A (64 rows x 16 k) and B (16 k x 64 columns), zero outside
+#pragma unroll
+    for (int q = 0; q < kGt * kGk / 256; ++q) {
+      const int e = tid + q * 256;
+      const int r = e / kGk, kk = e - r * kGk;
+      const int i = i0 + r, k = k0 + kk;
+      T v = T(0);
+      if (i < I && k < kend) {
+        v = A[i * g.a_si + k * g.a_sk];
+        if (KIND == 1 && ZSIDE) {
+          const int kr = m - 1 - k;
+          const T x2 = A[i * g.a_si + kr * g.a_sk];
+          v = tsym ? (kr == k ? v : v + x2) : v - x2;
+        }
+      }
+      As[r][kk] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < kGt * kGk / 256; ++q) {
+      const int e = tid + q * 256;
+      const int kk = e / kGt, cc = e - kk * kGt;
+      const int k = k0 + kk, c = c0 + cc;
+      T v = T(0);
+      if (c < C && k < kend) {
+        v = B[k * g.b_sk + c * g.b_sc];
+        if (KIND == 1 && !ZSIDE) {
+          const int kr = m - 1 - k;
+          const T x2 = B[kr * g.b_sk + c * g.b_sc];
+          v = tsym ? (kr == k ? v : v + x2) : v - x2;
+        }
+      }
+      Bs[kk][cc] = v;
+    }
+    __syncthreads();
+    const bool upper = KIND == 2 && k0 >= ps;  // ps is a multiple of 16: chunks do not straddle it
+#pragma unroll
+    for (int ks = 0; ks < kGk / 4; ++ks) {
+      T av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = As[wr + x * 16 + li][ks * 4 + lk];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[ks * 4 + lk][wc + y * 16 + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          if (upper) acr[KIND == 2 ? x : 0][KIND == 2 ? y : 0] =
+              Mfma<T>::mac(av[x], bv[y], acr[KIND == 2 ? x : 0][KIND == 2 ? y : 0]);
+          else acc[x][y] = Mfma<T>::mac(av[x], bv[y], acc[x][y]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int c = c0 + wc + y * 16 + li;
+      if (c >= C) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + x * 16 + Mfma<T>::row(lk, r);
+        if (i >= I) continue;
+        if (KIND != 2) {
+          D[i * g.d_si + c * g.d_sc] = acc[x][y][r];
+        } else {
+          const T P = acc[x][y][r], R = acr[KIND == 2 ? x : 0][KIND == 2 ? y : 0][r];
+          D[i * g.d_si + c * g.d_sc] = P + R;
+          if (ZSIDE ? c < ph : i < ph) {
+            if (ZSIDE) D[i * g.d_si + (m - 1 - c) * g.d_sc] = P - R;
+            else D[(m - 1 - i) * g.d_si + c * g.d_sc] = P - R;
+          }
+        }
+      }
+    }
+}
+
 // Contraction of packed blocks along one axis with a dense m x m matrix,
 // y_i = sum_k M[i][k] x_k per pencil (M^T with trans), for m <= MP <= 128, on
 // the matrix cores (MFMA 16x16x4).  One wave owns a task of 16 pencils and
@@ -1273,10 +1386,16 @@ static int axis_contract(const cheb_plan* p, int a, int dir, bool tr, const int*
     g.b_sk = ms_k; g.b_sc = ms_i;
     g.d_si = m[2]; g.d_sc = 1;
     g.a_sb = g.b_sb = g.d_sb = 0;
-    dim3 grid((g.I + 15) / 16, ((kind == 2 ? ps : g.C) + 255) / 256, 1);
-    if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_split<T, 1, true>), grid, dim3(256), 0, s, g);
-    else if (kind == 2) hipLaunchKernelGGL((k_axis_gemm_split<T, 2, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+    if (kind == 0 || ps % kGt == 0) {
+      dim3 grid((g.I + kGt - 1) / kGt, ((kind == 2 ? ps : g.C) + kGt - 1) / kGt, 1);
+      if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_lds<T, 1, true>), grid, dim3(256), 0, s, g);
+      else if (kind == 2) hipLaunchKernelGGL((k_axis_gemm_lds<T, 2, true>), grid, dim3(256), 0, s, g);
+      else hipLaunchKernelGGL((k_axis_gemm_lds<T, 0, true>), grid, dim3(256), 0, s, g);
+    } else {
+      dim3 grid((g.I + 15) / 16, ((kind == 2 ? ps : g.C) + 255) / 256, 1);
+      if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_split<T, 1, true>), grid, dim3(256), 0, s, g);
+      else hipLaunchKernelGGL((k_axis_gemm_split<T, 2, true>), grid, dim3(256), 0, s, g);
+    }
   } else {
     // Y_b = M X_b with X_b (m_axis x C), C = product of the later dims
     const int C = a == 0 ? m[1] * m[2] : m[2];
@@ -1288,10 +1407,16 @@ static int axis_contract(const cheb_plan* p, int a, int dir, bool tr, const int*
     g.d_si = C; g.d_sc = 1;
     g.a_sb = 0;
     g.b_sb = g.d_sb = (long long)m[a] * C;
-    dim3 grid(((kind == 2 ? ps : g.I) + 15) / 16, (C + 255) / 256, batch);
-    if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_split<T, 1, false>), grid, dim3(256), 0, s, g);
-    else if (kind == 2) hipLaunchKernelGGL((k_axis_gemm_split<T, 2, false>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(256), 0, s, g);
+    if (kind == 0 || ps % kGt == 0) {
+      dim3 grid(((kind == 2 ? ps : g.I) + kGt - 1) / kGt, (C + kGt - 1) / kGt, batch);
+      if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_lds<T, 1, false>), grid, dim3(256), 0, s, g);
+      else if (kind == 2) hipLaunchKernelGGL((k_axis_gemm_lds<T, 2, false>), grid, dim3(256), 0, s, g);
+      else hipLaunchKernelGGL((k_axis_gemm_lds<T, 0, false>), grid, dim3(256), 0, s, g);
+    } else {
+      dim3 grid(((kind == 2 ? ps : g.I) + 15) / 16, (C + 255) / 256, batch);
+      if (kind == 1) hipLaunchKernelGGL((k_axis_gemm_split<T, 1, false>), grid, dim3(256), 0, s, g);
+      else hipLaunchKernelGGL((k_axis_gemm_split<T, 2, false>), grid, dim3(256), 0, s, g);
+    }
   }
   return hip_check(hipGetLastError(), "axis contraction");
 }

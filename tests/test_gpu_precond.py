@@ -176,6 +176,10 @@ def test_precond_exact_even_split_widths(shape, robin):
     ((20, 258, 17), (0, 0, 1, 1, 0, 0), None),            # y interior 256 (no middle node)
     ((17, 20, 226), (0, 0, 0, 0, 1, 1), None),            # z interior 224, halves of 112
     ((20, 17, 257), (0, 0, 0, 0, 1, 1), (0.0, 0.0, 0.0, 0.0, 0.7, 0.7)),  # z 255, Robin pair
+    # faces that differ at the two ends of a long axis: the plain (unsplit)
+    # contraction past 128 interior nodes, z side and x side
+    ((20, 17, 200), (0, 0, 0, 0, 0, 1), None),            # z interior 198, Dirichlet-Neumann
+    ((200, 17, 20), (1, 0, 0, 0, 0, 0), None),            # x interior 198, Neumann-Dirichlet
     ((66, 130, 34), (0, 0, 1, 1, 0, 0), (0.0, 0.0, 0.7, 0.7, 0.0, 0.0)),  # Robin pair, even widths
     # y and z axes with one 1-D problem (cubic y-z box), which share their
     # fragment tables
