@@ -53,13 +53,17 @@ static int dispatch_pass(const PassArgs<T>& a, int mode, hipStream_t s) {
   switch (a.N) {
     case 4: return launch_pass_mode<T, 4>(a, mode, s);
     case 8: return launch_pass_mode<T, 8>(a, mode, s);
+    case 12: return launch_pass_mode<T, 12>(a, mode, s);
     case 16: return launch_pass_mode<T, 16>(a, mode, s);
+    case 24: return launch_pass_mode<T, 24>(a, mode, s);
     case 32: return launch_pass_mode<T, 32>(a, mode, s);
     case 48: return launch_pass_mode<T, 48>(a, mode, s);
     case 64: return launch_pass_mode<T, 64>(a, mode, s);
     case 96: return launch_pass_mode<T, 96>(a, mode, s);
     case 128: return launch_pass_mode<T, 128>(a, mode, s);
+    case 192: return launch_pass_mode<T, 192>(a, mode, s);
     case 256: return launch_pass_mode<T, 256>(a, mode, s);
+    case 384: return launch_pass_mode<T, 384>(a, mode, s);
     case 512: return launch_pass_mode<T, 512>(a, mode, s);
     default: return launch_pass_mode<T, 0>(a, mode, s);
   }

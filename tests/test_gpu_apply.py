@@ -17,7 +17,9 @@ F64_TOL = 1e-12
 F32_TOL = 1e-5
 
 SIZES = [(5, 5, 5), (9, 9, 9), (17, 17, 17), (24, 24, 24), (33, 33, 33), (49, 49, 49),
-         (65, 65, 65), (97, 97, 97), (17, 33, 9), (13, 6, 65)]
+         (65, 65, 65), (97, 97, 97), (17, 33, 9), (13, 6, 65),
+         # the FFT route's other transform sizes: N = 24, 192 and 384
+         (25, 9, 7), (193, 9, 9), (9, 193, 7), (6, 5, 385)]
 
 
 def _case(n, bc, seed, lo=(0.0, -1.0, 0.5), hi=(1.0, 1.0, 2.0)):
