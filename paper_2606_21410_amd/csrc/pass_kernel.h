@@ -387,10 +387,11 @@ __global__ __launch_bounds__(pass_threads(NC)) void k_axis_pass(PassArgs<T> a) {
   constexpr bool NEEDK = (MODE != MODE_DERIV && MODE != MODE_DERIV_T && MODE != MODE_DERIV_ACC);
   constexpr bool ACC = (MODE == MODE_FULL || MODE == MODE_REDUCED || MODE == MODE_TRANSPOSE ||
                         MODE == MODE_DERIV_ACC);
-  // K held in registers through the first derivative: up to 18 elements per
-  // thread in FP64 (N = 192, 256: the apply 2.7% and 4.5% faster), 12 in FP32
-  // (at N = 256 the prefetch slowed the FP32 apply by a quarter)
-  constexpr bool PRE_K = ONE && NEEDK && CHK <= (sizeof(T) == 8 ? 18 : 12);
+  // K held in registers through the first derivative: up to 12 elements per
+  // thread, and up to 18 for FP64 at N >= 192 (N = 192, 256: the apply 2.7% and
+  // 4.5% faster; at N = 128 the registers cost occupancy and the FP64 apply
+  // slowed by a third, at N = 256 in FP32 by a quarter)
+  constexpr bool PRE_K = ONE && NEEDK && CHK <= ((sizeof(T) == 8 && NC >= 192) ? 18 : 12);
   constexpr bool PRE_Y = ONE && ACC && CHK <= 12;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = NC > 0 ? NC : a.N;
